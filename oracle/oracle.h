@@ -1,0 +1,108 @@
+/*
+ * Oracle for Fast and Robust ICP (Zhang, Yao, Deng, arXiv 2007.07627).
+ *
+ * TEST INFRASTRUCTURE ONLY. This is a plain, slow, FP64 CPU implementation of
+ * what the GPU path computes. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it. It shares no code, header, table
+ * or helper with the GPU library; the GPU library never includes or links it.
+ *
+ * Conventions
+ *   - Point sets are host AoS, row-major n x 3, float32.
+ *   - A rigid transform T is FP64 row-major 4x4 [R t; 0 0 0 1].
+ *   - An se(3) parameter vector xi is FP64 [delta_1..3, u_1..3] (Sec. 4.2,
+ *     eq. Matrixsed: S = delta^, translation part u).
+ */
+#ifndef ICP_ORACLE_H
+#define ICP_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_P2P_L2 = 0, ORC_P2P_WELSCH = 1, ORC_P2PL_WELSCH = 2 };
+
+enum {
+  ORC_FLAG_CONVERGED = 1u,
+  ORC_FLAG_MAX_ITER = 2u,
+  ORC_FLAG_ZERO_WEIGHT = 4u,
+  ORC_FLAG_DEGENERATE = 8u,
+  ORC_FLAG_AA_SINGULAR = 16u
+};
+
+typedef struct {
+  int mode;              /* ORC_P2P_L2 / ORC_P2P_WELSCH / ORC_P2PL_WELSCH */
+  int anderson_m;        /* Anderson depth m; 0 = plain MM iteration */
+  double nu_max;         /* <= 0: 3 x median rule at T0 */
+  double nu_min;         /* must be > 0 for the Welsch modes */
+  double eps;            /* per-stage convergence threshold */
+  int iter_first;        /* I_nu for the first stage */
+  int iter_inc;          /* I_nu increment per stage */
+  int iter_cap;          /* I_nu upper bound */
+  int max_total_iter;    /* <= 0: unlimited */
+  int max_line_search;   /* l_max of the point-to-plane line search */
+  double T0[16];
+} orc_params;
+
+typedef struct {
+  double T[16];
+  double energy;         /* E_nu (or sum of squares for L2) at the returned T */
+  double nu_final;
+  int iterations;        /* inner-loop iterations over all stages */
+  int nn_passes;         /* correspondence computations at a new transform */
+  int evaluations;       /* passes incl. re-weighting at an unchanged transform */
+  int aa_accepted, aa_rejected, line_search_trials, stages;
+  unsigned flags;
+} orc_result;
+
+/* Eq. CorresponcePoint with the transform rounded once to FP32 (see .c). */
+void orc_transform_f32(const double T[16], const float *P, int64_t M, float *out);
+void orc_nn_brute(const float *Pt, int64_t M, const float *Q, int64_t N,
+                  int32_t *idx, float *d2);
+void orc_nn_query(const float *P, int64_t M, const float *Q, int64_t N,
+                  const double T[16], int32_t *idx, float *d2);
+
+/* se(3) exponential and logarithm (eq. MatrixExp, Appendix A). */
+void orc_se3_exp(const double xi[6], double T[16]);
+void orc_se3_log(const double T[16], double xi[6]);
+
+/* 3x3 SVD A = U diag(S) V^T, S descending; returns 0. */
+int orc_svd3(const double A[9], double U[9], double S[3], double V[9]);
+
+/* Weighted rigid Procrustes (eq. WelschAlignment). P, Qh: M x 3 float;
+ * w: M weights or NULL for all ones. Returns flags (ZERO_WEIGHT/DEGENERATE). */
+unsigned orc_procrustes(const float *P, const float *Qh, const double *w,
+                        int64_t M, double T[16]);
+
+/* Signed point-to-plane distance B_i(xi) and its gradient (Appendix D). */
+double orc_plane_residual(const double xi[6], const float p[3], const float q[3],
+                          const float n[3]);
+void orc_plane_gradient(const double xi[6], const float p[3], const float n[3],
+                        double J[6]);
+
+/* Anderson least squares (Sec. 4.1). dF: m x 6 rows (F^{k-j+1}-F^{k-j}),
+ * Fk: 6, metric 0 = Frobenius on the 4x4 log (rotation part weighted 2),
+ * 1 = Euclidean. theta: m. Returns 1 if the system was singular (theta=0). */
+int orc_anderson_solve(const double *dF, const double *Fk, int m, int metric,
+                       double *theta);
+
+/* Element of rank floor(n/2) in ascending order (copy is sorted). */
+double orc_median(const double *v, int64_t n);
+
+/* Full registration: Fast ICP (L2 + AA), Algorithm 1, Algorithm 2.
+ * Qn may be NULL except for ORC_P2PL_WELSCH. trace (optional) receives the
+ * 16 entries of every transform at which correspondences were computed, up
+ * to trace_cap transforms; etrace (optional) receives (stage, accepted energy)
+ * for every inner iteration, up to etrace_cap pairs.
+ * Returns 0 on success, -1 on invalid arguments. */
+int orc_register(const float *P, int64_t M, const float *Q, const float *Qn,
+                 int64_t N, const orc_params *prm, orc_result *res,
+                 double *trace, int trace_cap, int *trace_len,
+                 double *etrace, int etrace_cap, int *etrace_len);
+
+void orc_params_default(int mode, orc_params *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,442 @@
+"""Pins of the CPU oracle against things other than itself: exact rational
+arithmetic, library routines (scipy expm/logm, numpy SVD/lstsq/sort), closed
+forms (Horn's quaternion Procrustes), finite differences and the paper's
+invariants (MM monotone decrease, exact recovery)."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_2007_07627_amd import metrics, synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- helpers
+
+def _fma_exact(a, b, c):
+    """Correctly rounded FP64 fma via exact rationals."""
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def _hat(a):
+    return np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0.0]])
+
+
+def _twist_matrix(xi):
+    X = np.zeros((4, 4))
+    X[:3, :3] = _hat(xi[:3])
+    X[:3, 3] = xi[3:]
+    return X
+
+
+def _rand_rot(rng, max_angle=math.pi):
+    R, _ = synth.random_motion(rng, math.degrees(max_angle), 0.0)
+    return R
+
+
+def _horn(P, Q, w):
+    """Horn's closed-form quaternion solution of weighted absolute orientation
+    (a different algorithm from the SVD route)."""
+    w = np.asarray(w, np.float64)
+    P = np.asarray(P, np.float64)
+    Q = np.asarray(Q, np.float64)
+    W = w.sum()
+    pb = (w[:, None] * P).sum(0) / W
+    qb = (w[:, None] * Q).sum(0) / W
+    S = ((P - pb) * w[:, None]).T @ (Q - qb)
+    Sxx, Sxy, Sxz = S[0]
+    Syx, Syy, Syz = S[1]
+    Szx, Szy, Szz = S[2]
+    N = np.array([[Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx],
+                  [Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz],
+                  [Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy],
+                  [Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz]])
+    ev, V = np.linalg.eigh(N)
+    q0, qx, qy, qz = V[:, -1]
+    R = np.array([[q0 * q0 + qx * qx - qy * qy - qz * qz, 2 * (qx * qy - q0 * qz), 2 * (qx * qz + q0 * qy)],
+                  [2 * (qy * qx + q0 * qz), q0 * q0 - qx * qx + qy * qy - qz * qz, 2 * (qy * qz - q0 * qx)],
+                  [2 * (qz * qx - q0 * qy), 2 * (qz * qy + q0 * qx), q0 * q0 - qx * qx - qy * qy + qz * qz]])
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = qb - R @ pb
+    return T
+
+
+# ---------------------------------------------------------------- transform (O1)
+
+def test_transform_matches_exact_rational_fma_chain():
+    rng = np.random.default_rng(1)
+    R = _rand_rot(rng)
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = rng.normal(size=3)
+    P = rng.normal(size=(200, 3)).astype(np.float32)
+    got = oracle.transform_f32(T, P)
+    for i in range(P.shape[0]):
+        for a in range(3):
+            x = _fma_exact(T[a, 2], float(P[i, 2]),
+                           _fma_exact(T[a, 1], float(P[i, 1]), _fma_exact(T[a, 0], float(P[i, 0]), T[a, 3])))
+            assert np.float32(x) == got[i, a]
+
+
+def test_transform_identity_is_exact():
+    P = np.random.default_rng(2).normal(size=(100, 3)).astype(np.float32)
+    assert np.array_equal(oracle.transform_f32(np.eye(4), P), P)
+
+
+# ---------------------------------------------------------------- NN (O2)
+
+def _exact_argmin(p, Q):
+    best, bi, second = None, -1, None
+    for j, q in enumerate(Q):
+        d = sum((Fraction(float(p[a])) - Fraction(float(q[a]))) ** 2 for a in range(3))
+        if best is None or d < best:
+            second = best
+            best, bi = d, j
+        elif second is None or d < second:
+            second = d
+    return bi, best, second
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_nn_matches_exact_rational_argmin(seed):
+    rng = np.random.default_rng(seed)
+    Q = rng.uniform(-1, 1, size=(48, 3)).astype(np.float32)
+    P = rng.uniform(-1.2, 1.2, size=(40, 3)).astype(np.float32)
+    idx, d2 = oracle.nn_brute(P, Q)
+    checked = 0
+    for i in range(P.shape[0]):
+        bi, best, second = _exact_argmin(P[i], Q)
+        # the FP32 distance is within a few ulps of the exact one
+        assert abs(float(d2[i]) - float(best)) <= 8 * 2.0 ** -24 * float(best) + 1e-45
+        if second is not None and second > best * Fraction(1000001, 1000000):
+            assert idx[i] == bi
+            checked += 1
+    assert checked >= 35
+
+
+def test_nn_ties_and_duplicates_lowest_index():
+    Q = np.array([[1, 0, 0], [0, 1, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0]], np.float32)
+    P = np.array([[0, 0, 0], [0.9, 0, 0], [0, 2, 0], [0.5, 0.5, 0]], np.float32)
+    idx, d2 = oracle.nn_brute(P, Q)
+    # origin: equidistant to all four distinct points -> index 0
+    assert idx.tolist() == [0, 0, 1, 0]
+    assert d2[0] == 1.0 and d2[2] == 1.0
+
+
+def test_nn_single_target_and_far_points():
+    Q = np.array([[3, -2, 1]], np.float32)
+    P = np.random.default_rng(4).normal(scale=100, size=(17, 3)).astype(np.float32)
+    idx, _ = oracle.nn_brute(P, Q)
+    assert (idx == 0).all()
+
+
+def test_nn_query_applies_transform():
+    rng = np.random.default_rng(5)
+    Q = rng.normal(size=(300, 3)).astype(np.float32)
+    T = np.eye(4)
+    T[:3, :3] = _rand_rot(rng)
+    T[:3, 3] = [0.3, -0.1, 0.2]
+    P = rng.normal(size=(50, 3)).astype(np.float32)
+    i1, d1 = oracle.nn_query(P, Q, T)
+    i2, d2 = oracle.nn_brute(oracle.transform_f32(T, P), Q)
+    assert np.array_equal(i1, i2) and np.array_equal(d1, d2)
+
+
+# ---------------------------------------------------------------- exp / log (O5)
+
+def test_exp_matches_scipy_expm():
+    rng = np.random.default_rng(6)
+    for scale in [0.0, 1e-9, 1e-5, 1e-3, 0.05, 0.3, 1.0, 2.5, 3.1]:
+        for _ in range(5):
+            d = rng.normal(size=3)
+            d = d / np.linalg.norm(d) * scale
+            xi = np.concatenate([d, rng.normal(size=3)])
+            ref = scipy.linalg.expm(_twist_matrix(xi))
+            assert np.abs(oracle.se3_exp(xi) - ref).max() < 1e-13
+
+
+def test_log_matches_scipy_logm_and_round_trips():
+    rng = np.random.default_rng(7)
+    for ang in [0.0, 1e-8, 1e-4, 0.01, 0.5, 1.5, 3.0, math.pi - 1e-4]:
+        for _ in range(4):
+            d = rng.normal(size=3)
+            d = d / np.linalg.norm(d) * ang
+            xi = np.concatenate([d, rng.normal(size=3)])
+            T = oracle.se3_exp(xi)
+            got = oracle.se3_log(T)
+            assert np.abs(got - xi).max() < 1e-8 if ang > 3 else np.abs(got - xi).max() < 1e-12
+            if 0.01 <= ang <= 3.0:
+                L = np.real(scipy.linalg.logm(T))
+                assert np.abs(_twist_matrix(got) - L).max() < 1e-10
+            assert np.abs(oracle.se3_exp(got) - T).max() < 1e-13
+
+
+def test_exp_log_golden_quarter_turn():
+    """Closed-form values of eq. MatrixExp for a quarter turn about z
+    (tests/golden/se3_quarter_turn.json)."""
+    with open(os.path.join(GOLDEN, "se3_quarter_turn.json")) as f:
+        g = json.load(f)
+    T = oracle.se3_exp(np.array(g["xi"]))
+    assert np.abs(T - np.array(g["T"])).max() < 1e-15
+    assert np.abs(oracle.se3_log(np.array(g["T"])) - np.array(g["xi"])).max() < 1e-14
+
+
+def test_appendix_d_translation_form_agrees_with_V_u():
+    """App. D writes t = ((R - I) u^ delta + delta delta^T u)/|delta|^2; it must
+    equal the translation of exp([delta^ u; 0 0])."""
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        xi = rng.normal(size=6)
+        xi[:3] *= rng.uniform(0.01, 2.5) / np.linalg.norm(xi[:3])
+        T = oracle.se3_exp(xi)
+        d, u = xi[:3], xi[3:]
+        R = T[:3, :3]
+        t = ((R - np.eye(3)) @ _hat(u) @ d + d * (d @ u)) / (d @ d)
+        assert np.abs(t - T[:3, 3]).max() < 1e-13
+
+
+# ---------------------------------------------------------------- SVD / Procrustes (O4)
+
+def test_svd3_against_numpy():
+    rng = np.random.default_rng(9)
+    mats = [rng.normal(size=(3, 3)) for _ in range(20)]
+    mats.append(np.outer(rng.normal(size=3), rng.normal(size=3)))  # rank 1
+    a, b = rng.normal(size=3), rng.normal(size=3)
+    mats.append(np.outer(a, rng.normal(size=3)) + np.outer(b, rng.normal(size=3)))  # rank 2
+    mats.append(np.zeros((3, 3)))
+    for A in mats:
+        U, S, V = oracle.svd3(A)
+        ref = np.linalg.svd(A, compute_uv=False)
+        assert np.abs(S - ref).max() <= 1e-13 * max(1.0, ref[0])
+        assert np.abs(U @ np.diag(S) @ V.T - A).max() <= 1e-13 * max(1.0, ref[0])
+        assert np.abs(U.T @ U - np.eye(3)).max() < 1e-12
+        assert np.abs(V.T @ V - np.eye(3)).max() < 1e-12
+
+
+def test_procrustes_matches_horn_weighted_and_unweighted():
+    rng = np.random.default_rng(10)
+    for trial in range(10):
+        P = rng.normal(size=(500, 3)).astype(np.float32)
+        R = _rand_rot(rng)
+        t = rng.normal(size=3)
+        Q = (P.astype(np.float64) @ R.T + t + rng.normal(scale=0.05, size=P.shape)).astype(np.float32)
+        w = rng.uniform(0.01, 1.0, size=500) if trial % 2 else np.ones(500)
+        T, flags = oracle.procrustes(P, Q, w)
+        assert flags == 0
+        Th = _horn(P, Q, w)
+        assert np.abs(T - Th).max() < 1e-12
+
+
+def test_procrustes_exact_recovery_and_reflection_free():
+    rng = np.random.default_rng(11)
+    P = rng.normal(size=(1000, 3)).astype(np.float32)
+    R = _rand_rot(rng)
+    t = np.array([0.5, -1.0, 2.0])
+    Q = (P.astype(np.float64) @ R.T + t).astype(np.float32)
+    T, _ = oracle.procrustes(P, Q)
+    assert metrics.rotation_error_rad(T, np.block([[R, t[:, None]], [np.zeros((1, 3)), 1]])) < 1e-6
+    assert np.abs(T[:3, 3] - t).max() < 1e-6
+    assert np.linalg.det(T[:3, :3]) > 0.999999
+    # uniform weights == no weights (textbook unweighted Kabsch)
+    T1, _ = oracle.procrustes(P, Q, np.full(1000, 0.37))
+    assert np.abs(T1 - T).max() < 1e-13
+
+
+def test_procrustes_degenerate_and_zero_weight_flags():
+    P = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [3, 0, 0]], np.float32)  # collinear
+    T, flags = oracle.procrustes(P, P)
+    assert flags & oracle.FLAG_DEGENERATE
+    _, flags = oracle.procrustes(P, P, np.zeros(4))
+    assert flags & oracle.FLAG_ZERO_WEIGHT
+
+
+# ---------------------------------------------------------------- point-to-plane gradient (O6)
+
+@pytest.mark.parametrize("ang", [0.0, 1e-7, 1e-4, 9e-4, 2e-3, 0.1, 1.0, 2.5])
+def test_plane_gradient_central_differences(ang):
+    rng = np.random.default_rng(int(ang * 1e7) % 1000 + 12)
+    for _ in range(5):
+        d = rng.normal(size=3)
+        d = d / np.linalg.norm(d) * ang
+        xi = np.concatenate([d, rng.normal(scale=0.3, size=3)])
+        p = rng.normal(size=3).astype(np.float32)
+        q = rng.normal(size=3).astype(np.float32)
+        n = rng.normal(size=3)
+        n = (n / np.linalg.norm(n)).astype(np.float32)
+        J = oracle.plane_gradient(xi, p, n)
+        h = 1e-6
+        Jfd = np.zeros(6)
+        for a in range(6):
+            e = np.zeros(6)
+            e[a] = h
+            Jfd[a] = (oracle.plane_residual(xi + e, p, q, n) - oracle.plane_residual(xi - e, p, q, n)) / (2 * h)
+        assert np.abs(J - Jfd).max() <= 1e-7 * max(1.0, np.abs(Jfd).max())
+
+
+def test_gauss_newton_fixed_point_noise_free():
+    """Noise-free point-to-plane with exact correspondences: the ground truth is
+    a fixed point and a nearby start converges to it (eq. GNSystem/GNMapping)."""
+    rng = synth.rng_for(3, 99)
+    d = synth.height_field_pair(rng, m=3000, n=3000, outliers=0.0, noise=0.0, max_angle=3.0,
+                                trans_frac=0.01)
+    # same surface samples are not shared; use the target itself as the source
+    Q, Qn = d["Q"], d["Qn"]
+    R, t = synth.random_motion(synth.rng_for(3, 98), 2.0, 0.01)
+    P = (Q.astype(np.float64) @ R.T + t).astype(np.float32)
+    Tgt = np.eye(4)
+    Tgt[:3, :3] = R.T
+    Tgt[:3, 3] = -R.T @ t
+    r = oracle.register(P, Q, Qn, mode=oracle.P2PL_WELSCH, anderson_m=6, nu_min=1e-2, nu_max=0.1)
+    assert metrics.rotation_error_rad(r["T"], Tgt) < 1e-6
+    assert metrics.translation_error(r["T"], Tgt) < 1e-6
+
+
+# ---------------------------------------------------------------- Anderson (O7)
+
+def test_anderson_solve_matches_lstsq_with_metric():
+    rng = np.random.default_rng(13)
+    for metric in (0, 1):
+        for m in range(1, 6):
+            dF = rng.normal(size=(m, 6))
+            Fk = rng.normal(size=6)
+            th, sing = oracle.anderson_solve(dF, Fk, metric)
+            wv = np.sqrt(np.array([2.0, 2.0, 2.0, 1, 1, 1]) if metric == 0 else np.ones(6))
+            ref = np.linalg.lstsq((dF * wv).T, Fk * wv, rcond=None)[0]
+            assert not sing
+            assert np.abs(th - ref).max() < 1e-9 * max(1.0, np.abs(ref).max())
+
+
+def test_anderson_singular_gives_zero():
+    dF = np.array([[1.0, 0, 0, 0, 0, 0], [2.0, 0, 0, 0, 0, 0]])
+    th, sing = oracle.anderson_solve(dF, np.ones(6), 1)
+    assert sing and (th == 0).all()
+
+
+def test_anderson_affine_fixed_point_in_few_steps():
+    """On an affine contraction in R^6, AA with m = 6 behaves like GMRES and
+    reaches the fixed point within n + 1 steps."""
+    rng = np.random.default_rng(14)
+    Q_, _ = np.linalg.qr(rng.normal(size=(6, 6)))
+    A = Q_ @ np.diag(rng.uniform(-0.9, 0.9, 6)) @ Q_.T
+    b = rng.normal(size=6)
+    xs = np.linalg.solve(np.eye(6) - A, b)
+    G = lambda x: A @ x + b
+    x = np.zeros(6)
+    Gs, Fs = [G(x)], [G(x) - x]
+    x = Gs[-1]
+    for k in range(1, 9):
+        g = G(x)
+        Gs.append(g)
+        Fs.append(g - x)
+        mk = min(k, 6)
+        dF = np.array([Fs[-j] - Fs[-j - 1] for j in range(1, mk + 1)])
+        dG = np.array([Gs[-j] - Gs[-j - 1] for j in range(1, mk + 1)])
+        th, _ = oracle.anderson_solve(dF, Fs[-1], 1)
+        x = Gs[-1] - th @ dG
+        if np.abs(x - xs).max() < 1e-11:
+            break
+    assert np.abs(x - xs).max() < 1e-11 and k <= 8
+
+
+# ---------------------------------------------------------------- median (R11)
+
+def test_median_rank_floor_half():
+    rng = np.random.default_rng(15)
+    for n in [1, 2, 3, 10, 11, 1000, 1001]:
+        v = rng.normal(size=n)
+        assert oracle.median(v) == np.sort(v)[n // 2]
+
+
+# ---------------------------------------------------------------- Welsch surrogate (eq. WelschSurrogate)
+
+def test_welsch_surrogate_majorizes():
+    nu = 0.7
+    psi = lambda x: 1 - np.exp(-x * x / (2 * nu * nu))
+    chi = lambda x, y: psi(y) + (x * x - y * y) / (2 * nu * nu) * np.exp(-y * y / (2 * nu * nu))
+    xs = np.linspace(0, 5, 501)
+    for y in np.linspace(0, 5, 51):
+        assert (chi(xs, y) >= psi(xs) - 1e-15).all()
+        assert abs(chi(y, y) - psi(y)) < 1e-15
+
+
+# ---------------------------------------------------------------- Algorithms (O8)
+
+def test_fast_icp_exact_recovery_noise_free():
+    d = synth.fast_icp_pair(synth.rng_for(1, 7), n=2000, noise=0.0)
+    r = oracle.register(d["P"], d["Q"], mode=oracle.P2P_L2, anderson_m=5, eps=1e-9,
+                        iter_first=200, iter_cap=200)
+    assert metrics.rotation_error_rad(r["T"], d["T_gt"]) < 1e-6
+    assert metrics.translation_error(r["T"], d["T_gt"]) < 1e-6 * d["diag"]
+
+
+def test_alg1_energy_monotone_within_stages():
+    d = synth.partial_sphere_pair(synth.rng_for(2, 3), m=3000, n=3000)
+    r = oracle.register(d["P"], d["Q"], mode=oracle.P2P_WELSCH, anderson_m=5, nu_min=d["nu_min"],
+                        etrace_cap=20000)
+    e = r["etrace"]
+    assert len(e) > 10
+    for i in range(1, len(e)):
+        if e[i, 0] == e[i - 1, 0]:
+            assert e[i, 1] <= e[i - 1, 1] * (1 + 1e-12)
+
+
+def test_plain_mm_energy_monotone_l2():
+    d = synth.fast_icp_pair(synth.rng_for(1, 8), n=2000)
+    r = oracle.register(d["P"], d["Q"], mode=oracle.P2P_L2, anderson_m=0, eps=1e-7,
+                        iter_first=300, iter_cap=300, etrace_cap=1000)
+    e = r["etrace"][:, 1]
+    assert (np.diff(e) <= 1e-12 * e[:-1]).all()
+
+
+def test_fast_icp_matches_plain_icp_with_fewer_passes():
+    """Fast ICP reaches the same solution as plain ICP (same RMSE, the
+    qualitative claim of Tables 1-4) and needs no more correspondence passes in
+    total over a set of seeds. With the same points on both sides the
+    correspondences settle, so both end on the identical transform."""
+    pa = pb = 0
+    for s in range(8):
+        d = synth.fast_icp_pair(synth.rng_for(1, 20 + s), n=1500)
+        a = oracle.register(d["P"], d["Q"], mode=0, anderson_m=5, eps=1e-8, iter_first=2000, iter_cap=2000)
+        b = oracle.register(d["P"], d["Q"], mode=0, anderson_m=0, eps=1e-8, iter_first=2000, iter_cap=2000)
+        assert metrics.rotation_error_rad(a["T"], b["T"]) < 1e-9
+        assert metrics.translation_error(a["T"], b["T"]) < 1e-9 * d["diag"]
+        pa += a["nn_passes"]
+        pb += b["nn_passes"]
+    assert pa <= pb
+
+
+def test_alg2_monotone_where_line_search_succeeds():
+    d = synth.height_field_pair(synth.rng_for(3, 1), m=2000, n=5000)
+    r = oracle.register(d["P"], d["Q"], d["Qn"], mode=oracle.P2PL_WELSCH, anderson_m=6,
+                        nu_min=d["nu_min"], etrace_cap=5000)
+    assert r["flags"] & (oracle.FLAG_CONVERGED | oracle.FLAG_MAX_ITER)
+    assert metrics.rmse(d["T_gt"], r["T"], d["P"]) < 2e-3
+
+
+def test_welsch_large_nu_reduces_to_l2():
+    """nu -> infinity makes every Welsch weight 1: the robust alignment equals
+    the L2 alignment (textbook special case)."""
+    d = synth.fast_icp_pair(synth.rng_for(1, 9), n=1000)
+    a = oracle.register(d["P"], d["Q"], mode=0, anderson_m=0, eps=1e-9, iter_first=5, iter_cap=5)
+    b = oracle.register(d["P"], d["Q"], mode=1, anderson_m=0, eps=1e-9, iter_first=5, iter_cap=5,
+                        nu_max=1e8, nu_min=1e8)
+    assert np.abs(a["T"] - b["T"]).max() < 1e-9
+
+
+def test_register_rejects_bad_arguments():
+    P = np.zeros((10, 3), np.float32)
+    with pytest.raises(ValueError):
+        oracle.register(P, P, mode=oracle.P2PL_WELSCH, nu_min=1e-3)  # no normals
+    with pytest.raises(ValueError):
+        oracle.register(P, P, mode=oracle.P2P_WELSCH)  # nu_min unset
+    T = np.eye(4)
+    T[0, 0] = 2
+    with pytest.raises(ValueError):
+        oracle.register(P, P, mode=0, T0=T)
