@@ -1,0 +1,197 @@
+/*
+ * libicp -- Fast and Robust Iterative Closest Point (Zhang, Yao, Deng,
+ * arXiv 2007.07627) on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI. Every call returns icp_status; nothing aborts or throws across the
+ * ABI. Plain pointers and sizes only. Unless a function says otherwise,
+ * pointers are HOST pointers; the *_dev functions take DEVICE pointers (HBM of
+ * the context's GPU) and an optional hipStream_t passed as void*.
+ *
+ * Problem (Sec. 3, eq. ICPOptimization; Sec. 4.3, eq. WelschRegistration;
+ * Sec. 5, eq. WelschPointToPlaneOptimization): find the rigid T = [R t; 0 1]
+ * that aligns the source P (M x 3) to the target Q (N x 3, optional unit
+ * normals Qn) under the L2, robust point-to-point or robust point-to-plane
+ * metric.
+ *
+ * Layouts: point sets are row-major n x 3 float32 (x, y, z per point).
+ * Transforms are float64 row-major 4 x 4, mapping source to target; they must
+ * be rigid: |R^T R - I| <= 1e-9 entrywise, det R > 0, last row (0, 0, 0, 1).
+ * Coordinates must be finite with magnitude <= 1e15.
+ *
+ * Threading: one icp_ctx may be used from several threads; calls are
+ * serialised internally per engine (synchronous calls vs. the batch engine).
+ */
+#ifndef ICP_H
+#define ICP_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct icp_ctx icp_ctx;
+
+typedef enum {
+  ICP_OK = 0,
+  ICP_ERR_INVALID_ARG = 1,   /* bad shape, pointer, parameter or transform */
+  ICP_ERR_NONFINITE = 2,     /* NaN / Inf (or |x| > 1e15) in an input coordinate */
+  ICP_ERR_NO_NORMALS = 3,    /* point-to-plane mode without target normals */
+  ICP_ERR_OOM = 4,           /* the request does not fit the context's HBM budget */
+  ICP_ERR_DEVICE = 5,        /* a HIP runtime call failed */
+  ICP_ERR_NOT_READY = 6,     /* icp_poll: the ticket is still queued or running */
+  ICP_ERR_UNKNOWN_TICKET = 7,/* icp_poll: never issued, or its result was already taken */
+  ICP_ERR_QUEUE_FULL = 8     /* icp_batch_submit: host queue limit reached */
+} icp_status;
+
+typedef enum {
+  ICP_P2P_L2 = 0,        /* Fast ICP: L2 point-to-point + Anderson (Sec. 4.2) */
+  ICP_P2P_WELSCH = 1,    /* Algorithm 1: Welsch point-to-point + Anderson (Sec. 4.3) */
+  ICP_P2PL_WELSCH = 2    /* Algorithm 2: Welsch point-to-plane + Anderson (Sec. 5) */
+} icp_mode;
+
+/* Closest-point search (eq. CorresponcePoint). All methods return the same
+ * bit-exact result: the FP32 transformed point p' = fl32(T p) (FP64 fused
+ * order), d2 = fma(dz,dz, fma(dy,dy, dx*dx)) with FP32 differences, minimum
+ * d2, ties to the lowest target index. BRUTE scans every target; CLUSTER
+ * prunes with a Morton-ordered cluster index (a uniform 1024^3 cell grid over
+ * the target's bounding box); AUTO picks by size. */
+typedef enum { ICP_NN_AUTO = 0, ICP_NN_BRUTE = 1, ICP_NN_CLUSTER = 2 } icp_nn_method;
+
+/* How icp_register drives the iterations: GRAPH keeps the per-pair state on
+ * the device and replays a captured hipGraph of several passes between host
+ * polls; PLAIN launches every pass and synchronises the host after each one
+ * (the one-pair-at-a-time comparator). Both give bit-identical results. */
+typedef enum { ICP_ENGINE_GRAPH = 0, ICP_ENGINE_PLAIN = 1 } icp_engine;
+
+typedef struct {
+  icp_mode mode;
+  int anderson_m;        /* Anderson depth m in [0, 6]; 0 disables mixing (plain MM); paper: 5 (Sec. 4.2) */
+  double nu_max;         /* <= 0: 3 x median of the initial residuals (Sec. 4.3, Sec. 5) */
+  double nu_min;         /* > 0, required for the Welsch modes (the paper's kNN rule is not built) */
+  double eps;            /* stage threshold on ||T - T'||_F (p2p) / ||xi* - xi|| (p2pl); paper 1e-5 */
+  int iter_first;        /* I_nu of the first stage; paper: 1000 (p2p), 6 (p2pl) */
+  int iter_inc;          /* I_nu increment per stage; paper: 0 (p2p), 1 (p2pl) */
+  int iter_cap;          /* I_nu upper bound; paper: 1000 (p2p), 10 (p2pl); <= 0 none */
+  int max_total_iter;    /* cap on inner iterations over all stages; <= 0 unlimited */
+  int max_line_search;   /* l_max of Algorithm 2 (unspecified in the paper): 10 */
+  icp_nn_method nn;
+  icp_engine engine;
+  double T0[16];         /* initial transform, default identity */
+} icp_params;
+
+enum {
+  ICP_FLAG_CONVERGED = 1u,      /* the last stage ended by the eps test */
+  ICP_FLAG_MAX_ITER = 2u,       /* the last stage ended by its iteration cap */
+  ICP_FLAG_ZERO_WEIGHT = 4u,    /* every Welsch weight underflowed: no update possible */
+  ICP_FLAG_DEGENERATE = 8u,     /* rank-deficient alignment / singular 6x6 system */
+  ICP_FLAG_AA_SINGULAR = 16u    /* an Anderson least-squares system was singular (theta = 0 used) */
+};
+
+typedef struct {
+  double T[16];          /* final transform (source -> target) */
+  double energy;         /* target energy at T for the final nu (sum d^2 for L2) */
+  double nu_final;
+  int iterations;        /* inner iterations over all stages */
+  int nn_passes;         /* closest-point passes at a new transform */
+  int evaluations;       /* passes including re-weighting at an unchanged transform */
+  int aa_accepted, aa_rejected, line_search_trials, stages;
+  unsigned status_flags; /* ICP_FLAG_* */
+  double latency_ms;     /* batch engine: submit -> done; synchronous calls: wall time */
+} icp_result;
+
+typedef struct {
+  const float *P;        /* M x 3 host source */
+  int64_t M;
+  const float *Q;        /* N x 3 host target */
+  const float *Qn;       /* N x 3 host normals or NULL */
+  int64_t N;
+  icp_params params;
+} icp_request;
+
+/* Context on HIP device `device` with an HBM arena of hbm_budget_bytes
+ * (0 = 8 GiB). Owns its streams, graphs and memory. */
+icp_status icp_create(int device, size_t hbm_budget_bytes, icp_ctx **out);
+icp_status icp_destroy(icp_ctx *ctx);
+
+/* The paper's defaults for a mode (Sec. 4.2, Sec. 4.3, Sec. 5). */
+icp_status icp_params_default(icp_mode mode, icp_params *out);
+
+/* Synchronous registration (Algorithm 1 / Algorithm 2 / Fast ICP). Inputs are
+ * copied before the call returns; `out` is written by the call. */
+icp_status icp_register(icp_ctx *ctx, const float *P, int64_t M, const float *Q, const float *Qn,
+                        int64_t N, const icp_params *params, icp_result *out);
+
+/* One application of the un-accelerated iteration map at transform T with
+ * Welsch parameter nu (ignored for ICP_P2P_L2): correspondences at T
+ * (eq. CorresponcePoint), the energy E_nu(T) (eq. WelschRegistration; sum of
+ * squared distances for L2; eq. WelschPointToPlaneOptimization for
+ * point-to-plane) into *energy_out, and the updated transform into T_out: the
+ * weighted Procrustes solution of eq. WelschAlignment (the map G_ICP of
+ * eq. FixedPointICP) for point-to-point, or exp of the Gauss-Newton candidate
+ * G_ppl(log T) of eq. GNMapping for point-to-plane. *flags_out receives
+ * ICP_FLAG_ZERO_WEIGHT / ICP_FLAG_DEGENERATE when no update exists (T_out is
+ * then T). Synchronous; host pointers. */
+icp_status icp_eval(icp_ctx *ctx, const float *P, int64_t M, const float *Q, const float *Qn,
+                    int64_t N, icp_mode mode, const double T[16], double nu,
+                    double *energy_out, double T_out[16], unsigned *flags_out);
+
+/* icp_register that also records one row of 20 doubles per pass into the
+ * caller's host array trace_out (capacity trace_cap rows): the pass's energy
+ * (sum of psi_nu, eq. welsch, or sum of squares for L2), its nu (0 for L2),
+ * the solver position that requested it, 1 if the closest-point search was
+ * reused at an unchanged transform, and the 16 entries of the evaluated
+ * transform. *trace_len receives the number of rows written (passes beyond
+ * the capacity are not recorded). For convergence plots (energy against
+ * iteration, Sec. 4.2) and for replaying the evaluated transforms. */
+icp_status icp_register_trace(icp_ctx *ctx, const float *P, int64_t M, const float *Q,
+                              const float *Qn, int64_t N, const icp_params *params,
+                              icp_result *out, double *trace_out, int trace_cap,
+                              int *trace_len);
+
+/* Same with device-resident AoS inputs (no host copy); `stream` is ordered
+ * before and after the work (NULL = the null stream). Synchronous. */
+icp_status icp_register_dev(icp_ctx *ctx, const float *P_dev, int64_t M, const float *Q_dev,
+                            const float *Qn_dev, int64_t N, const icp_params *params,
+                            icp_result *out, void *stream);
+
+/* Closest target point of every source point under T (eq. CorresponcePoint):
+ * idx_out[i] (int32, 0-based target index) and d2_out[i] (FP32 squared
+ * distance), both caller-allocated host arrays of M entries. M = 0 is a no-op;
+ * N = 0 is ICP_ERR_INVALID_ARG. Synchronous. */
+icp_status icp_nn_query(icp_ctx *ctx, const float *P, int64_t M, const float *Q, int64_t N,
+                        const double T[16], icp_nn_method method, int32_t *idx_out,
+                        float *d2_out);
+
+/* Same with device pointers for inputs and outputs. Synchronous. */
+icp_status icp_nn_query_dev(icp_ctx *ctx, const float *P_dev, int64_t M, const float *Q_dev,
+                            int64_t N, const double T[16], icp_nn_method method,
+                            int32_t *idx_out_dev, float *d2_out_dev, void *stream);
+
+/* Batched / served registration. Each request is validated and its arrays are
+ * copied to pinned staging before the call returns (the caller may free them
+ * at once); tickets_out[i] receives a unique ticket. A background scheduler
+ * admits queued requests when a slot and enough HBM are free, advances all
+ * admitted pairs together (one pass per captured graph node group) and
+ * retires them as they finish, so requests that arrive while others run join
+ * in flight. On the first invalid request nothing is queued and its status is
+ * returned. */
+icp_status icp_batch_submit(icp_ctx *ctx, const icp_request *reqs, int n, uint64_t *tickets_out);
+
+/* ICP_OK and the result (handed out exactly once), ICP_ERR_NOT_READY while
+ * pending, ICP_ERR_UNKNOWN_TICKET otherwise. */
+icp_status icp_poll(icp_ctx *ctx, uint64_t ticket, icp_result *out);
+
+/* Block until every submitted request has finished (results stay pollable). */
+icp_status icp_batch_wait_all(icp_ctx *ctx);
+
+/* Scheduler knobs: passes per graph replay (>= 1) and the maximum number of
+ * concurrently resident pairs (1..1024). */
+icp_status icp_batch_config(icp_ctx *ctx, int passes_per_replay, int max_slots);
+
+const char *icp_status_str(icp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ICP_H */

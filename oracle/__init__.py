@@ -76,6 +76,9 @@ def lib():
                                    C.POINTER(C.c_int)]
         L.orc_register.restype = C.c_int
         L.orc_params_default.argtypes = [C.c_int, C.POINTER(Params)]
+        L.orc_eval.argtypes = [f32p, C.c_int64, f32p, C.c_void_p, C.c_int64, C.c_int, f64p,
+                               C.c_double, C.POINTER(C.c_double), f64p, C.POINTER(C.c_uint)]
+        L.orc_eval.restype = C.c_int
         _lib = L
     return _lib
 
@@ -166,6 +169,24 @@ def median(v):
     return lib().orc_median(v, v.shape[0])
 
 
+def eval_map(P, Q, Qn, mode, T, nu=0.0):
+    """One un-accelerated map application at T: (energy, T_next, flags)."""
+    P = _f32(P).reshape(-1, 3)
+    Q = _f32(Q).reshape(-1, 3)
+    qn = None
+    if Qn is not None:
+        Qn = _f32(Qn).reshape(-1, 3)
+        qn = Qn.ctypes.data
+    E = C.c_double(0.0)
+    Tn = np.zeros(16)
+    fl = C.c_uint(0)
+    rc = lib().orc_eval(P, P.shape[0], Q, qn, Q.shape[0], mode, _f64(T).reshape(16), float(nu),
+                        C.byref(E), Tn, C.byref(fl))
+    if rc != 0:
+        raise ValueError("oracle: invalid eval arguments")
+    return E.value, Tn.reshape(4, 4), fl.value
+
+
 def default_params(mode):
     p = Params()
     lib().orc_params_default(mode, C.byref(p))
@@ -193,7 +214,7 @@ def register(P, Q, Qn=None, params=None, trace_cap=0, etrace_cap=0, **overrides)
     tr = None
     tl = C.c_int(0)
     if trace_cap > 0:
-        tr = np.zeros(16 * trace_cap)
+        tr = np.zeros(20 * trace_cap)
     et = None
     el = C.c_int(0)
     if etrace_cap > 0:
@@ -206,7 +227,7 @@ def register(P, Q, Qn=None, params=None, trace_cap=0, etrace_cap=0, **overrides)
     out = {f: getattr(res, f) for f, _ in Result._fields_ if f != "T"}
     out["T"] = np.array(res.T[:]).reshape(4, 4)
     if tr is not None:
-        out["trace"] = tr[: 16 * tl.value].reshape(-1, 4, 4)
+        out["trace"] = tr[: 20 * tl.value].reshape(-1, 20)
     if et is not None:
         out["etrace"] = et[: 2 * el.value].reshape(-1, 2)
     return out

@@ -601,20 +601,29 @@ typedef struct {
   double E;        /* energy at the evaluated transform for the given nu */
   double prop[16]; /* alignment result T' (p2p) or Gauss-Newton candidate xi* (p2pl) */
   unsigned flags;
-} orc_eval;
+} orc_evalres;
 
 /* Correspondences at T (new pass only when T differs bitwise from the last
  * evaluated one), then FP64 residuals. */
-static void ctx_corr(orc_ctx *c, const double T[16], const double *key, int keylen) {
+static void ctx_record(orc_ctx *c, double E, double nu, int reused, const double T[16]) {
+  if (c->trace && c->trace_len < c->trace_cap) {
+    double *row = c->trace + 20 * c->trace_len;
+    row[0] = E;
+    row[1] = nu;
+    row[2] = -1.0;
+    row[3] = reused;
+    memcpy(row + 4, T, sizeof(double) * 16);
+    c->trace_len++;
+  }
+}
+
+/* Returns 1 when the correspondences of the previous pass were reused. */
+static int ctx_corr(orc_ctx *c, const double T[16], const double *key, int keylen) {
   c->evaluations++;
-  if (c->have_last && memcmp(c->last, key, sizeof(double) * (size_t)keylen) == 0) return;
+  if (c->have_last && memcmp(c->last, key, sizeof(double) * (size_t)keylen) == 0) return 1;
   memcpy(c->last, key, sizeof(double) * (size_t)keylen);
   c->have_last = 1;
   c->nn_passes++;
-  if (c->trace && c->trace_len < c->trace_cap) {
-    memcpy(c->trace + 16 * c->trace_len, T, sizeof(double) * 16);
-    c->trace_len++;
-  }
   orc_transform_f32(T, c->P, c->M, c->Pt);
   orc_nn_brute(c->Pt, c->M, c->Q, c->N, c->idx, c->d2f);
   for (int64_t i = 0; i < c->M; ++i) {
@@ -623,6 +632,7 @@ static void ctx_corr(orc_ctx *c, const double T[16], const double *key, int keyl
     c->Qh[3 * i + 1] = c->Q[3 * j + 1];
     c->Qh[3 * i + 2] = c->Q[3 * j + 2];
   }
+  return 0;
 }
 
 static void ctx_residuals(orc_ctx *c, const double T[16]) {
@@ -641,10 +651,10 @@ static void ctx_residuals(orc_ctx *c, const double T[16]) {
 }
 
 /* Point-to-point evaluation: E_nu and T' = align(Q^, T, nu). */
-static orc_eval eval_p2p(orc_ctx *c, const double T[16], double nu) {
-  orc_eval ev;
+static orc_evalres eval_p2p(orc_ctx *c, const double T[16], double nu) {
+  orc_evalres ev;
   memset(&ev, 0, sizeof ev);
-  ctx_corr(c, T, T, 16);
+  const int reused = ctx_corr(c, T, T, 16);
   ctx_residuals(c, T);
   double E = 0;
   if (c->mode == ORC_P2P_L2) {
@@ -659,6 +669,7 @@ static orc_eval eval_p2p(orc_ctx *c, const double T[16], double nu) {
     ev.flags = orc_procrustes(c->P, c->Qh, c->w, c->M, ev.prop);
   }
   ev.E = E;
+  ctx_record(c, E, c->mode == ORC_P2P_L2 ? 0.0 : nu, reused, T);
   return ev;
 }
 
@@ -693,12 +704,12 @@ static int chol6_solve(const double A[36], const double b[6], double x[6]) {
 
 /* Point-to-plane evaluation at xi: E~_nu(xi) and xi* = G_ppl(xi) (eq. GNMapping):
  * A = sum g J J^T, c = sum g B J, xi* = xi - A^{-1} c (reading R6). */
-static orc_eval eval_p2pl(orc_ctx *c, const double xi[6], double nu) {
-  orc_eval ev;
+static orc_evalres eval_p2pl(orc_ctx *c, const double xi[6], double nu) {
+  orc_evalres ev;
   memset(&ev, 0, sizeof ev);
   double T[16];
   orc_se3_exp(xi, T);
-  ctx_corr(c, T, xi, 6);
+  const int reused = ctx_corr(c, T, xi, 6);
   ctx_residuals(c, T);
   double dR[3][9], Dt[9], Du[9];
   se3_derivs(xi, dR, Dt, Du);
@@ -717,6 +728,7 @@ static orc_eval eval_p2pl(orc_ctx *c, const double xi[6], double nu) {
     }
   }
   ev.E = E;
+  ctx_record(c, E, nu, reused, T);
   for (int a = 0; a < 6; ++a) ev.prop[a] = xi[a];
   if (!(W > 1e-300)) {
     ev.flags = ORC_FLAG_ZERO_WEIGHT;
@@ -805,7 +817,7 @@ static void register_p2p(orc_ctx *c, const orc_params *prm, double nu0, orc_resu
   memcpy(Tkm1, prm->T0, sizeof Tkm1);
   double G[HIST][6], F[HIST][6];
   int k = 1, stage = 0, total = 0, stop_all = 0;
-  orc_eval ev;
+  orc_evalres ev;
   for (;;) {
     const int Inu = stage_cap(prm, stage);
     const int kstart = k - 1;
@@ -902,7 +914,7 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
     const int kstart = k - 1;
     double Eprev = INFINITY;
     res->stages++;
-    orc_eval ev = eval_p2pl(c, xkm1, nu);
+    orc_evalres ev = eval_p2pl(c, xkm1, nu);
     if (ev.flags & (ORC_FLAG_ZERO_WEIGHT | ORC_FLAG_DEGENERATE)) {
       res->flags |= ev.flags;
       memcpy(xk, xkm1, sizeof xk);
@@ -923,13 +935,13 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
       res->iterations++;
       total++;
       double E = ev.E;
-      orc_eval best = ev;
+      orc_evalres best = ev;
       if (E >= Eprev) {
         double tau = 1.0;
         for (int l = 1; l <= prm->max_line_search; ++l) {
           double xt[6];
           for (int a = 0; a < 6; ++a) xt[a] = xkm1[a] + tau * (xstar[a] - xkm1[a]);
-          orc_eval et = eval_p2pl(c, xt, nu);
+          orc_evalres et = eval_p2pl(c, xt, nu);
           res->line_search_trials++;
           if (et.E < E) {
             E = et.E;
@@ -991,6 +1003,38 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
   orc_se3_exp(xk, res->T);
   res->energy = Ecur;
   res->nu_final = nu;
+}
+
+/* One un-accelerated map application at T (see the header). */
+int orc_eval(const float *P, int64_t M, const float *Q, const float *Qn, int64_t N, int mode,
+             const double T[16], double nu, double *E, double Tout[16], unsigned *flags) {
+  if (!P || !Q || M <= 0 || N <= 0 || mode < 0 || mode > 2) return -1;
+  if (mode == ORC_P2PL_WELSCH && !Qn) return -1;
+  if (mode != ORC_P2P_L2 && !(nu > 0)) return -1;
+  orc_ctx c;
+  memset(&c, 0, sizeof c);
+  c.P = P; c.Q = Q; c.Qn = Qn; c.M = M; c.N = N; c.mode = mode;
+  c.Pt = (float *)malloc(sizeof(float) * 3 * (size_t)M);
+  c.idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)M);
+  c.d2f = (float *)malloc(sizeof(float) * (size_t)M);
+  c.Qh = (float *)malloc(sizeof(float) * 3 * (size_t)M);
+  c.res = (double *)malloc(sizeof(double) * (size_t)M);
+  c.w = (double *)malloc(sizeof(double) * (size_t)M);
+  orc_evalres ev;
+  if (mode == ORC_P2PL_WELSCH) {
+    double xi[6];
+    orc_se3_log(T, xi);
+    ev = eval_p2pl(&c, xi, nu);
+    orc_se3_exp(ev.prop, Tout);
+  } else {
+    ev = eval_p2p(&c, T, nu);
+    if (ev.flags & ORC_FLAG_ZERO_WEIGHT) memcpy(Tout, T, sizeof(double) * 16);
+    else memcpy(Tout, ev.prop, sizeof(double) * 16);
+  }
+  *E = ev.E;
+  *flags = ev.flags;
+  free(c.Pt); free(c.idx); free(c.d2f); free(c.Qh); free(c.res); free(c.w);
+  return 0;
 }
 
 int orc_register(const float *P, int64_t M, const float *Q, const float *Qn, int64_t N,

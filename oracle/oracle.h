@@ -90,15 +90,22 @@ int orc_anderson_solve(const double *dF, const double *Fk, int m, int metric,
 double orc_median(const double *v, int64_t n);
 
 /* Full registration: Fast ICP (L2 + AA), Algorithm 1, Algorithm 2.
- * Qn may be NULL except for ORC_P2PL_WELSCH. trace (optional) receives the
- * 16 entries of every transform at which correspondences were computed, up
- * to trace_cap transforms; etrace (optional) receives (stage, accepted energy)
+ * Qn may be NULL except for ORC_P2PL_WELSCH. trace (optional) receives one
+ * row of 20 doubles per evaluation [E, nu, -1, reused, T(16)], up to
+ * trace_cap rows (the setup pass that only feeds the median is not a row);
+ * etrace (optional) receives (stage, accepted energy)
  * for every inner iteration, up to etrace_cap pairs.
  * Returns 0 on success, -1 on invalid arguments. */
 int orc_register(const float *P, int64_t M, const float *Q, const float *Qn,
                  int64_t N, const orc_params *prm, orc_result *res,
                  double *trace, int trace_cap, int *trace_len,
                  double *etrace, int etrace_cap, int *etrace_len);
+
+/* One application of the un-accelerated map at T with parameter nu: the
+ * energy at T and the alignment update (point-to-point) or exp of the
+ * Gauss-Newton candidate at log T (point-to-plane). Returns 0 / -1. */
+int orc_eval(const float *P, int64_t M, const float *Q, const float *Qn, int64_t N, int mode,
+             const double T[16], double nu, double *E, double Tout[16], unsigned *flags);
 
 void orc_params_default(int mode, orc_params *out);
 

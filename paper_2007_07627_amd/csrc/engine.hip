@@ -1,0 +1,976 @@
+// Host runtime of libicp: HBM arena, slot admission (device-side setup on a
+// side stream), the per-pass launch sequence, the plain host-synchronised loop,
+// the hipGraph replay loop and the background scheduler that serves batched
+// requests with continuous admission. Exposes the C ABI of include/icp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "icp.h"
+#include "icp_internal.h"
+
+namespace icp {
+
+// kernels launched from the other translation units
+void launch_nn(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
+void launch_epi(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
+void launch_solver(const SlotDesc*, SlotState*, int, int*, hipStream_t);
+void launch_boot(SlotState*, int, hipStream_t);
+void launch_median(const SlotDesc*, SlotState*, int, hipStream_t);
+void launch_plan(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
+void launch_aos_to_soa(const float*, int, float*, float*, float*, hipStream_t);
+void launch_bbox(const float*, const float*, const float*, int, float*, double*, hipStream_t);
+size_t sort_scratch_words(int);
+void launch_morton_order(const float*, const float*, const float*, int, const float*, unsigned*,
+                         unsigned**, hipStream_t);
+void launch_build_clusters(const float*, const float*, const float*, const unsigned*, int, int,
+                           float4*, float4*, float4*, float4*, float4*, hipStream_t);
+void launch_build_super(const float4*, const float4*, const float4*, int, int, float4*, float4*,
+                        float*, hipStream_t);
+void launch_build_tiles(const float*, const float*, const float*, const unsigned*, int, int, float*,
+                        float*, float*, int*, double4*, hipStream_t);
+void launch_fill_u64(unsigned long long*, int, unsigned long long, hipStream_t);
+
+using Clock = std::chrono::steady_clock;
+
+#define HIP_OK(x)                         \
+  do {                                    \
+    if ((x) != hipSuccess) return false;  \
+  } while (0)
+
+// ------------------------------------------------------------------ arena
+
+// First-fit allocator over one hipMalloc'd region (256-byte granules).
+class Arena {
+ public:
+  bool init(size_t bytes) {
+    size_ = bytes;
+    if (hipMalloc(&base_, bytes) != hipSuccess) { base_ = nullptr; return false; }
+    free_[0] = bytes;
+    return true;
+  }
+  ~Arena() { if (base_) (void)hipFree(base_); }
+  // returns nullptr when no block is large enough
+  char* alloc(size_t bytes) {
+    std::lock_guard<std::mutex> g(mu_);
+    bytes = (bytes + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const size_t off = it->first, sz = it->second;
+        free_.erase(it);
+        if (sz > bytes) free_[off + bytes] = sz - bytes;
+        used_[off] = bytes;
+        in_use_ += bytes;
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(char* p) {
+    std::lock_guard<std::mutex> g(mu_);
+    const size_t off = p - base_;
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    size_t sz = u->second;
+    const size_t orig = sz;
+    used_.erase(u);
+    in_use_ -= sz;
+    size_t start = off;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) { start = pv->first; sz += pv->second; free_.erase(pv); }
+    }
+    nx = free_.lower_bound(off);
+    if (nx != free_.end() && nx->first == off + orig) { sz += nx->second; free_.erase(nx); }
+    free_[start] = sz;
+  }
+  size_t capacity() const { return size_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0, in_use_ = 0;
+  std::map<size_t, size_t> free_, used_;
+  std::mutex mu_;
+};
+
+// ------------------------------------------------------------------ slot memory
+
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+struct Layout {
+  int M, N, ntile, ncl, nsup, nepi;
+  bool normals, outputs;
+  size_t total = 0;
+  // byte offsets
+  size_t o_px, o_py, o_pz, o_perm, o_tsph, o_pox, o_poy, o_poz;
+  size_t o_qx, o_qy, o_qz, o_nx, o_ny, o_nz;
+  size_t o_qloc, o_qorg, o_ccen, o_clo, o_chi, o_slo, o_shi;
+  size_t o_keys, o_nnidx, o_nnd2, o_part, o_med, o_idx, o_d2, o_scratch, o_trace;
+  int trace_cap = 0;
+  size_t add(size_t bytes) {
+    const size_t o = total;
+    total += (bytes + 255) & ~size_t(255);
+    return o;
+  }
+  void plan(int64_t m, int64_t n, bool nrm, bool outs, int tcap = 0) {
+    M = (int)m; N = (int)n;
+    trace_cap = tcap;
+    normals = nrm; outputs = outs;
+    ntile = cdiv(M, kTile);
+    ncl = cdiv(N, kCluster);
+    nsup = cdiv(ncl, kSuper);
+    nepi = cdiv(M, kEpiTile);
+    total = 0;
+    o_px = add(4ull * M); o_py = add(4ull * M); o_pz = add(4ull * M);
+    o_perm = add(4ull * M);
+    o_tsph = add(32ull * ntile);
+    o_pox = add(4ull * M); o_poy = add(4ull * M); o_poz = add(4ull * M);
+    o_qx = add(4ull * N); o_qy = add(4ull * N); o_qz = add(4ull * N);
+    o_nx = add(nrm ? 4ull * N : 0); o_ny = add(nrm ? 4ull * N : 0); o_nz = add(nrm ? 4ull * N : 0);
+    o_qloc = add(16ull * ncl * kCluster);
+    o_qorg = add(16ull * ncl * kCluster);
+    o_ccen = add(16ull * ncl); o_clo = add(16ull * ncl); o_chi = add(16ull * ncl);
+    o_slo = add(16ull * nsup); o_shi = add(16ull * nsup);
+    o_keys = add(8ull * M);
+    o_nnidx = add(4ull * M);
+    o_nnd2 = add(4ull * M);
+    o_part = add(8ull * kPartStride * nepi);
+    o_med = add(8ull * M);
+    o_idx = add(outs ? 4ull * M : 0);
+    o_d2 = add(outs ? 4ull * M : 0);
+    const size_t sw = std::max(sort_scratch_words(std::max(M, N)) * 4, (size_t)12 * std::max(M, N));
+    o_scratch = add(sw);
+    o_trace = add(8ull * kTraceRow * tcap);
+  }
+};
+
+struct HostSlot {
+  bool used = false;
+  char* mem = nullptr;
+  Layout L;
+  uint64_t ticket = 0;
+  Clock::time_point t_submit;
+  int32_t* user_idx = nullptr;  // host outputs of a query (copied at harvest)
+  float* user_d2 = nullptr;
+};
+
+// ------------------------------------------------------------------ requests
+
+struct OwnedRequest {
+  std::vector<float> P, Q, Qn;  // host copies (batch path)
+  const float* P_dev = nullptr;  // device AoS inputs (dev path)
+  const float* Q_dev = nullptr;
+  const float* Qn_dev = nullptr;
+  int64_t M = 0, N = 0;
+  icp_params prm{};
+  bool query = false;
+  bool eval = false;   // one application of the MM map (icp_eval)
+  double Tq[16];
+  icp_nn_method qmethod = ICP_NN_AUTO;
+  int32_t* idx_dev_out = nullptr;  // device outputs for a dev query
+  float* d2_dev_out = nullptr;
+  int trace_cap = 0;               // per-pass trace rows kept on the device
+  uint64_t ticket = 0;
+  Clock::time_point t_submit;
+};
+
+static void fill_result(const SlotState& S, icp_result* r) {
+  std::memcpy(r->T, S.Tres, sizeof r->T);
+  r->energy = S.energy;
+  r->nu_final = S.nu_final;
+  r->iterations = S.iterations;
+  r->nn_passes = S.nn_passes;
+  r->evaluations = S.evaluations;
+  r->aa_accepted = S.aa_accepted;
+  r->aa_rejected = S.aa_rejected;
+  r->line_search_trials = S.ls_trials;
+  r->stages = S.stages;
+  r->status_flags = S.flags;
+}
+
+// ------------------------------------------------------------------ engine
+
+struct Engine {
+  int dev = 0;
+  int capacity = 1;
+  int target_items = 4096;   // NN work items aimed for when choosing splits
+  hipStream_t st = nullptr;  // passes
+  hipStream_t side = nullptr;  // admission / setup
+  SlotDesc* d_desc = nullptr;
+  SlotState* d_state = nullptr;
+  WorkList* d_wl = nullptr;
+  int* d_done = nullptr;
+  int* h_done = nullptr;
+  std::vector<HostSlot> hs;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int gphases = 0;
+  int gcap = 0;
+  int nn_grid = 4096, epi_grid = 1024;
+  Arena* arena = nullptr;
+
+  bool init(int device, int cap, Arena* a, int items) {
+    dev = device;
+    capacity = cap;
+    arena = a;
+    target_items = items;
+    HIP_OK(hipSetDevice(dev));
+    HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    HIP_OK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    HIP_OK(hipMalloc(&d_desc, sizeof(SlotDesc) * kMaxSlots));
+    HIP_OK(hipMalloc(&d_state, sizeof(SlotState) * kMaxSlots));
+    HIP_OK(hipMalloc(&d_wl, sizeof(WorkList)));
+    HIP_OK(hipMalloc(&d_done, sizeof(int) * kMaxSlots));
+    HIP_OK(hipHostMalloc((void**)&h_done, sizeof(int) * kMaxSlots, hipHostMallocDefault));
+    HIP_OK(hipMemset(d_desc, 0, sizeof(SlotDesc) * kMaxSlots));
+    HIP_OK(hipMemset(d_state, 0, sizeof(SlotState) * kMaxSlots));
+    HIP_OK(hipMemset(d_done, 0, sizeof(int) * kMaxSlots));
+    std::memset(h_done, 0, sizeof(int) * kMaxSlots);
+    hs.assign(kMaxSlots, HostSlot());
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+    nn_grid = cus * 16;
+    epi_grid = cus * 4;
+    return true;
+  }
+
+  void destroy() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr; graph = nullptr;
+    for (auto& h : hs)
+      if (h.used && h.mem) arena->release(h.mem);
+    if (d_desc) (void)hipFree(d_desc);
+    if (d_state) (void)hipFree(d_state);
+    if (d_wl) (void)hipFree(d_wl);
+    if (d_done) (void)hipFree(d_done);
+    if (h_done) (void)hipHostFree(h_done);
+    if (st) (void)hipStreamDestroy(st);
+    if (side) (void)hipStreamDestroy(side);
+    d_desc = nullptr; d_state = nullptr; d_wl = nullptr; d_done = nullptr; h_done = nullptr;
+    st = nullptr; side = nullptr;
+  }
+
+  void enqueue_pass(hipStream_t s) {
+    launch_plan(d_desc, d_state, d_wl, capacity, s);
+    launch_nn(d_desc, d_state, d_wl, nn_grid, s);
+    launch_epi(d_desc, d_state, d_wl, epi_grid, s);
+    launch_median(d_desc, d_state, capacity, s);
+    launch_solver(d_desc, d_state, capacity, d_done, s);
+  }
+
+  bool build_graph(int phases) {
+    if (gexec && gphases == phases && gcap == capacity) return true;
+    if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
+    if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+    HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < phases; ++i) enqueue_pass(st);
+    HIP_OK(hipStreamEndCapture(st, &graph));
+    HIP_OK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    gphases = phases;
+    gcap = capacity;
+    return true;
+  }
+
+  int free_slot() const {
+    for (int i = 0; i < capacity; ++i)
+      if (!hs[i].used) return i;
+    return -1;
+  }
+
+  static size_t footprint(const OwnedRequest& r) {
+    Layout L;
+    L.plan(r.M, r.N, r.prm.mode == ICP_P2PL_WELSCH, r.query && !r.idx_dev_out);
+    return L.total;
+  }
+
+  // Device-side setup of slot `s` for request r on the side stream. Returns
+  // false on a HIP error; OOM is reported through *oom.
+  bool admit(int s, const OwnedRequest& r, bool* oom) {
+    *oom = false;
+    HostSlot& h = hs[s];
+    const bool p2pl = !r.query && r.prm.mode == ICP_P2PL_WELSCH;
+    h.L.plan(r.M, r.N, p2pl, r.query && !r.idx_dev_out, r.trace_cap);
+    h.mem = arena->alloc(h.L.total);
+    if (!h.mem) { *oom = true; return true; }
+    h.used = true;
+    h.ticket = r.ticket;
+    h.t_submit = r.t_submit;
+    const Layout& L = h.L;
+    char* b = h.mem;
+    auto F = [&](size_t o) { return reinterpret_cast<float*>(b + o); };
+    auto F4 = [&](size_t o) { return reinterpret_cast<float4*>(b + o); };
+    float* stage = F(L.o_scratch);
+    unsigned* scratch = reinterpret_cast<unsigned*>(b + L.o_scratch);
+    hipStream_t ss = side;
+    char* st_base = reinterpret_cast<char*>(d_state + s);
+    float* bbQ = reinterpret_cast<float*>(st_base + offsetof(SlotState, bbQ));
+    float* bbP = reinterpret_cast<float*>(st_base + offsetof(SlotState, bbP));
+    double* cQ = reinterpret_cast<double*>(st_base + offsetof(SlotState, cQ));
+    double* cP = reinterpret_cast<double*>(st_base + offsetof(SlotState, cP));
+    float* rho = reinterpret_cast<float*>(reinterpret_cast<char*>(d_desc + s) + offsetof(SlotDesc, rho_max));
+    // state first (kernels below write some of its fields)
+    SlotState S;
+    std::memset(&S, 0, sizeof S);
+    S.status = ST_SETUP;
+    S.mode = r.query ? P2P_L2 : (int)r.prm.mode;
+    S.sm = r.query ? SM_QUERY : (r.eval ? SM_EVAL : SM_INIT);
+    S.m = r.prm.anderson_m;
+    S.lmax = r.prm.max_line_search;
+    S.iter_first = r.prm.iter_first;
+    S.iter_inc = r.prm.iter_inc;
+    S.iter_cap = r.prm.iter_cap;
+    S.max_total = r.prm.max_total_iter;
+    S.eps = r.prm.eps;
+    S.nu_min = r.prm.nu_min;
+    S.nu_max = r.prm.nu_max;
+    S.nu_auto = (!r.query && !r.eval && r.prm.mode != ICP_P2P_L2 && !(r.prm.nu_max > 0)) ? 1 : 0;
+    S.want_median = S.nu_auto;
+    S.k = 1;
+    std::memcpy(S.Tkm1, (r.query || r.eval) ? r.Tq : r.prm.T0, sizeof S.Tkm1);
+    HIP_OK(hipMemcpyAsync(d_state + s, &S, sizeof S, hipMemcpyHostToDevice, ss));
+    // inputs -> SoA
+    auto upload = [&](const std::vector<float>& hv, const float* dv, int n, float* x, float* y,
+                      float* z) -> bool {
+      const float* src = dv;
+      if (!dv) {
+        HIP_OK(hipMemcpyAsync(stage, hv.data(), 12ull * n, hipMemcpyHostToDevice, ss));
+        src = stage;
+      }
+      launch_aos_to_soa(src, n, x, y, z, ss);
+      return true;
+    };
+    if (!upload(r.Q, r.Q_dev, L.N, F(L.o_qx), F(L.o_qy), F(L.o_qz))) return false;
+    if (p2pl && !upload(r.Qn, r.Qn_dev, L.N, F(L.o_nx), F(L.o_ny), F(L.o_nz))) return false;
+    if (!upload(r.P, r.P_dev, L.M, F(L.o_pox), F(L.o_poy), F(L.o_poz))) return false;
+    // target cluster index
+    launch_bbox(F(L.o_qx), F(L.o_qy), F(L.o_qz), L.N, bbQ, cQ, ss);
+    unsigned* order = nullptr;
+    launch_morton_order(F(L.o_qx), F(L.o_qy), F(L.o_qz), L.N, bbQ, scratch, &order, ss);
+    launch_build_clusters(F(L.o_qx), F(L.o_qy), F(L.o_qz), order, L.N, L.ncl, F4(L.o_qloc),
+                          F4(L.o_qorg), F4(L.o_ccen), F4(L.o_clo), F4(L.o_chi), ss);
+    launch_build_super(F4(L.o_clo), F4(L.o_chi), F4(L.o_ccen), L.ncl, L.nsup, F4(L.o_slo),
+                       F4(L.o_shi), rho, ss);
+    // source tiles
+    launch_bbox(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, cP, ss);
+    launch_morton_order(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, scratch, &order, ss);
+    launch_build_tiles(F(L.o_pox), F(L.o_poy), F(L.o_poz), order, L.M, L.ntile, F(L.o_px),
+                       F(L.o_py), F(L.o_pz), reinterpret_cast<int*>(b + L.o_perm),
+                       reinterpret_cast<double4*>(b + L.o_tsph), ss);
+    launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_keys), L.M, ~0ull, ss);
+    // descriptor (rho_max is written by build_super above, so copy the rest around it)
+    SlotDesc D;
+    std::memset(&D, 0, sizeof D);
+    D.px = F(L.o_px); D.py = F(L.o_py); D.pz = F(L.o_pz);
+    D.perm = reinterpret_cast<int*>(b + L.o_perm);
+    D.tsph = reinterpret_cast<double4*>(b + L.o_tsph);
+    D.qx = F(L.o_qx); D.qy = F(L.o_qy); D.qz = F(L.o_qz);
+    D.nx = p2pl ? F(L.o_nx) : nullptr;
+    D.ny = p2pl ? F(L.o_ny) : nullptr;
+    D.nz = p2pl ? F(L.o_nz) : nullptr;
+    D.qloc = F4(L.o_qloc); D.qorg = F4(L.o_qorg); D.ccen = F4(L.o_ccen);
+    D.clo = F4(L.o_clo); D.chi = F4(L.o_chi); D.slo = F4(L.o_slo); D.shi = F4(L.o_shi);
+    D.keys = reinterpret_cast<unsigned long long*>(b + L.o_keys);
+    D.nnidx = reinterpret_cast<int32_t*>(b + L.o_nnidx);
+    D.nnd2 = F(L.o_nnd2);
+    D.part = reinterpret_cast<double*>(b + L.o_part);
+    D.medkey = reinterpret_cast<double*>(b + L.o_med);
+    if (r.query) {
+      D.idx_out = r.idx_dev_out ? r.idx_dev_out : reinterpret_cast<int32_t*>(b + L.o_idx);
+      D.d2_out = r.d2_dev_out ? r.d2_dev_out : F(L.o_d2);
+    }
+    D.trace = L.trace_cap > 0 ? reinterpret_cast<double*>(b + L.o_trace) : nullptr;
+    D.trace_cap = L.trace_cap;
+    D.M = L.M; D.N = L.N; D.ntile = L.ntile; D.ncl = L.ncl; D.nsup = L.nsup; D.nepi = L.nepi;
+    icp_nn_method meth = r.query ? r.qmethod : r.prm.nn;
+    if (meth == ICP_NN_AUTO) meth = ((double)L.M * L.N <= 64.0e6) ? ICP_NN_BRUTE : ICP_NN_CLUSTER;
+    D.method = meth == ICP_NN_BRUTE ? NN_BRUTE : NN_CLUSTER;
+    D.mode = S.mode;
+    int split = std::max(1, cdiv(target_items, std::max(1, L.ntile)));
+    split = std::min(split, std::min(kMaxSplit, L.ncl));
+    D.split = std::max(1, split);
+    HIP_OK(hipMemcpyAsync(d_desc + s, &D, offsetof(SlotDesc, rho_max), hipMemcpyHostToDevice, ss));
+    const int zero = 0;
+    HIP_OK(hipMemcpyAsync(d_done + s, &zero, sizeof(int), hipMemcpyHostToDevice, ss));
+    h_done[s] = 0;
+    // host sources of the async copies above live in this frame / the request
+    HIP_OK(hipStreamSynchronize(ss));
+    return hipGetLastError() == hipSuccess;
+  }
+
+  // Make the slot RUNNING on the pass stream once its setup has completed.
+  bool activate(int s) {
+    hipEvent_t ev;
+    HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_OK(hipEventRecord(ev, side));
+    HIP_OK(hipStreamWaitEvent(st, ev, 0));
+    launch_boot(d_state, s, st);
+    (void)hipEventDestroy(ev);
+    return hipGetLastError() == hipSuccess;
+  }
+
+  bool read_state(int s, SlotState* S) {
+    HIP_OK(hipMemcpyAsync(S, d_state + s, sizeof(SlotState), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return true;
+  }
+
+  void release(int s) {
+    HostSlot& h = hs[s];
+    if (h.mem) arena->release(h.mem);
+    h = HostSlot();
+    h_done[s] = 0;
+  }
+};
+
+}  // namespace icp
+
+using namespace icp;
+
+// ------------------------------------------------------------------ context
+
+struct icp_ctx {
+  int device = 0;
+  Arena arena;
+  Engine sync_eng;       // icp_register / icp_nn_query
+  Engine batch_eng;      // icp_batch_submit / icp_poll
+  std::mutex sync_mu;
+  // batch scheduler
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::deque<std::unique_ptr<OwnedRequest>> queue;
+  std::unordered_map<uint64_t, int> state;   // 0 queued, 1 running, 2 done
+  std::unordered_map<uint64_t, icp_result> results;
+  std::thread worker;
+  bool stop = false;
+  bool started = false;
+  bool failed = false;
+  uint64_t next_ticket = 1;
+  int passes_per_replay = 4;
+  int max_slots = 256;
+  int running = 0;
+};
+
+static const size_t kQueueCap = 1 << 20;
+
+static bool finite_coords(const float* p, int64_t n) {
+  for (int64_t i = 0; i < 3 * n; ++i) {
+    const float v = p[i];
+    if (!std::isfinite(v) || std::fabs(v) > 1e15f) return false;
+  }
+  return true;
+}
+
+static bool rigid_ok(const double* T) {
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(T[i])) return false;
+  if (T[12] != 0.0 || T[13] != 0.0 || T[14] != 0.0 || T[15] != 1.0) return false;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += T[4 * k + i] * T[4 * k + j];
+      if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-9) return false;
+    }
+  const double det = T[0] * (T[5] * T[10] - T[6] * T[9]) - T[1] * (T[4] * T[10] - T[6] * T[8]) +
+                     T[2] * (T[4] * T[9] - T[5] * T[8]);
+  return det > 0.0;
+}
+
+static icp_status check_params(const icp_params* p) {
+  if (!p) return ICP_ERR_INVALID_ARG;
+  if (p->mode < ICP_P2P_L2 || p->mode > ICP_P2PL_WELSCH) return ICP_ERR_INVALID_ARG;
+  if (p->anderson_m < 0 || p->anderson_m > 6) return ICP_ERR_INVALID_ARG;
+  if (p->mode != ICP_P2P_L2 && !(p->nu_min > 0.0 && std::isfinite(p->nu_min))) return ICP_ERR_INVALID_ARG;
+  if (!(p->eps > 0.0) || p->iter_first <= 0 || p->max_line_search < 0) return ICP_ERR_INVALID_ARG;
+  if (p->nn < ICP_NN_AUTO || p->nn > ICP_NN_CLUSTER) return ICP_ERR_INVALID_ARG;
+  if (p->engine != ICP_ENGINE_GRAPH && p->engine != ICP_ENGINE_PLAIN) return ICP_ERR_INVALID_ARG;
+  if (!std::isfinite(p->nu_max)) return ICP_ERR_INVALID_ARG;
+  if (!rigid_ok(p->T0)) return ICP_ERR_INVALID_ARG;
+  return ICP_OK;
+}
+
+static icp_status check_sizes(int64_t M, int64_t N) {
+  if (M <= 0 || N <= 0 || M > (1 << 28) || N > (1 << 28)) return ICP_ERR_INVALID_ARG;
+  return ICP_OK;
+}
+
+// Run one slot of the synchronous engine to completion.
+static icp_status run_sync(icp_ctx* ctx, OwnedRequest& r, icp_result* out, void* ustream,
+                           int32_t* host_idx, float* host_d2, double* host_trace = nullptr,
+                           int* trace_len = nullptr) {
+  Engine& E = ctx->sync_eng;
+  const auto t0 = Clock::now();
+  hipStream_t us = reinterpret_cast<hipStream_t>(ustream);
+  if (hipSetDevice(ctx->device) != hipSuccess) return ICP_ERR_DEVICE;
+  // order after the caller's stream
+  if (r.P_dev) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return ICP_ERR_DEVICE;
+    if (hipEventRecord(ev, us) != hipSuccess || hipStreamWaitEvent(E.side, ev, 0) != hipSuccess) {
+      (void)hipEventDestroy(ev);
+      return ICP_ERR_DEVICE;
+    }
+    (void)hipEventDestroy(ev);
+  }
+  bool oom = false;
+  if (!E.admit(0, r, &oom)) { E.release(0); return ICP_ERR_DEVICE; }
+  if (oom) return ICP_ERR_OOM;
+  if (!E.activate(0)) { E.release(0); return ICP_ERR_DEVICE; }
+  const bool plain = !r.query && !r.eval && r.prm.engine == ICP_ENGINE_PLAIN;
+  icp_status rc = ICP_OK;
+  const long kMaxPasses = 200000;  // host guard against a runaway state machine
+  long passes = 0;
+  if (plain) {
+    for (;; ++passes) {
+      if (passes > kMaxPasses) { rc = ICP_ERR_DEVICE; break; }
+      E.enqueue_pass(E.st);
+      if (hipMemcpyAsync(E.h_done, E.d_done, sizeof(int), hipMemcpyDeviceToHost, E.st) != hipSuccess ||
+          hipStreamSynchronize(E.st) != hipSuccess) { rc = ICP_ERR_DEVICE; break; }
+      if (E.h_done[0]) break;
+    }
+  } else {
+    const int R = (r.query || r.eval) ? 1 : 8;
+    if (!E.build_graph(R)) { E.release(0); return ICP_ERR_DEVICE; }
+    for (;; passes += R) {
+      if (passes > kMaxPasses) { rc = ICP_ERR_DEVICE; break; }
+      if (hipGraphLaunch(E.gexec, E.st) != hipSuccess ||
+          hipMemcpyAsync(E.h_done, E.d_done, sizeof(int), hipMemcpyDeviceToHost, E.st) != hipSuccess ||
+          hipStreamSynchronize(E.st) != hipSuccess) { rc = ICP_ERR_DEVICE; break; }
+      if (E.h_done[0]) break;
+    }
+  }
+  if (rc == ICP_OK) {
+    SlotState S;
+    if (!E.read_state(0, &S)) rc = ICP_ERR_DEVICE;
+    else if (out) {
+      fill_result(S, out);
+      out->latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+    }
+    if (rc == ICP_OK && host_trace && trace_len) {
+      const Layout& L = E.hs[0].L;
+      *trace_len = std::min(S.trace_len, L.trace_cap);
+      if (*trace_len > 0 &&
+          hipMemcpy(host_trace, E.hs[0].mem + L.o_trace, 8ull * kTraceRow * *trace_len,
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        rc = ICP_ERR_DEVICE;
+    }
+    if (rc == ICP_OK && r.query && host_idx) {
+      const Layout& L = E.hs[0].L;
+      if (hipMemcpy(host_idx, E.hs[0].mem + L.o_idx, 4ull * r.M, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(host_d2, E.hs[0].mem + L.o_d2, 4ull * r.M, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = ICP_ERR_DEVICE;
+    }
+  }
+  // the caller's stream waits for our work
+  if (r.P_dev) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+      (void)hipEventRecord(ev, E.st);
+      (void)hipStreamWaitEvent(us, ev, 0);
+      (void)hipEventDestroy(ev);
+    }
+  }
+  (void)hipStreamSynchronize(E.st);
+  E.release(0);
+  return rc;
+}
+
+// ------------------------------------------------------------------ scheduler
+
+static void scheduler(icp_ctx* ctx) {
+  Engine& E = ctx->batch_eng;
+  (void)hipSetDevice(ctx->device);
+  for (;;) {
+    int R, running;
+    {
+      std::unique_lock<std::mutex> lk(ctx->mu);
+      ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty() || ctx->running > 0; });
+      if (ctx->stop) return;
+      R = ctx->passes_per_replay;
+      running = ctx->running;
+      if (running == 0) E.capacity = ctx->max_slots;
+    }
+    bool ok = true;
+    // 1) advance every resident pair by R passes (asynchronous)
+    if (running > 0) ok = E.build_graph(R) && hipGraphLaunch(E.gexec, E.st) == hipSuccess;
+    // 2) meanwhile set up queued requests on the side stream (FIFO; a request
+    //    that does not fit waits for memory unless nothing else is resident)
+    for (; ok;) {
+      std::unique_ptr<OwnedRequest> req;
+      int s;
+      {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->queue.empty()) break;
+        s = E.free_slot();
+        if (s < 0) break;
+        req = std::move(ctx->queue.front());
+        ctx->queue.pop_front();
+      }
+      bool oom = false;
+      const bool adm = E.admit(s, *req, &oom);
+      if (adm && oom) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->running == 0) {
+          ctx->state[req->ticket] = 3;  // can never fit the budget
+        } else {
+          ctx->queue.push_front(std::move(req));
+        }
+        break;
+      }
+      if (!adm || !E.activate(s)) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->state[req->ticket] = 4;
+        E.release(s);
+        ok = false;
+        break;
+      }
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->state[req->ticket] = 1;
+      ctx->running++;
+    }
+    // 3) completion flags after the replay (and after the boots of new slots)
+    if (ok)
+      ok = hipMemcpyAsync(E.h_done, E.d_done, sizeof(int) * E.capacity, hipMemcpyDeviceToHost, E.st) ==
+               hipSuccess &&
+           hipStreamSynchronize(E.st) == hipSuccess;
+    if (!ok) {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->failed = true;
+      ctx->stop = true;
+      ctx->cv_done.notify_all();
+      return;
+    }
+    // 4) retire finished pairs
+    for (int s = 0; s < E.capacity; ++s) {
+      if (!E.hs[s].used || !E.h_done[s]) continue;
+      SlotState S;
+      icp_result res;
+      std::memset(&res, 0, sizeof res);
+      if (E.read_state(s, &S)) fill_result(S, &res);
+      res.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - E.hs[s].t_submit).count();
+      const int zero = 0;
+      const int st_free = ST_FREE;
+      (void)hipMemcpyAsync(E.d_done + s, &zero, sizeof(int), hipMemcpyHostToDevice, E.st);
+      (void)hipMemcpyAsync(reinterpret_cast<char*>(E.d_state + s) + offsetof(SlotState, status), &st_free,
+                           sizeof(int), hipMemcpyHostToDevice, E.st);
+      (void)hipStreamSynchronize(E.st);
+      const uint64_t t = E.hs[s].ticket;
+      E.release(s);
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->results[t] = res;
+      ctx->state[t] = 2;
+      ctx->running--;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->cv_done.notify_all();
+  }
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* icp_status_str(icp_status s) {
+  switch (s) {
+    case ICP_OK: return "ok";
+    case ICP_ERR_INVALID_ARG: return "invalid argument";
+    case ICP_ERR_NONFINITE: return "non-finite or out-of-range coordinate";
+    case ICP_ERR_NO_NORMALS: return "point-to-plane mode needs target normals";
+    case ICP_ERR_OOM: return "out of device memory budget";
+    case ICP_ERR_DEVICE: return "HIP device error";
+    case ICP_ERR_NOT_READY: return "not ready";
+    case ICP_ERR_UNKNOWN_TICKET: return "unknown ticket";
+    case ICP_ERR_QUEUE_FULL: return "queue full";
+  }
+  return "unknown status";
+}
+
+icp_status icp_params_default(icp_mode mode, icp_params* out) {
+  if (!out || mode < ICP_P2P_L2 || mode > ICP_P2PL_WELSCH) return ICP_ERR_INVALID_ARG;
+  std::memset(out, 0, sizeof *out);
+  out->mode = mode;
+  out->anderson_m = 5;
+  out->nu_max = -1.0;
+  out->nu_min = -1.0;
+  out->eps = 1e-5;
+  out->max_total_iter = 0;
+  out->max_line_search = 10;
+  if (mode == ICP_P2PL_WELSCH) {
+    out->iter_first = 6; out->iter_inc = 1; out->iter_cap = 10;
+  } else {
+    out->iter_first = 1000; out->iter_inc = 0; out->iter_cap = 1000;
+  }
+  out->nn = ICP_NN_AUTO;
+  out->engine = ICP_ENGINE_GRAPH;
+  for (int i = 0; i < 16; ++i) out->T0[i] = (i % 5 == 0) ? 1.0 : 0.0;
+  return ICP_OK;
+}
+
+icp_status icp_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
+  if (!out) return ICP_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return ICP_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return ICP_ERR_DEVICE;
+  auto* c = new (std::nothrow) icp_ctx();
+  if (!c) return ICP_ERR_OOM;
+  c->device = device;
+  if (hbm_budget_bytes == 0) hbm_budget_bytes = size_t(8) << 30;
+  if (!c->arena.init(hbm_budget_bytes)) { delete c; return ICP_ERR_OOM; }
+  if (!c->sync_eng.init(device, 1, &c->arena, 4096) || !c->batch_eng.init(device, c->max_slots, &c->arena, 64)) {
+    c->sync_eng.destroy();
+    c->batch_eng.destroy();
+    delete c;
+    return ICP_ERR_DEVICE;
+  }
+  *out = c;
+  return ICP_OK;
+}
+
+icp_status icp_destroy(icp_ctx* ctx) {
+  if (!ctx) return ICP_ERR_INVALID_ARG;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->stop = true;
+  }
+  ctx->cv.notify_all();
+  if (ctx->worker.joinable()) ctx->worker.join();
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->sync_eng.destroy();
+  ctx->batch_eng.destroy();
+  delete ctx;
+  return ICP_OK;
+}
+
+static icp_status validate_host(const float* P, int64_t M, const float* Q, const float* Qn, int64_t N,
+                                const icp_params* prm) {
+  if (!P || !Q) return ICP_ERR_INVALID_ARG;
+  icp_status s = check_sizes(M, N);
+  if (s != ICP_OK) return s;
+  s = check_params(prm);
+  if (s != ICP_OK) return s;
+  if (prm->mode == ICP_P2PL_WELSCH && !Qn) return ICP_ERR_NO_NORMALS;
+  if (!finite_coords(P, M) || !finite_coords(Q, N)) return ICP_ERR_NONFINITE;
+  if (prm->mode == ICP_P2PL_WELSCH) {
+    if (!finite_coords(Qn, N)) return ICP_ERR_NONFINITE;
+    for (int64_t i = 0; i < N; ++i) {
+      const double l = (double)Qn[3 * i] * Qn[3 * i] + (double)Qn[3 * i + 1] * Qn[3 * i + 1] +
+                       (double)Qn[3 * i + 2] * Qn[3 * i + 2];
+      if (!(l > 0.25 && l < 4.0)) return ICP_ERR_INVALID_ARG;  // zero or far-from-unit normals
+    }
+  }
+  return ICP_OK;
+}
+
+icp_status icp_register(icp_ctx* ctx, const float* P, int64_t M, const float* Q, const float* Qn,
+                        int64_t N, const icp_params* params, icp_result* out) {
+  if (!ctx || !out) return ICP_ERR_INVALID_ARG;
+  const icp_status v = validate_host(P, M, Q, Qn, N, params);
+  if (v != ICP_OK) return v;
+  OwnedRequest r;
+  r.P.assign(P, P + 3 * M);
+  r.Q.assign(Q, Q + 3 * N);
+  if (params->mode == ICP_P2PL_WELSCH) r.Qn.assign(Qn, Qn + 3 * N);
+  r.M = M; r.N = N; r.prm = *params;
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  return run_sync(ctx, r, out, nullptr, nullptr, nullptr);
+}
+
+icp_status icp_eval(icp_ctx* ctx, const float* P, int64_t M, const float* Q, const float* Qn,
+                    int64_t N, icp_mode mode, const double T[16], double nu, double* energy_out,
+                    double T_out[16], unsigned* flags_out) {
+  if (!ctx || !T || !energy_out || !T_out || !flags_out) return ICP_ERR_INVALID_ARG;
+  icp_params prm;
+  if (icp_params_default(mode, &prm) != ICP_OK) return ICP_ERR_INVALID_ARG;
+  if (mode != ICP_P2P_L2 && !(nu > 0.0 && std::isfinite(nu))) return ICP_ERR_INVALID_ARG;
+  prm.nu_min = mode == ICP_P2P_L2 ? 0.0 : nu;
+  prm.nu_max = mode == ICP_P2P_L2 ? 1.0 : nu;
+  std::memcpy(prm.T0, T, sizeof prm.T0);
+  const icp_status v = validate_host(P, M, Q, Qn, N, &prm);
+  if (v != ICP_OK) return v;
+  OwnedRequest r;
+  r.P.assign(P, P + 3 * M);
+  r.Q.assign(Q, Q + 3 * N);
+  if (mode == ICP_P2PL_WELSCH) r.Qn.assign(Qn, Qn + 3 * N);
+  r.M = M; r.N = N; r.prm = prm;
+  r.eval = true;
+  std::memcpy(r.Tq, T, sizeof r.Tq);
+  icp_result res;
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  const icp_status rc = run_sync(ctx, r, &res, nullptr, nullptr, nullptr);
+  if (rc != ICP_OK) return rc;
+  *energy_out = res.energy;
+  std::memcpy(T_out, res.T, sizeof res.T);
+  *flags_out = res.status_flags;
+  return ICP_OK;
+}
+
+icp_status icp_register_trace(icp_ctx* ctx, const float* P, int64_t M, const float* Q,
+                              const float* Qn, int64_t N, const icp_params* params, icp_result* out,
+                              double* trace_out, int trace_cap, int* trace_len) {
+  if (!ctx || !out || !trace_len || trace_cap < 0 || (trace_cap > 0 && !trace_out))
+    return ICP_ERR_INVALID_ARG;
+  *trace_len = 0;
+  const icp_status v = validate_host(P, M, Q, Qn, N, params);
+  if (v != ICP_OK) return v;
+  OwnedRequest r;
+  r.P.assign(P, P + 3 * M);
+  r.Q.assign(Q, Q + 3 * N);
+  if (params->mode == ICP_P2PL_WELSCH) r.Qn.assign(Qn, Qn + 3 * N);
+  r.M = M; r.N = N; r.prm = *params;
+  r.trace_cap = trace_cap;
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  return run_sync(ctx, r, out, nullptr, nullptr, nullptr, trace_out, trace_len);
+}
+
+icp_status icp_register_dev(icp_ctx* ctx, const float* P_dev, int64_t M, const float* Q_dev,
+                            const float* Qn_dev, int64_t N, const icp_params* params,
+                            icp_result* out, void* stream) {
+  if (!ctx || !out || !P_dev || !Q_dev) return ICP_ERR_INVALID_ARG;
+  icp_status s = check_sizes(M, N);
+  if (s != ICP_OK) return s;
+  s = check_params(params);
+  if (s != ICP_OK) return s;
+  if (params->mode == ICP_P2PL_WELSCH && !Qn_dev) return ICP_ERR_NO_NORMALS;
+  OwnedRequest r;
+  r.P_dev = P_dev; r.Q_dev = Q_dev; r.Qn_dev = Qn_dev;
+  r.M = M; r.N = N; r.prm = *params;
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  return run_sync(ctx, r, out, stream, nullptr, nullptr);
+}
+
+icp_status icp_nn_query(icp_ctx* ctx, const float* P, int64_t M, const float* Q, int64_t N,
+                        const double T[16], icp_nn_method method, int32_t* idx_out, float* d2_out) {
+  if (!ctx || !T || method < ICP_NN_AUTO || method > ICP_NN_CLUSTER) return ICP_ERR_INVALID_ARG;
+  if (M < 0 || N <= 0 || M > (1 << 28) || N > (1 << 28) || !Q) return ICP_ERR_INVALID_ARG;
+  if (M == 0) return ICP_OK;
+  if (!P || !idx_out || !d2_out) return ICP_ERR_INVALID_ARG;
+  if (!rigid_ok(T)) return ICP_ERR_INVALID_ARG;
+  if (!finite_coords(P, M) || !finite_coords(Q, N)) return ICP_ERR_NONFINITE;
+  OwnedRequest r;
+  r.P.assign(P, P + 3 * M);
+  r.Q.assign(Q, Q + 3 * N);
+  r.M = M; r.N = N;
+  icp_params_default(ICP_P2P_L2, &r.prm);
+  r.query = true;
+  std::memcpy(r.Tq, T, sizeof r.Tq);
+  r.qmethod = method;
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  icp_result res;
+  return run_sync(ctx, r, &res, nullptr, idx_out, d2_out);
+}
+
+icp_status icp_nn_query_dev(icp_ctx* ctx, const float* P_dev, int64_t M, const float* Q_dev,
+                            int64_t N, const double T[16], icp_nn_method method,
+                            int32_t* idx_out_dev, float* d2_out_dev, void* stream) {
+  if (!ctx || !T || method < ICP_NN_AUTO || method > ICP_NN_CLUSTER) return ICP_ERR_INVALID_ARG;
+  if (M < 0 || N <= 0 || M > (1 << 28) || N > (1 << 28) || !Q_dev) return ICP_ERR_INVALID_ARG;
+  if (M == 0) return ICP_OK;
+  if (!P_dev || !idx_out_dev || !d2_out_dev) return ICP_ERR_INVALID_ARG;
+  if (!rigid_ok(T)) return ICP_ERR_INVALID_ARG;
+  OwnedRequest r;
+  r.P_dev = P_dev; r.Q_dev = Q_dev;
+  r.M = M; r.N = N;
+  icp_params_default(ICP_P2P_L2, &r.prm);
+  r.query = true;
+  std::memcpy(r.Tq, T, sizeof r.Tq);
+  r.qmethod = method;
+  r.idx_dev_out = idx_out_dev;
+  r.d2_dev_out = d2_out_dev;
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  icp_result res;
+  return run_sync(ctx, r, &res, stream, nullptr, nullptr);
+}
+
+icp_status icp_batch_config(icp_ctx* ctx, int passes_per_replay, int max_slots) {
+  if (!ctx || passes_per_replay < 1 || passes_per_replay > 64 || max_slots < 1 || max_slots > kMaxSlots)
+    return ICP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (ctx->running > 0) {
+    // shrinking below resident slots is not allowed while pairs run
+    if (max_slots < ctx->max_slots) return ICP_ERR_INVALID_ARG;
+  }
+  ctx->passes_per_replay = passes_per_replay;
+  ctx->max_slots = max_slots;
+  return ICP_OK;
+}
+
+icp_status icp_batch_submit(icp_ctx* ctx, const icp_request* reqs, int n, uint64_t* tickets_out) {
+  if (!ctx || n < 0 || (n > 0 && (!reqs || !tickets_out))) return ICP_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    const icp_request& q = reqs[i];
+    const icp_status v = validate_host(q.P, q.M, q.Q, q.Qn, q.N, &q.params);
+    if (v != ICP_OK) return v;
+  }
+  std::vector<std::unique_ptr<OwnedRequest>> owned;
+  owned.reserve(n);
+  const auto now = Clock::now();
+  for (int i = 0; i < n; ++i) {
+    const icp_request& q = reqs[i];
+    auto r = std::make_unique<OwnedRequest>();
+    r->P.assign(q.P, q.P + 3 * q.M);
+    r->Q.assign(q.Q, q.Q + 3 * q.N);
+    if (q.params.mode == ICP_P2PL_WELSCH) r->Qn.assign(q.Qn, q.Qn + 3 * q.N);
+    r->M = q.M; r->N = q.N; r->prm = q.params;
+    r->t_submit = now;
+    owned.push_back(std::move(r));
+  }
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->failed) return ICP_ERR_DEVICE;
+    if (ctx->queue.size() + n > kQueueCap) return ICP_ERR_QUEUE_FULL;
+    for (int i = 0; i < n; ++i) {
+      owned[i]->ticket = ctx->next_ticket++;
+      tickets_out[i] = owned[i]->ticket;
+      ctx->state[owned[i]->ticket] = 0;
+      ctx->queue.push_back(std::move(owned[i]));
+    }
+    if (!ctx->started) {
+      ctx->started = true;
+      ctx->worker = std::thread(scheduler, ctx);
+    }
+  }
+  ctx->cv.notify_all();
+  return ICP_OK;
+}
+
+icp_status icp_poll(icp_ctx* ctx, uint64_t ticket, icp_result* out) {
+  if (!ctx) return ICP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->state.find(ticket);
+  if (it == ctx->state.end()) return ICP_ERR_UNKNOWN_TICKET;
+  if (it->second == 0 || it->second == 1) return ctx->failed ? ICP_ERR_DEVICE : ICP_ERR_NOT_READY;
+  const int st = it->second;
+  ctx->state.erase(it);
+  auto r = ctx->results.find(ticket);
+  if (st == 3) { if (r != ctx->results.end()) ctx->results.erase(r); return ICP_ERR_OOM; }
+  if (st == 4) { if (r != ctx->results.end()) ctx->results.erase(r); return ICP_ERR_DEVICE; }
+  if (out && r != ctx->results.end()) *out = r->second;
+  if (r != ctx->results.end()) ctx->results.erase(r);
+  return ICP_OK;
+}
+
+icp_status icp_batch_wait_all(icp_ctx* ctx) {
+  if (!ctx) return ICP_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  ctx->cv_done.wait(lk, [&] { return ctx->failed || (ctx->queue.empty() && ctx->running == 0); });
+  return ctx->failed ? ICP_ERR_DEVICE : ICP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+// Weight-and-reduce pass after the closest-point search: per source point the
+// FP64 residual at the evaluated transform, the Welsch weight and energy term,
+// and the moments of the alignment problem; one fixed-order FP64 partial per
+// 256-source tile (no floating-point atomics, so results do not depend on the
+// batch composition or on scheduling).
+//
+//  point-to-point (eq. WelschAlignment): w = exp(-r^2 / (2 nu^2)) (w = 1 for
+//    L2), energy psi_nu(r) = -expm1(-r^2 / (2 nu^2)) (eq. welsch) or r^2, and
+//    sum w, sum w p~, sum w q~, sum w p~ q~^T with p~, q~ centred by fixed
+//    per-pair bounding-box centres.
+//  point-to-plane (eq. ProxyPointToPlaneAlignment, eq. GNSystem): B = (x - q) . n,
+//    g = exp(-B^2 / (2 nu^2)), J from the per-pass derivative matrices
+//    (App. D), sum g J J^T (upper triangle), sum g B J, sum g, sum psi_nu(B).
+#include "icp_internal.h"
+
+namespace icp {
+
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* out) {
+  __shared__ double s_red[4][32];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double x = v[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    v[i] = x;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s_red[wave][i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int i = threadIdx.x;
+    out[i] = ((s_red[0][i] + s_red[1][i]) + s_red[2][i]) + s_red[3][i];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ descs,
+                                                  const SlotState* __restrict__ states,
+                                                  WorkList* __restrict__ wl) {
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&wl->epi_counter, 1);
+    __syncthreads();
+    const int g = s_item;
+    __syncthreads();
+    if (g >= wl->epi_total) break;
+    int lo = 0, hi = wl->n_active - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (wl->epi_base[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    const int slot = wl->slot[lo];
+    const SlotDesc& D = descs[slot];
+    const SlotState& S = states[slot];
+    const int e = g - wl->epi_base[lo];
+    const int si = e * kEpiTile + threadIdx.x;
+    const bool valid = si < D.M;
+    const double* T = S.Teval;
+
+    int idx = 0;
+    double px = 0, py = 0, pz = 0, dx = 0, dy = 0, dz = 0, qxd = 0, qyd = 0, qzd = 0;
+    if (valid) {
+      if (!S.reuse) {
+        const unsigned long long key = D.keys[si];
+        idx = (int)(unsigned)(key & 0xffffffffull);
+        // every source receives a key from the search; stay in bounds regardless
+        if ((unsigned)idx >= (unsigned)D.N) idx = 0;
+        const float d2 = __uint_as_float((unsigned)(key >> 32));
+        D.nnidx[si] = idx;
+        D.nnd2[si] = d2;
+        if (D.split > 1) D.keys[si] = ~0ull;
+        if (D.idx_out) {
+          const int o = D.perm[si];
+          D.idx_out[o] = idx;
+          D.d2_out[o] = d2;
+        }
+      } else {
+        idx = D.nnidx[si];
+      }
+      px = D.px[si];
+      py = D.py[si];
+      pz = D.pz[si];
+      // FP64 transform with the same fused order as the search, not rounded
+      const double x = __builtin_fma(T[2], pz, __builtin_fma(T[1], py, __builtin_fma(T[0], px, T[3])));
+      const double y = __builtin_fma(T[6], pz, __builtin_fma(T[5], py, __builtin_fma(T[4], px, T[7])));
+      const double z = __builtin_fma(T[10], pz, __builtin_fma(T[9], py, __builtin_fma(T[8], px, T[11])));
+      qxd = D.qx[idx];
+      qyd = D.qy[idx];
+      qzd = D.qz[idx];
+      dx = x - qxd;
+      dy = y - qyd;
+      dz = z - qzd;
+    }
+    double* out = D.part + (size_t)e * kPartStride;
+    const double s = S.inv2nu2;
+    if (D.mode != P2PL_WELSCH) {
+      double v[kP2PVals];
+#pragma unroll
+      for (int i = 0; i < kP2PVals; ++i) v[i] = 0.0;
+      if (valid) {
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        double w = 1.0;
+        if (D.mode == P2P_L2) {
+          v[0] = r2;
+        } else {
+          v[0] = -expm1(-r2 * s);
+          w = exp(-r2 * s);
+        }
+        if (S.want_median) D.medkey[si] = r2;
+        const double a0 = px - S.cP[0], a1 = py - S.cP[1], a2 = pz - S.cP[2];
+        const double b0 = qxd - S.cQ[0], b1 = qyd - S.cQ[1], b2 = qzd - S.cQ[2];
+        v[1] = w;
+        v[2] = w * a0; v[3] = w * a1; v[4] = w * a2;
+        v[5] = w * b0; v[6] = w * b1; v[7] = w * b2;
+        v[8] = v[2] * b0; v[9] = v[2] * b1; v[10] = v[2] * b2;
+        v[11] = v[3] * b0; v[12] = v[3] * b1; v[13] = v[3] * b2;
+        v[14] = v[4] * b0; v[15] = v[4] * b1; v[16] = v[4] * b2;
+      }
+      block_reduce_store<kP2PVals>(v, out);
+    } else {
+      double v[kP2PLVals];
+#pragma unroll
+      for (int i = 0; i < kP2PLVals; ++i) v[i] = 0.0;
+      if (valid) {
+        const double n0 = D.nx[idx], n1 = D.ny[idx], n2 = D.nz[idx];
+        const double B = __builtin_fma(dz, n2, __builtin_fma(dy, n1, dx * n0));
+        const double B2s = B * B * s;
+        const double gam = exp(-B2s);
+        v[0] = -expm1(-B2s);
+        v[1] = gam;
+        if (S.want_median) D.medkey[si] = fabs(B);
+        // J: rotation part n . (dR_j p + dt/d delta_j), translation part (dt/du)^T n
+        const double* K = S.K;
+        double J[6];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const double* R = K + 9 * j;
+          const double r0 = R[0] * px + R[1] * py + R[2] * pz + K[27 + 0 + j];
+          const double r1 = R[3] * px + R[4] * py + R[5] * pz + K[27 + 3 + j];
+          const double r2 = R[6] * px + R[7] * py + R[8] * pz + K[27 + 6 + j];
+          J[j] = n0 * r0 + n1 * r1 + n2 * r2;
+          J[3 + j] = K[36 + j] * n0 + K[36 + 3 + j] * n1 + K[36 + 6 + j] * n2;
+        }
+        int t = 2;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          const double ga = gam * J[a];
+#pragma unroll
+          for (int b = a; b < 6; ++b) v[t++] = ga * J[b];
+        }
+        const double gB = gam * B;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) v[23 + a] = gB * J[a];
+      }
+      block_reduce_store<kP2PLVals>(v, out);
+    }
+  }
+}
+
+void launch_epi(const SlotDesc* descs, const SlotState* states, WorkList* wl, int grid,
+                hipStream_t st) {
+  hipLaunchKernelGGL(epi_kernel, dim3(grid), dim3(256), 0, st, descs, states, wl);
+}
+
+}  // namespace icp

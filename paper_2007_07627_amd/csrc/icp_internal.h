@@ -1,0 +1,140 @@
+// Internal layout shared by the HIP translation units of libicp (never by the
+// oracle). One "slot" is one registration (or one nearest-neighbour query)
+// resident in HBM: its point sets, the cluster index over the target, the
+// per-tile partial sums and the per-pair solver state.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace icp {
+
+constexpr int kTile = 64;        // sources per NN work item (one wavefront)
+constexpr int kCluster = 128;    // targets per cluster of the Morton-ordered index
+constexpr int kChunk = 32;       // targets per deferred-argmin chunk
+constexpr int kChunksPerCluster = kCluster / kChunk;
+constexpr int kSuper = 16;       // clusters per super-cluster (coarse culling level)
+constexpr int kEpiTile = 256;    // sources per reduction work item
+constexpr int kPartStride = 32;  // doubles per reduction partial
+constexpr int kHist = 8;         // Anderson ring capacity (m <= 6 needs m + 1)
+constexpr int kCandCap = 1024;   // LDS candidate list capacity per NN work item
+constexpr int kSupCap = 512;     // LDS candidate super-cluster capacity per NN work item
+constexpr int kMaxSplit = 8;
+
+enum Mode { P2P_L2 = 0, P2P_WELSCH = 1, P2PL_WELSCH = 2 };
+enum NNMethod { NN_AUTO = 0, NN_BRUTE = 1, NN_CLUSTER = 2 };
+enum SlotStatus { ST_FREE = 0, ST_SETUP = 1, ST_RUNNING = 2, ST_DONE = 3 };
+
+// Solver state-machine positions.
+enum SmPos {
+  SM_INIT = 0,         // evaluation at T0 done (setup pass)
+  SM_STAGE_EVAL = 1,   // evaluation at T^(k-1) with the stage's nu
+  SM_ITER_EVAL = 2,    // evaluation at T^(k)
+  SM_REVERT_EVAL = 3,  // point-to-point: evaluation at the un-accelerated T'
+  SM_LS_EVAL = 4,      // point-to-plane: line-search trial
+  SM_QUERY = 5,        // plain nearest-neighbour query: one pass, then done
+  SM_EVAL = 6          // one application of the un-accelerated map, then done
+};
+
+enum Flags : unsigned {
+  F_CONVERGED = 1u, F_MAX_ITER = 2u, F_ZERO_WEIGHT = 4u, F_DEGENERATE = 8u, F_AA_SINGULAR = 16u
+};
+
+// Partial-sum layout (doubles) written per reduction tile.
+// point-to-point: [0]=E [1]=W [2..4]=sum w p~ [5..7]=sum w q~ [8..16]=sum w p~ q~^T
+// point-to-plane: [0]=E [1]=W [2..22]=A upper (row-major i<=j) [23..28]=c
+constexpr int kP2PVals = 17;
+constexpr int kP2PLVals = 29;
+
+// Static description of a slot (written once at admission).
+struct SlotDesc {
+  // sources, Morton-ordered SoA (original FP32 values)
+  const float* px;
+  const float* py;
+  const float* pz;
+  const int* perm;            // sorted position -> original source index
+  const double4* tsph;        // per tile: centre (x,y,z) and radius
+  // targets, original order SoA (+ normals)
+  const float* qx;
+  const float* qy;
+  const float* qz;
+  const float* nx;
+  const float* ny;
+  const float* nz;
+  // cluster index (Morton order, kCluster targets per cluster, padded)
+  const float4* qloc;         // (x - cc, y - cc, z - cc, |q - cc|^2 / 2), padding h = +inf
+  const float4* qorg;         // (x, y, z, bits(original index)), padding index = -1
+  const float4* ccen;         // cluster centre (x, y, z) and radius
+  const float4* clo;          // cluster AABB min
+  const float4* chi;          // cluster AABB max
+  const float4* slo;          // super-cluster AABB min
+  const float4* shi;          // super-cluster AABB max
+  unsigned long long* keys;   // per sorted source: (bits(d2) << 32) | index
+  int32_t* nnidx;             // per sorted source: closest original target index
+  float* nnd2;                // per sorted source: its FP32 squared distance
+  double* part;               // nepi x kPartStride
+  double* medkey;             // per sorted source (setup pass only)
+  int32_t* idx_out;           // optional: original-order outputs (queries)
+  float* d2_out;
+  double* trace;              // optional per-pass rows [E, nu, sm, reuse, T(16)]
+  int trace_cap;
+  int M, N, ntile, ncl, nsup, nepi;
+  int split;                  // target splits per source tile
+  int method;                 // NN_BRUTE or NN_CLUSTER
+  int mode;
+  float rho_max;              // max cluster radius (upper bound)
+};
+
+// Per-slot mutable state (device resident; the solver wave owns it).
+struct SlotState {
+  // ---- evaluation request, read by the NN and reduction kernels
+  double Teval[16];
+  double K[27 + 9 + 9];       // point-to-plane: dR/d delta_j (3x3 x3), dt/d delta, dt/du
+  double inv2nu2;             // 1 / (2 nu^2) of the evaluation (0 for L2)
+  double nu_eval;             // nu of the evaluation (0 for L2)
+  int reuse;                  // 1: same transform as the previous pass, skip the NN search
+  int want_median;            // 1: this pass also writes median keys
+  int status;                 // SlotStatus
+  int sm;                     // SmPos
+  // ---- parameters
+  int mode, m, lmax, iter_first, iter_inc, iter_cap, max_total;
+  int nu_auto;
+  double eps, nu_min, nu_max;
+  // ---- algorithm state
+  int k, kstart, stage, total, Inu, is_aa, ls_l;
+  double nu, Eprev, Eit, tau;
+  double Tk[16], Tp[16], Tkm1[16];
+  double xk[6], xkm1[6], xstar[6], xt[6];
+  double best_prop[6];
+  unsigned best_flags;
+  double G[kHist][6], F[kHist][6];
+  double last_key[16];
+  int have_last;
+  double median;              // written by the median kernel
+  double cP[3], cQ[3];        // fixed centring of the moments (bbox centres)
+  float bbP[6], bbQ[6];       // bounding boxes (min xyz, max xyz)
+  // ---- results
+  double Tres[16];
+  double energy, nu_final;
+  int iterations, nn_passes, evaluations, aa_accepted, aa_rejected, ls_trials, stages;
+  unsigned flags;
+  int phases;
+  int trace_len;
+};
+
+// Active-slot work lists rebuilt before every phase.
+struct WorkList {
+  int n_active;
+  int nn_total;
+  int epi_total;
+  int nn_counter;             // dynamic work counters (reset by the planner)
+  int epi_counter;
+  int pad[3];
+  int slot[1024];             // compacted active slot ids
+  int nn_base[1025];          // prefix of NN items over the compacted list
+  int epi_base[1025];
+};
+
+constexpr int kMaxSlots = 1024;
+constexpr int kTraceRow = 20;
+
+}  // namespace icp

@@ -1,0 +1,409 @@
+// Per-request setup on the device (once per registration, before the
+// iterations): layout conversion, bounding boxes, Morton ordering of both point
+// sets with a stable LSD radix sort, the cluster index over the target
+// (cluster AABBs, centres, radii, centred coordinates) and bounding spheres of
+// the 64-source tiles. Also the planner that rebuilds the active work lists
+// before every pass.
+#include "icp_internal.h"
+
+namespace icp {
+
+// ------------------------------------------------------------------ layout
+
+__global__ void aos_to_soa_kernel(const float* __restrict__ aos, int n, float* __restrict__ x,
+                                  float* __restrict__ y, float* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    x[i] = aos[3 * (size_t)i];
+    y[i] = aos[3 * (size_t)i + 1];
+    z[i] = aos[3 * (size_t)i + 2];
+  }
+}
+
+// Min/max over n points (one block of 1024 threads); writes the box and its
+// FP64 centre.
+__global__ __launch_bounds__(1024) void bbox_kernel(const float* __restrict__ x,
+                                                    const float* __restrict__ y,
+                                                    const float* __restrict__ z, int n,
+                                                    float* __restrict__ box,
+                                                    double* __restrict__ centre) {
+  float mn[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+  float mx[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const float v[3] = {x[i], y[i], z[i]};
+    for (int a = 0; a < 3; ++a) { mn[a] = fminf(mn[a], v[a]); mx[a] = fmaxf(mx[a], v[a]); }
+  }
+  __shared__ float s[6][16];
+  for (int a = 0; a < 3; ++a) {
+    for (int o = 32; o > 0; o >>= 1) {
+      mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+      mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+    }
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0)
+    for (int a = 0; a < 3; ++a) { s[a][w] = mn[a]; s[3 + a][w] = mx[a]; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int a = 0; a < 3; ++a) {
+      float lo = s[a][0], hi = s[3 + a][0];
+      for (int k = 1; k < nw; ++k) { lo = fminf(lo, s[a][k]); hi = fmaxf(hi, s[3 + a][k]); }
+      box[a] = lo;
+      box[3 + a] = hi;
+      if (centre) centre[a] = 0.5 * ((double)lo + (double)hi);
+    }
+  }
+}
+
+__device__ inline unsigned spread10(unsigned v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// 30-bit Morton key of the 1024^3 grid over the bounding box; value = index.
+__global__ void morton_kernel(const float* __restrict__ x, const float* __restrict__ y,
+                              const float* __restrict__ z, int n, const float* __restrict__ box,
+                              unsigned* __restrict__ keys, unsigned* __restrict__ vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float v[3] = {x[i], y[i], z[i]};
+  unsigned c[3];
+  for (int a = 0; a < 3; ++a) {
+    const float ext = box[3 + a] - box[a];
+    float f = ext > 0.0f ? (v[a] - box[a]) / ext * 1024.0f : 0.0f;
+    int q = (int)f;
+    q = q < 0 ? 0 : (q > 1023 ? 1023 : q);
+    c[a] = (unsigned)q;
+  }
+  keys[i] = spread10(c[0]) | (spread10(c[1]) << 1) | (spread10(c[2]) << 2);
+  vals[i] = (unsigned)i;
+}
+
+// ------------------------------------------------------------------ radix sort
+// Stable LSD sort of (32-bit key, 32-bit value) pairs, 8 bits per pass. Each
+// block (one wavefront) owns a contiguous chunk of kSortChunk elements and
+// ranks them in order, 64 at a time, so equal keys keep their input order.
+
+constexpr int kSortChunk = 2048;
+
+__global__ __launch_bounds__(64) void rs_hist_kernel(const unsigned* __restrict__ keys, int n,
+                                                     int shift, int nblocks,
+                                                     unsigned* __restrict__ hist) {
+  __shared__ unsigned h[256];
+  for (int i = threadIdx.x; i < 256; i += 64) h[i] = 0u;
+  __syncthreads();
+  const int base = blockIdx.x * kSortChunk;
+  for (int s = 0; s < kSortChunk; s += 64) {
+    const int e = base + s + threadIdx.x;
+    if (e < n) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += 64) hist[(size_t)i * nblocks + blockIdx.x] = h[i];
+}
+
+// Exclusive scan of the digit-major histogram (single block of 1024 threads).
+__global__ __launch_bounds__(1024) void rs_scan_kernel(unsigned* __restrict__ hist, int total) {
+  __shared__ unsigned s[1024];
+  const int per = (total + 1023) / 1024;
+  const int b = threadIdx.x * per;
+  unsigned sum = 0;
+  for (int i = 0; i < per; ++i)
+    if (b + i < total) sum += hist[b + i];
+  s[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const unsigned v = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += v;
+    __syncthreads();
+  }
+  unsigned run = s[threadIdx.x] - sum;
+  for (int i = 0; i < per; ++i)
+    if (b + i < total) {
+      const unsigned v = hist[b + i];
+      hist[b + i] = run;
+      run += v;
+    }
+}
+
+__global__ __launch_bounds__(64) void rs_scatter_kernel(const unsigned* __restrict__ kin,
+                                                        const unsigned* __restrict__ vin, int n,
+                                                        int shift, int nblocks,
+                                                        const unsigned* __restrict__ hist,
+                                                        unsigned* __restrict__ kout,
+                                                        unsigned* __restrict__ vout) {
+  __shared__ unsigned cnt[256];
+  for (int i = threadIdx.x; i < 256; i += 64) cnt[i] = hist[(size_t)i * nblocks + blockIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const int base = blockIdx.x * kSortChunk;
+  for (int s = 0; s < kSortChunk; s += 64) {
+    const int e = base + s + lane;
+    const bool valid = e < n;
+    unsigned k = 0, v = 0, d = 0;
+    if (valid) {
+      k = kin[e];
+      v = vin[e];
+      d = (k >> shift) & 255u;
+    }
+    unsigned long long m = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const unsigned long long bb = __ballot(valid && bit);
+      m &= bit ? bb : ~bb;
+    }
+    const unsigned rank = (unsigned)__popcll(m & lt);
+    unsigned pos = 0;
+    if (valid) pos = cnt[d] + rank;
+    __syncthreads();
+    if (valid && rank == 0) cnt[d] += (unsigned)__popcll(m);
+    __syncthreads();
+    if (valid) {
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ cluster index
+
+// One wavefront per cluster of kCluster sorted targets.
+__global__ __launch_bounds__(64) void build_clusters_kernel(
+    const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+    const unsigned* __restrict__ order, int n, int ncl, float4* __restrict__ qloc,
+    float4* __restrict__ qorg, float4* __restrict__ ccen, float4* __restrict__ clo,
+    float4* __restrict__ chi) {
+  const int c = blockIdx.x;
+  if (c >= ncl) return;
+  const int lane = threadIdx.x;
+  float p[2][3];
+  int id[2];
+  float mn[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+  float mx[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+  for (int r = 0; r < 2; ++r) {
+    const int pos = c * kCluster + r * 64 + lane;
+    id[r] = pos < n ? (int)order[pos] : -1;
+    if (id[r] >= 0) {
+      p[r][0] = x[id[r]];
+      p[r][1] = y[id[r]];
+      p[r][2] = z[id[r]];
+      for (int a = 0; a < 3; ++a) { mn[a] = fminf(mn[a], p[r][a]); mx[a] = fmaxf(mx[a], p[r][a]); }
+    } else {
+      p[r][0] = p[r][1] = p[r][2] = 0.0f;
+    }
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int o = 32; o > 0; o >>= 1) {
+      mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+      mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+    }
+  const float cc[3] = {0.5f * (mn[0] + mx[0]), 0.5f * (mn[1] + mx[1]), 0.5f * (mn[2] + mx[2])};
+  double rmax = 0.0;
+  for (int r = 0; r < 2; ++r) {
+    const int pos = c * kCluster + r * 64 + lane;
+    if (id[r] >= 0) {
+      const double ex = (double)p[r][0] - cc[0], ey = (double)p[r][1] - cc[1],
+                   ez = (double)p[r][2] - cc[2];
+      rmax = fmax(rmax, sqrt(ex * ex + ey * ey + ez * ez));
+      const float lx = p[r][0] - cc[0], ly = p[r][1] - cc[1], lz = p[r][2] - cc[2];
+      const double h = 0.5 * ((double)lx * lx + (double)ly * ly + (double)lz * lz);
+      qloc[pos] = make_float4(lx, ly, lz, (float)h);
+      qorg[pos] = make_float4(p[r][0], p[r][1], p[r][2], __int_as_float(id[r]));
+    } else {
+      qloc[pos] = make_float4(0.0f, 0.0f, 0.0f, __builtin_inff());
+      qorg[pos] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
+  if (lane == 0) {
+    // radius rounded up so that it bounds |q - cc| for every member
+    ccen[c] = make_float4(cc[0], cc[1], cc[2], (float)(rmax * (1.0 + 1e-6)) + 1e-30f);
+    clo[c] = make_float4(mn[0], mn[1], mn[2], 0.0f);
+    chi[c] = make_float4(mx[0], mx[1], mx[2], 0.0f);
+  }
+}
+
+// Super-cluster boxes and the maximum cluster radius (one block of 64).
+__global__ __launch_bounds__(64) void build_super_kernel(const float4* __restrict__ clo,
+                                                         const float4* __restrict__ chi,
+                                                         const float4* __restrict__ ccen, int ncl,
+                                                         int nsup, float4* __restrict__ slo,
+                                                         float4* __restrict__ shi,
+                                                         float* __restrict__ rho_out) {
+  float rmax = 0.0f;
+  for (int s = threadIdx.x; s < nsup; s += 64) {
+    float4 lo = make_float4(__builtin_inff(), __builtin_inff(), __builtin_inff(), 0.f);
+    float4 hi = make_float4(-__builtin_inff(), -__builtin_inff(), -__builtin_inff(), 0.f);
+    for (int c = s * kSuper; c < min(ncl, (s + 1) * kSuper); ++c) {
+      lo.x = fminf(lo.x, clo[c].x); lo.y = fminf(lo.y, clo[c].y); lo.z = fminf(lo.z, clo[c].z);
+      hi.x = fmaxf(hi.x, chi[c].x); hi.y = fmaxf(hi.y, chi[c].y); hi.z = fmaxf(hi.z, chi[c].z);
+      rmax = fmaxf(rmax, ccen[c].w);
+    }
+    slo[s] = lo;
+    shi[s] = hi;
+  }
+  for (int o = 32; o > 0; o >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, o, 64));
+  if (threadIdx.x == 0) *rho_out = rmax;
+}
+
+// Sorted source copy and the bounding sphere of each 64-source tile.
+__global__ __launch_bounds__(64) void build_tiles_kernel(
+    const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+    const unsigned* __restrict__ order, int m, int ntile, float* __restrict__ sx,
+    float* __restrict__ sy, float* __restrict__ sz, int* __restrict__ perm,
+    double4* __restrict__ tsph) {
+  const int t = blockIdx.x;
+  if (t >= ntile) return;
+  const int pos = t * kTile + threadIdx.x;
+  const bool valid = pos < m;
+  float p[3] = {0.f, 0.f, 0.f};
+  float mn[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+  float mx[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+  if (valid) {
+    const int o = (int)order[pos];
+    p[0] = x[o]; p[1] = y[o]; p[2] = z[o];
+    sx[pos] = p[0]; sy[pos] = p[1]; sz[pos] = p[2];
+    perm[pos] = o;
+    for (int a = 0; a < 3; ++a) { mn[a] = p[a]; mx[a] = p[a]; }
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int o = 32; o > 0; o >>= 1) {
+      mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, 64));
+      mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, 64));
+    }
+  const double c[3] = {0.5 * ((double)mn[0] + mx[0]), 0.5 * ((double)mn[1] + mx[1]),
+                       0.5 * ((double)mn[2] + mx[2])};
+  double r = 0.0;
+  if (valid) {
+    const double ex = p[0] - c[0], ey = p[1] - c[1], ez = p[2] - c[2];
+    r = sqrt(ex * ex + ey * ey + ez * ez);
+  }
+  for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
+  if (threadIdx.x == 0) tsph[t] = make_double4(c[0], c[1], c[2], r * (1.0 + 1e-9) + 1e-300);
+}
+
+__global__ void fill_u64_kernel(unsigned long long* __restrict__ p, int n, unsigned long long v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ planner
+
+// Rebuild the compacted list of RUNNING slots and the prefix sums of their
+// closest-point and reduction work items; reset the dynamic work counters.
+__global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__ descs,
+                                                    const SlotState* __restrict__ states,
+                                                    WorkList* __restrict__ wl, int capacity) {
+  __shared__ int s_act[1024], s_nn[1024], s_epi[1024];
+  const int t = threadIdx.x;
+  int act = 0, nn = 0, ep = 0;
+  if (t < capacity && states[t].status == ST_RUNNING) {
+    act = 1;
+    nn = states[t].reuse ? 0 : descs[t].ntile * descs[t].split;
+    ep = descs[t].nepi;
+  }
+  s_act[t] = act; s_nn[t] = nn; s_epi[t] = ep;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int a = 0, b = 0, c = 0;
+    if (t >= o) { a = s_act[t - o]; b = s_nn[t - o]; c = s_epi[t - o]; }
+    __syncthreads();
+    s_act[t] += a; s_nn[t] += b; s_epi[t] += c;
+    __syncthreads();
+  }
+  if (act) {
+    const int pos = s_act[t] - 1;
+    wl->slot[pos] = t;
+    wl->nn_base[pos] = s_nn[t] - nn;
+    wl->epi_base[pos] = s_epi[t] - ep;
+  }
+  if (t == 1023) {
+    wl->n_active = s_act[t];
+    wl->nn_total = s_nn[t];
+    wl->epi_total = s_epi[t];
+    wl->nn_base[s_act[t]] = s_nn[t];
+    wl->epi_base[s_act[t]] = s_epi[t];
+    wl->nn_counter = 0;
+    wl->epi_counter = 0;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+void launch_aos_to_soa(const float* aos, int n, float* x, float* y, float* z, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(aos_to_soa_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, aos, n, x, y, z);
+}
+
+void launch_bbox(const float* x, const float* y, const float* z, int n, float* box,
+                 double* centre, hipStream_t st) {
+  hipLaunchKernelGGL(bbox_kernel, dim3(1), dim3(1024), 0, st, x, y, z, n, box, centre);
+}
+
+size_t sort_scratch_words(int n) {
+  const int nb = cdiv(n > 0 ? n : 1, kSortChunk);
+  return (size_t)4 * n + (size_t)256 * nb + 64;
+}
+
+// Morton order of n points: returns (through out_vals) the permutation sorted
+// by (cell key, original index). scratch: sort_scratch_words(n) unsigned words.
+void launch_morton_order(const float* x, const float* y, const float* z, int n, const float* box,
+                         unsigned* scratch, unsigned** out_vals, hipStream_t st) {
+  unsigned* ka = scratch;
+  unsigned* va = ka + n;
+  unsigned* kb = va + n;
+  unsigned* vb = kb + n;
+  unsigned* hist = vb + n;
+  const int nb = cdiv(n, kSortChunk);
+  hipLaunchKernelGGL(morton_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, x, y, z, n, box, ka, va);
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 8 * pass;
+    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(64), 0, st, ka, n, shift, nb, hist);
+    hipLaunchKernelGGL(rs_scan_kernel, dim3(1), dim3(1024), 0, st, hist, 256 * nb);
+    hipLaunchKernelGGL(rs_scatter_kernel, dim3(nb), dim3(64), 0, st, ka, va, n, shift, nb, hist, kb,
+                       vb);
+    unsigned* t = ka; ka = kb; kb = t;
+    t = va; va = vb; vb = t;
+  }
+  *out_vals = va;
+}
+
+void launch_build_clusters(const float* x, const float* y, const float* z, const unsigned* order,
+                           int n, int ncl, float4* qloc, float4* qorg, float4* ccen, float4* clo,
+                           float4* chi, hipStream_t st) {
+  hipLaunchKernelGGL(build_clusters_kernel, dim3(ncl), dim3(64), 0, st, x, y, z, order, n, ncl, qloc,
+                     qorg, ccen, clo, chi);
+}
+
+void launch_build_super(const float4* clo, const float4* chi, const float4* ccen, int ncl, int nsup,
+                        float4* slo, float4* shi, float* rho_out, hipStream_t st) {
+  hipLaunchKernelGGL(build_super_kernel, dim3(1), dim3(64), 0, st, clo, chi, ccen, ncl, nsup, slo, shi,
+                     rho_out);
+}
+
+void launch_build_tiles(const float* x, const float* y, const float* z, const unsigned* order, int m,
+                        int ntile, float* sx, float* sy, float* sz, int* perm, double4* tsph,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(build_tiles_kernel, dim3(ntile), dim3(64), 0, st, x, y, z, order, m, ntile, sx, sy,
+                     sz, perm, tsph);
+}
+
+void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n, v);
+}
+
+void launch_plan(const SlotDesc* descs, const SlotState* states, WorkList* wl, int capacity,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl, capacity);
+}
+
+}  // namespace icp

@@ -1,0 +1,859 @@
+// Per-pair FP64 solver wavefront: merges the reduction partials in a fixed
+// order, then advances Algorithm 1 (robust point-to-point, and Fast ICP as its
+// L2 case) or Algorithm 2 (robust point-to-plane) by one step. Every step ends
+// with a request "evaluate at transform T with parameter nu" that the next
+// closest-point + reduction pass serves, so control never leaves the device.
+//
+// Readings of the paper (where it is silent, ambiguous or garbled):
+//  - F^(k) = G(x^(k)) - x^(k); the Anderson sums run over m_k columns.
+//  - Stage convergence ||T^(k) - T'||_F < eps (point-to-point, 4x4) and
+//    ||xi*^(k+1) - xi^(k)|| < eps (point-to-plane); not squared.
+//  - Anderson metric: Frobenius of the 4x4 logarithm (rotation part x2) for
+//    point-to-point, Euclidean for point-to-plane; Algorithm 2 applies no
+//    exponential to the mixed vector.
+//  - Gauss-Newton: xi* = xi - A^{-1} sum g B J (the sign that decreases the
+//    linearised objective of eq. GNSystem).
+//  - Line search: tau halves after each trial, at most l_max trials, the
+//    lowest-energy trial is kept.
+//  - A safeguard rejection keeps the Anderson history.
+//  - Zero total weight or a singular 6x6 system ends the registration with a
+//    flag and the current transform.
+#include "icp_internal.h"
+
+namespace icp {
+
+// ------------------------------------------------------------------ FP64 math
+
+__device__ inline void skew(const double a[3], double W[9]) {
+  W[0] = 0.0;   W[1] = -a[2]; W[2] = a[1];
+  W[3] = a[2];  W[4] = 0.0;   W[5] = -a[0];
+  W[6] = -a[1]; W[7] = a[0];  W[8] = 0.0;
+}
+
+__device__ inline void mm3(const double A[9], const double B[9], double C[9]) {
+  double t[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      t[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+  for (int i = 0; i < 9; ++i) C[i] = t[i];
+}
+
+__device__ inline void mv3(const double A[9], const double x[3], double y[3]) {
+  const double a = A[0] * x[0] + A[1] * x[1] + A[2] * x[2];
+  const double b = A[3] * x[0] + A[4] * x[1] + A[5] * x[2];
+  const double c = A[6] * x[0] + A[7] * x[1] + A[8] * x[2];
+  y[0] = a; y[1] = b; y[2] = c;
+}
+
+// Coefficients of the Rodrigues-type series and their theta-derivatives over
+// theta:  A = sin/t, B = (1-cos)/t^2, C = (t-sin)/t^3, Ad = A'/t, Bd = B'/t,
+// Cd = C'/t. Closed forms for t >= 0.3, Taylor series below.
+struct Coef { double A, B, C, Ad, Bd, Cd; };
+
+__device__ inline Coef coeffs(double t) {
+  Coef k;
+  const double t2 = t * t;
+  if (t < 0.3) {
+    const double t4 = t2 * t2, t6 = t4 * t2, t8 = t4 * t4, t10 = t8 * t2;
+    k.A = 1.0 - t2 / 6.0 + t4 / 120.0 - t6 / 5040.0 + t8 / 362880.0 - t10 / 39916800.0;
+    k.B = 0.5 - t2 / 24.0 + t4 / 720.0 - t6 / 40320.0 + t8 / 3628800.0 - t10 / 479001600.0;
+    k.C = 1.0 / 6.0 - t2 / 120.0 + t4 / 5040.0 - t6 / 362880.0 + t8 / 39916800.0 - t10 / 6227020800.0;
+    k.Ad = -1.0 / 3.0 + t2 / 30.0 - t4 / 840.0 + t6 / 45360.0 - t8 / 3991680.0;
+    k.Bd = -1.0 / 12.0 + t2 / 180.0 - t4 / 6720.0 + t6 / 453600.0 - t8 / 47900160.0;
+    k.Cd = -1.0 / 60.0 + t2 / 1260.0 - t4 / 60480.0 + t6 / 4989600.0 - t8 / 622702080.0;
+  } else {
+    const double s = sin(t), c = cos(t), h = sin(0.5 * t);
+    const double omc = 2.0 * h * h;  // 1 - cos t
+    k.A = s / t;
+    k.B = omc / t2;
+    k.C = (t - s) / (t2 * t);
+    k.Ad = (t * c - s) / (t2 * t);
+    k.Bd = (t * s - 2.0 * omc) / (t2 * t2);
+    k.Cd = (omc * t - 3.0 * (t - s)) / (t2 * t2 * t);
+  }
+  return k;
+}
+
+// exp of the twist xi = (delta, u): R = I + A W + B W^2, t = (I + B W + C W^2) u.
+__device__ void twist_exp(const double xi[6], double T[16]) {
+  const double th = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+  const Coef k = coeffs(th);
+  double W[9], W2[9];
+  skew(xi, W);
+  mm3(W, W, W2);
+  double V[9];
+  for (int i = 0; i < 9; ++i) {
+    const double I = (i % 4 == 0) ? 1.0 : 0.0;
+    const double r = I + k.A * W[i] + k.B * W2[i];
+    T[4 * (i / 3) + (i % 3)] = r;
+    V[i] = I + k.B * W[i] + k.C * W2[i];
+  }
+  double t[3];
+  mv3(V, xi + 3, t);
+  T[3] = t[0]; T[7] = t[1]; T[11] = t[2];
+  T[12] = 0.0; T[13] = 0.0; T[14] = 0.0; T[15] = 1.0;
+}
+
+// Principal logarithm (angle in [0, pi], Appendix A): the rotation vector from
+// the skew part (or, near pi, from the symmetric part), u = V^{-1} t.
+__device__ void twist_log(const double T[16], double xi[6]) {
+  const double R[9] = {T[0], T[1], T[2], T[4], T[5], T[6], T[8], T[9], T[10]};
+  const double v[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};
+  const double sn = 0.5 * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const double cs = fmin(1.0, fmax(-1.0, 0.5 * (R[0] + R[4] + R[8] - 1.0)));
+  const double th = atan2(sn, cs);
+  double d[3];
+  if (th < 3.0) {
+    // theta / (2 sin theta): series below 0.2
+    double f;
+    if (th < 0.2) {
+      const double t2 = th * th;
+      f = 0.5 + t2 / 12.0 + 7.0 * t2 * t2 / 720.0 + 31.0 * t2 * t2 * t2 / 30240.0;
+    } else {
+      f = th / (2.0 * sin(th));
+    }
+    d[0] = f * v[0]; d[1] = f * v[1]; d[2] = f * v[2];
+  } else {
+    const double oc = 1.0 - cs;
+    double S[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        S[3 * i + j] = (0.5 * (R[3 * i + j] + R[3 * j + i]) - (i == j ? cs : 0.0)) / oc;
+    int kk = 0;
+    if (S[4] > S[0]) kk = 1;
+    if (S[8] > S[4 * kk]) kk = 2;
+    double a[3] = {S[3 * kk], S[3 * kk + 1], S[3 * kk + 2]};
+    const double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    a[0] /= na; a[1] /= na; a[2] /= na;
+    const double sg = a[0] * v[0] + a[1] * v[1] + a[2] * v[2];
+    if (sg < 0.0 || (sg == 0.0 && a[kk] < 0.0)) { a[0] = -a[0]; a[1] = -a[1]; a[2] = -a[2]; }
+    d[0] = th * a[0]; d[1] = th * a[1]; d[2] = th * a[2];
+  }
+  double g;
+  if (th < 0.2) {
+    const double t2 = th * th;
+    g = 1.0 / 12.0 + t2 / 720.0 + t2 * t2 / 30240.0 + t2 * t2 * t2 / 1209600.0 +
+        t2 * t2 * t2 * t2 / 47900160.0;
+  } else {
+    const double h = sin(0.5 * th);
+    g = (1.0 - th * sin(th) / (4.0 * h * h)) / (th * th);
+  }
+  double W[9], W2[9];
+  skew(d, W);
+  mm3(W, W, W2);
+  const double t[3] = {T[3], T[7], T[11]};
+  double Vi[9];
+  for (int i = 0; i < 9; ++i) Vi[i] = ((i % 4 == 0) ? 1.0 : 0.0) - 0.5 * W[i] + g * W2[i];
+  double u[3];
+  mv3(Vi, t, u);
+  xi[0] = d[0]; xi[1] = d[1]; xi[2] = d[2];
+  xi[3] = u[0]; xi[4] = u[1]; xi[5] = u[2];
+}
+
+// Derivatives of R(delta) and t = V(delta) u at xi (the gradient of App. D):
+// K[0..26]  dR/d delta_j = A E_j + B (E_j W + W E_j) + Ad d_j W + Bd d_j W^2
+// K[27..35] dt/d delta (column j) = [B E_j + C (E_j W + W E_j) + Bd d_j W + Cd d_j W^2] u
+// K[36..44] dt/du = I + B W + C W^2
+__device__ void twist_derivs(const double xi[6], double K[45]) {
+  const double* d = xi;
+  const double* u = xi + 3;
+  const double th = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const Coef k = coeffs(th);
+  double W[9], W2[9];
+  skew(d, W);
+  mm3(W, W, W2);
+  double Wu[3], W2u[3];
+  mv3(W, u, Wu);
+  mv3(W2, u, W2u);
+  for (int j = 0; j < 3; ++j) {
+    double e[3] = {0.0, 0.0, 0.0};
+    e[j] = 1.0;
+    double E[9], EW[9], WE[9];
+    skew(e, E);
+    mm3(E, W, EW);
+    mm3(W, E, WE);
+    for (int i = 0; i < 9; ++i)
+      K[9 * j + i] = k.A * E[i] + k.B * (EW[i] + WE[i]) + k.Ad * d[j] * W[i] + k.Bd * d[j] * W2[i];
+    double S[9];
+    for (int i = 0; i < 9; ++i) S[i] = k.B * E[i] + k.C * (EW[i] + WE[i]);
+    double Su[3];
+    mv3(S, u, Su);
+    for (int a = 0; a < 3; ++a) K[27 + 3 * a + j] = Su[a] + k.Bd * d[j] * Wu[a] + k.Cd * d[j] * W2u[a];
+  }
+  for (int i = 0; i < 9; ++i) K[36 + i] = ((i % 4 == 0) ? 1.0 : 0.0) + k.B * W[i] + k.C * W2[i];
+}
+
+// Symmetric 4x4 eigen-decomposition by cyclic Jacobi rotations; returns the
+// unit eigenvector of the largest eigenvalue and the two largest eigenvalues.
+__device__ void sym4_top(double A[16], double q[4], double& l0, double& l1) {
+  double V[16];
+  for (int i = 0; i < 16; ++i) V[i] = (i % 5 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        tot += A[4 * i + j] * A[4 * i + j];
+        if (i != j) off += A[4 * i + j] * A[4 * i + j];
+      }
+    if (off <= 1e-32 * tot || off == 0.0) break;
+    for (int p = 0; p < 3; ++p)
+      for (int r = p + 1; r < 4; ++r) {
+        const double apr = A[4 * p + r];
+        if (apr == 0.0) continue;
+        const double theta = (A[4 * r + r] - A[4 * p + p]) / (2.0 * apr);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int kk = 0; kk < 4; ++kk) {
+          const double akp = A[4 * kk + p], akr = A[4 * kk + r];
+          A[4 * kk + p] = c * akp - s * akr;
+          A[4 * kk + r] = s * akp + c * akr;
+        }
+        for (int kk = 0; kk < 4; ++kk) {
+          const double apk = A[4 * p + kk], ark = A[4 * r + kk];
+          A[4 * p + kk] = c * apk - s * ark;
+          A[4 * r + kk] = s * apk + c * ark;
+        }
+        for (int kk = 0; kk < 4; ++kk) {
+          const double vkp = V[4 * kk + p], vkr = V[4 * kk + r];
+          V[4 * kk + p] = c * vkp - s * vkr;
+          V[4 * kk + r] = s * vkp + c * vkr;
+        }
+      }
+  }
+  int b0 = 0;
+  for (int i = 1; i < 4; ++i) if (A[5 * i] > A[5 * b0]) b0 = i;
+  int b1 = b0 == 0 ? 1 : 0;
+  for (int i = 0; i < 4; ++i) if (i != b0 && A[5 * i] > A[5 * b1]) b1 = i;
+  l0 = A[5 * b0];
+  l1 = A[5 * b1];
+  for (int i = 0; i < 4; ++i) q[i] = V[4 * i + b0];
+}
+
+// Weighted absolute orientation from the merged moments by Horn's unit-
+// quaternion method (the optimum of eq. WelschAlignment over rotations):
+// S = sum w (p - pb)(q - qb)^T, the quaternion is the top eigenvector of the
+// symmetric 4x4 matrix built from S; t = qb - R pb.
+__device__ unsigned align_p2p(const double* mom, const double cP[3], const double cQ[3],
+                              double T[16]) {
+  const double W = mom[1];
+  if (!(W > 1e-300)) return F_ZERO_WEIGHT;
+  const double pb[3] = {mom[2] / W, mom[3] / W, mom[4] / W};
+  const double qb[3] = {mom[5] / W, mom[6] / W, mom[7] / W};
+  double S[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) S[3 * a + b] = mom[8 + 3 * a + b] - mom[2 + a] * mom[5 + b] / W;
+  const double Sxx = S[0], Sxy = S[1], Sxz = S[2], Syx = S[3], Syy = S[4], Syz = S[5],
+               Szx = S[6], Szy = S[7], Szz = S[8];
+  double N[16] = {Sxx + Syy + Szz, Syz - Szy,        Szx - Sxz,        Sxy - Syx,
+                  Syz - Szy,       Sxx - Syy - Szz,  Sxy + Syx,        Szx + Sxz,
+                  Szx - Sxz,       Sxy + Syx,        -Sxx + Syy - Szz, Syz + Szy,
+                  Sxy - Syx,       Szx + Sxz,        Syz + Szy,        -Sxx - Syy + Szz};
+  double q[4], l0, l1;
+  sym4_top(N, q, l0, l1);
+  unsigned flags = 0;
+  // rank test on S through S^T S (singular values squared)
+  {
+    double M[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        M[3 * i + j] = S[i] * S[j] + S[3 + i] * S[3 + j] + S[6 + i] * S[6 + j];
+    // eigenvalues of the symmetric 3x3 via the 4x4 routine on a padded matrix
+    double P[16] = {M[0], M[1], M[2], 0, M[3], M[4], M[5], 0, M[6], M[7], M[8], 0, 0, 0, 0, -1.0};
+    double qq[4], e0, e1;
+    sym4_top(P, qq, e0, e1);
+    if (!(e1 > 1e-24 * e0)) flags |= F_DEGENERATE;
+  }
+  const double q0 = q[0], qx = q[1], qy = q[2], qz = q[3];
+  double R[9] = {q0 * q0 + qx * qx - qy * qy - qz * qz, 2.0 * (qx * qy - q0 * qz), 2.0 * (qx * qz + q0 * qy),
+                 2.0 * (qy * qx + q0 * qz), q0 * q0 - qx * qx + qy * qy - qz * qz, 2.0 * (qy * qz - q0 * qx),
+                 2.0 * (qz * qx - q0 * qy), 2.0 * (qz * qy + q0 * qx), q0 * q0 - qx * qx - qy * qy + qz * qz};
+  const double pbar[3] = {cP[0] + pb[0], cP[1] + pb[1], cP[2] + pb[2]};
+  const double qbar[3] = {cQ[0] + qb[0], cQ[1] + qb[1], cQ[2] + qb[2]};
+  double Rp[3];
+  mv3(R, pbar, Rp);
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) T[4 * i + j] = R[3 * i + j];
+    T[4 * i + 3] = qbar[i] - Rp[i];
+  }
+  T[12] = 0.0; T[13] = 0.0; T[14] = 0.0; T[15] = 1.0;
+  return flags;
+}
+
+// Gauss-Newton candidate xi* = xi - A^{-1} c by Cholesky (eq. GNSystem).
+__device__ unsigned gn_p2pl(const double* mom, const double xi[6], double out[6]) {
+  for (int a = 0; a < 6; ++a) out[a] = xi[a];
+  if (!(mom[1] > 1e-300)) return F_ZERO_WEIGHT;
+  double A[36];
+  int t = 2;
+  for (int a = 0; a < 6; ++a)
+    for (int b = a; b < 6; ++b) { A[6 * a + b] = mom[t]; A[6 * b + a] = mom[t]; ++t; }
+  double dmax = 0.0;
+  for (int a = 0; a < 6; ++a) dmax = fmax(dmax, A[7 * a]);
+  if (!(dmax > 0.0)) return F_DEGENERATE;
+  double L[36];
+  for (int i = 0; i < 36; ++i) L[i] = 0.0;
+  for (int j = 0; j < 6; ++j) {
+    double s = A[7 * j];
+    for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
+    if (!(s > 1e-14 * dmax)) return F_DEGENERATE;
+    L[7 * j] = sqrt(s);
+    for (int i = j + 1; i < 6; ++i) {
+      double v = A[6 * i + j];
+      for (int k = 0; k < j; ++k) v -= L[6 * i + k] * L[6 * j + k];
+      L[6 * i + j] = v / L[7 * j];
+    }
+  }
+  double y[6], x[6];
+  for (int i = 0; i < 6; ++i) {
+    double v = mom[23 + i];
+    for (int k = 0; k < i; ++k) v -= L[6 * i + k] * y[k];
+    y[i] = v / L[7 * i];
+  }
+  for (int i = 5; i >= 0; --i) {
+    double v = y[i];
+    for (int k = i + 1; k < 6; ++k) v -= L[6 * k + i] * x[k];
+    x[i] = v / L[7 * i];
+  }
+  for (int a = 0; a < 6; ++a) out[a] = xi[a] - x[a];
+  return 0;
+}
+
+// Anderson mixing: theta = argmin || F^k - sum_j theta_j dF_j ||^2 in the given
+// metric by normal equations (Cholesky, pivot <= 1e-10 max diag = singular,
+// theta = 0); returns G^k - sum_j theta_j dG_j.
+__device__ bool anderson(const SlotState& S, int k, int mk, int metric, double out[6]) {
+  double dF[6][6], dG[6][6];
+  for (int j = 1; j <= mk; ++j)
+    for (int a = 0; a < 6; ++a) {
+      dF[j - 1][a] = S.F[(k - j + 1) % kHist][a] - S.F[(k - j) % kHist][a];
+      dG[j - 1][a] = S.G[(k - j + 1) % kHist][a] - S.G[(k - j) % kHist][a];
+    }
+  const double* Fk = S.F[k % kHist];
+  const double wr = metric == 0 ? 2.0 : 1.0;
+  double N[36], r[6], dmax = 0.0;
+  for (int i = 0; i < mk; ++i) {
+    r[i] = wr * (dF[i][0] * Fk[0] + dF[i][1] * Fk[1] + dF[i][2] * Fk[2]) + dF[i][3] * Fk[3] +
+           dF[i][4] * Fk[4] + dF[i][5] * Fk[5];
+    for (int j = 0; j < mk; ++j)
+      N[6 * i + j] = wr * (dF[i][0] * dF[j][0] + dF[i][1] * dF[j][1] + dF[i][2] * dF[j][2]) +
+                     dF[i][3] * dF[j][3] + dF[i][4] * dF[j][4] + dF[i][5] * dF[j][5];
+    dmax = fmax(dmax, N[7 * i]);
+  }
+  double L[36], th[6];
+  for (int i = 0; i < 36; ++i) L[i] = 0.0;
+  bool sing = !(dmax > 0.0);
+  for (int j = 0; j < mk && !sing; ++j) {
+    double s = N[7 * j];
+    for (int kk = 0; kk < j; ++kk) s -= L[6 * j + kk] * L[6 * j + kk];
+    if (!(s > 1e-10 * dmax)) { sing = true; break; }
+    L[7 * j] = sqrt(s);
+    for (int i = j + 1; i < mk; ++i) {
+      double v = N[6 * i + j];
+      for (int kk = 0; kk < j; ++kk) v -= L[6 * i + kk] * L[6 * j + kk];
+      L[6 * i + j] = v / L[7 * j];
+    }
+  }
+  if (sing) {
+    for (int i = 0; i < mk; ++i) th[i] = 0.0;
+  } else {
+    double y[6];
+    for (int i = 0; i < mk; ++i) {
+      double v = r[i];
+      for (int kk = 0; kk < i; ++kk) v -= L[6 * i + kk] * y[kk];
+      y[i] = v / L[7 * i];
+    }
+    for (int i = mk - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int kk = i + 1; kk < mk; ++kk) v -= L[6 * kk + i] * th[kk];
+      th[i] = v / L[7 * i];
+    }
+  }
+  for (int a = 0; a < 6; ++a) {
+    double v = S.G[k % kHist][a];
+    for (int j = 1; j <= mk; ++j) v -= th[j - 1] * dG[j - 1][a];
+    out[a] = v;
+  }
+  return sing;
+}
+
+// ------------------------------------------------------------------ requests
+
+__device__ inline bool same_bits(const double* a, const double* b, int n) {
+  for (int i = 0; i < n; ++i)
+    if (__double_as_longlong(a[i]) != __double_as_longlong(b[i])) return false;
+  return true;
+}
+
+__device__ inline void set_nu(SlotState& S, double nu) {
+  S.inv2nu2 = S.mode == P2P_L2 ? 0.0 : 1.0 / (2.0 * nu * nu);
+  S.nu_eval = S.mode == P2P_L2 ? 0.0 : nu;
+}
+
+__device__ void request_T(SlotState& S, const double T[16], double nu) {
+  S.evaluations++;
+  const bool same = S.have_last && same_bits(S.last_key, T, 16);
+  S.reuse = same ? 1 : 0;
+  if (!same) {
+    for (int i = 0; i < 16; ++i) S.last_key[i] = T[i];
+    S.have_last = 1;
+    S.nn_passes++;
+  }
+  for (int i = 0; i < 16; ++i) S.Teval[i] = T[i];
+  set_nu(S, nu);
+}
+
+__device__ void request_xi(SlotState& S, const double xi[6], double nu) {
+  S.evaluations++;
+  const bool same = S.have_last && same_bits(S.last_key, xi, 6);
+  S.reuse = same ? 1 : 0;
+  if (!same) {
+    for (int i = 0; i < 6; ++i) S.last_key[i] = xi[i];
+    S.have_last = 1;
+    S.nn_passes++;
+  }
+  twist_exp(xi, S.Teval);
+  twist_derivs(xi, S.K);
+  set_nu(S, nu);
+}
+
+__device__ void finish(SlotState& S, const double T[16], double E) {
+  for (int i = 0; i < 16; ++i) S.Tres[i] = T[i];
+  S.energy = E;
+  S.nu_final = S.mode == P2P_L2 ? 0.0 : S.nu;
+  S.status = ST_DONE;
+}
+
+__device__ inline int stage_cap(const SlotState& S) {
+  long v = (long)S.iter_first + (long)S.stage * S.iter_inc;
+  if (S.iter_cap > 0 && v > S.iter_cap) v = S.iter_cap;
+  return (int)v;
+}
+
+__device__ inline double frob16(const double* a, const double* b) {
+  double s = 0.0;
+  for (int i = 0; i < 16; ++i) s += (a[i] - b[i]) * (a[i] - b[i]);
+  return sqrt(s);
+}
+
+__device__ inline void cpy(double* d, const double* s, int n) {
+  for (int i = 0; i < n; ++i) d[i] = s[i];
+}
+
+// ------------------------------------------------------------------ Algorithm 1
+
+__device__ void step_p2p(SlotState& S, const double* mom) {
+  const double E = mom[0];
+  double Tprop[16];
+  const unsigned pf = align_p2p(mom, S.cP, S.cQ, Tprop);
+  const int m = S.m;
+  int sm = S.sm;
+  if (sm == SM_INIT) {
+    if (S.mode != P2P_L2 && S.nu_auto) {
+      S.nu = 3.0 * sqrt(S.median);
+      S.want_median = 0;
+      request_T(S, S.Tkm1, S.nu);
+      S.sm = SM_STAGE_EVAL;
+      return;
+    }
+    S.nu = S.mode == P2P_L2 ? 0.0 : S.nu_max;
+    S.want_median = 0;
+    sm = SM_STAGE_EVAL;
+  }
+  if (sm == SM_STAGE_EVAL) {
+    // stage start: T' = align(Q^(k-1), T^(k-1), nu)
+    S.stages++;
+    S.Inu = stage_cap(S);
+    S.kstart = S.k - 1;
+    S.Eprev = __builtin_inf();
+    if (pf & F_ZERO_WEIGHT) {
+      S.flags |= F_ZERO_WEIGHT;
+      cpy(S.Tk, S.Tkm1, 16);
+      finish(S, S.Tk, E);
+      return;
+    }
+    S.flags |= pf & F_DEGENERATE;
+    cpy(S.Tp, Tprop, 16);
+    cpy(S.Tk, Tprop, 16);
+    double lp[6], lq[6];
+    twist_log(S.Tp, lp);
+    twist_log(S.Tkm1, lq);
+    for (int a = 0; a < 6; ++a) {
+      S.G[(S.k - 1) % kHist][a] = lp[a];
+      S.F[(S.k - 1) % kHist][a] = lp[a] - lq[a];
+    }
+    S.is_aa = 0;
+    request_T(S, S.Tk, S.nu);
+    S.sm = SM_ITER_EVAL;
+    return;
+  }
+  bool post = false;
+  if (sm == SM_ITER_EVAL) {
+    if (!(S.k - S.kstart <= S.Inu)) {
+      // iteration cap of the stage reached
+      S.flags = (S.flags & ~F_CONVERGED) | F_MAX_ITER;
+      goto stage_end;
+    }
+    if (S.max_total > 0 && S.total >= S.max_total) {
+      S.flags |= F_MAX_ITER;
+      finish(S, S.Tk, E);
+      return;
+    }
+    S.iterations++;
+    S.total++;
+    if (m > 0 && E >= S.Eprev) {
+      // safeguard: revert to the un-accelerated iterate
+      cpy(S.Tk, S.Tp, 16);
+      S.aa_rejected++;
+      request_T(S, S.Tk, S.nu);
+      S.sm = SM_REVERT_EVAL;
+      return;
+    }
+    if (S.is_aa) S.aa_accepted++;
+    post = true;
+  } else if (sm == SM_REVERT_EVAL) {
+    post = true;
+  }
+  if (post) {
+    S.Eprev = E;
+    S.Eit = E;
+    if (pf & F_ZERO_WEIGHT) {
+      S.flags |= F_ZERO_WEIGHT;
+      finish(S, S.Tk, E);
+      return;
+    }
+    S.flags |= pf & F_DEGENERATE;
+    cpy(S.Tp, Tprop, 16);
+    if (frob16(S.Tk, S.Tp) < S.eps) {
+      S.flags = (S.flags & ~F_MAX_ITER) | F_CONVERGED;
+      goto stage_end;
+    }
+    double Tn[16];
+    if (m == 0) {
+      cpy(Tn, S.Tp, 16);
+      S.is_aa = 0;
+    } else {
+      double lp[6], lk[6], xa[6];
+      twist_log(S.Tp, lp);
+      twist_log(S.Tk, lk);
+      for (int a = 0; a < 6; ++a) {
+        S.G[S.k % kHist][a] = lp[a];
+        S.F[S.k % kHist][a] = lp[a] - lk[a];
+      }
+      const int mk = (S.k - S.kstart) < m ? (S.k - S.kstart) : m;
+      if (anderson(S, S.k, mk, 0, xa)) S.flags |= F_AA_SINGULAR;
+      twist_exp(xa, Tn);
+      S.is_aa = 1;
+    }
+    cpy(S.Tk, Tn, 16);
+    S.k++;
+    request_T(S, S.Tk, S.nu);
+    S.sm = SM_ITER_EVAL;
+    return;
+  }
+  return;
+stage_end:
+  if (S.mode == P2P_L2 || S.nu == S.nu_min) {
+    finish(S, S.Tk, E);
+    return;
+  }
+  S.nu = fmax(S.nu / 2.0, S.nu_min);
+  S.k++;
+  S.stage++;
+  cpy(S.Tkm1, S.Tk, 16);
+  request_T(S, S.Tkm1, S.nu);
+  S.sm = SM_STAGE_EVAL;
+}
+
+// ------------------------------------------------------------------ Algorithm 2
+
+__device__ void step_p2pl(SlotState& S, const double* mom) {
+  const double E = mom[0];
+  double xprop[6];
+  const double* xeval = S.last_key;  // parameters of this evaluation
+  const unsigned pf = gn_p2pl(mom, xeval, xprop);
+  int sm = S.sm;
+  if (sm == SM_INIT) {
+    if (S.nu_auto) {
+      S.nu = 3.0 * S.median;
+      S.want_median = 0;
+      request_xi(S, S.xkm1, S.nu);
+      S.sm = SM_STAGE_EVAL;
+      return;
+    }
+    S.nu = S.nu_max;
+    S.want_median = 0;
+    sm = SM_STAGE_EVAL;
+  }
+  if (sm == SM_STAGE_EVAL) {
+    S.stages++;
+    S.Inu = stage_cap(S);
+    S.kstart = S.k - 1;
+    S.Eprev = __builtin_inf();
+    if (pf & (F_ZERO_WEIGHT | F_DEGENERATE)) {
+      S.flags |= pf;
+      cpy(S.xk, S.xkm1, 6);
+      double T[16];
+      twist_exp(S.xk, T);
+      finish(S, T, E);
+      return;
+    }
+    cpy(S.xstar, xprop, 6);
+    for (int a = 0; a < 6; ++a) {
+      S.G[(S.k - 1) % kHist][a] = S.xstar[a];
+      S.F[(S.k - 1) % kHist][a] = S.xstar[a] - S.xkm1[a];
+    }
+    cpy(S.xk, S.xstar, 6);
+    S.is_aa = 0;
+    request_xi(S, S.xk, S.nu);
+    S.sm = SM_ITER_EVAL;
+    return;
+  }
+  bool post = false;
+  if (sm == SM_ITER_EVAL) {
+    S.Eit = E;  // energy of the current iterate (used at stage end)
+    if (!(S.k - S.kstart <= S.Inu)) {
+      S.flags = (S.flags & ~F_CONVERGED) | F_MAX_ITER;
+      goto stage_end;
+    }
+    if (S.max_total > 0 && S.total >= S.max_total) {
+      S.flags |= F_MAX_ITER;
+      double T[16];
+      twist_exp(S.xk, T);
+      finish(S, T, E);
+      return;
+    }
+    S.iterations++;
+    S.total++;
+    cpy(S.best_prop, xprop, 6);
+    S.best_flags = pf;
+    if (E >= S.Eprev) {
+      // line search from xi^(k-1) toward xi*^(k)
+      S.tau = 1.0;
+      S.ls_l = 1;
+      if (S.lmax >= 1) {
+        for (int a = 0; a < 6; ++a) S.xt[a] = S.xkm1[a] + S.tau * (S.xstar[a] - S.xkm1[a]);
+        request_xi(S, S.xt, S.nu);
+        S.sm = SM_LS_EVAL;
+        return;
+      }
+      if (S.is_aa) S.aa_rejected++;
+    } else if (S.is_aa) {
+      S.aa_accepted++;
+    }
+    post = true;
+  } else if (sm == SM_LS_EVAL) {
+    S.ls_trials++;
+    if (E < S.Eit) {
+      S.Eit = E;
+      cpy(S.xk, S.xt, 6);
+      cpy(S.best_prop, xprop, 6);
+      S.best_flags = pf;
+    }
+    if (!(E < S.Eprev)) {
+      S.tau *= 0.5;
+      S.ls_l++;
+      if (S.ls_l <= S.lmax) {
+        for (int a = 0; a < 6; ++a) S.xt[a] = S.xkm1[a] + S.tau * (S.xstar[a] - S.xkm1[a]);
+        request_xi(S, S.xt, S.nu);
+        S.sm = SM_LS_EVAL;
+        return;
+      }
+    }
+    if (S.is_aa) S.aa_rejected++;
+    post = true;
+  }
+  if (post) {
+    S.Eprev = S.Eit;
+    if (S.best_flags & (F_ZERO_WEIGHT | F_DEGENERATE)) {
+      S.flags |= S.best_flags;
+      double T[16];
+      twist_exp(S.xk, T);
+      finish(S, T, S.Eit);
+      return;
+    }
+    double dn = 0.0;
+    for (int a = 0; a < 6; ++a) dn += (S.best_prop[a] - S.xk[a]) * (S.best_prop[a] - S.xk[a]);
+    if (sqrt(dn) < S.eps) {
+      S.flags = (S.flags & ~F_MAX_ITER) | F_CONVERGED;
+      goto stage_end;
+    }
+    for (int a = 0; a < 6; ++a) {
+      S.G[S.k % kHist][a] = S.best_prop[a];
+      S.F[S.k % kHist][a] = S.best_prop[a] - S.xk[a];
+    }
+    double xn[6];
+    if (S.m == 0) {
+      cpy(xn, S.best_prop, 6);
+      S.is_aa = 0;
+    } else {
+      const int mk = (S.k - S.kstart) < S.m ? (S.k - S.kstart) : S.m;
+      if (anderson(S, S.k, mk, 1, xn)) S.flags |= F_AA_SINGULAR;
+      S.is_aa = 1;
+    }
+    cpy(S.xkm1, S.xk, 6);
+    cpy(S.xstar, S.best_prop, 6);
+    cpy(S.xk, xn, 6);
+    S.k++;
+    request_xi(S, S.xk, S.nu);
+    S.sm = SM_ITER_EVAL;
+    return;
+  }
+  return;
+stage_end:
+  if (S.nu == S.nu_min) {
+    double T[16];
+    twist_exp(S.xk, T);
+    finish(S, T, S.Eit);
+    return;
+  }
+  S.nu = fmax(S.nu / 2.0, S.nu_min);
+  S.k++;
+  S.stage++;
+  cpy(S.xkm1, S.xk, 6);
+  request_xi(S, S.xkm1, S.nu);
+  S.sm = SM_STAGE_EVAL;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Merge the partials of one slot in a fixed order (lane-strided sums, then a
+// fixed shuffle tree) and advance the state machine on lane 0.
+__global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__ descs,
+                                                    SlotState* __restrict__ states, int capacity,
+                                                    int* __restrict__ done) {
+  const int slot = blockIdx.x;
+  if (slot >= capacity) return;
+  SlotState& S = states[slot];
+  if (S.status != ST_RUNNING) return;
+  const SlotDesc& D = descs[slot];
+  const int nv = D.mode == P2PL_WELSCH ? kP2PLVals : kP2PVals;
+  const int lane = threadIdx.x;
+  double acc[kP2PLVals];
+  for (int v = 0; v < kP2PLVals; ++v) acc[v] = 0.0;
+  for (int e = lane; e < D.nepi; e += 64) {
+    const double* p = D.part + (size_t)e * kPartStride;
+    for (int v = 0; v < nv; ++v) acc[v] += p[v];
+  }
+  for (int v = 0; v < kP2PLVals; ++v) {
+    double x = acc[v];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    acc[v] = x;
+  }
+  if (lane != 0) return;
+  S.phases++;
+  if (D.trace && S.trace_len < D.trace_cap) {
+    double* row = D.trace + (size_t)S.trace_len * kTraceRow;
+    row[0] = acc[0];
+    row[1] = S.nu_eval;
+    row[2] = S.sm;
+    row[3] = S.reuse;
+    for (int i = 0; i < 16; ++i) row[4 + i] = S.Teval[i];
+    S.trace_len++;
+  }
+  if (S.sm == SM_QUERY) {
+    S.status = ST_DONE;
+  } else if (S.sm == SM_EVAL) {
+    // energy at the requested transform and the MM update from it
+    double T[16];
+    unsigned f;
+    if (D.mode == P2PL_WELSCH) {
+      double xp[6];
+      f = gn_p2pl(acc, S.last_key, xp);
+      twist_exp(xp, T);
+    } else {
+      f = align_p2p(acc, S.cP, S.cQ, T);
+    }
+    S.flags = f;
+    S.nu = S.nu_eval;
+    finish(S, T, acc[0]);
+  } else if (D.mode == P2PL_WELSCH) {
+    step_p2pl(S, acc);
+  } else {
+    step_p2p(S, acc);
+  }
+  if (S.status == ST_DONE) done[slot] = 1;
+}
+
+// First request of a freshly admitted slot: evaluation at T0 (point-to-plane:
+// at exp(log T0)), then the slot becomes RUNNING.
+__global__ void boot_kernel(SlotState* __restrict__ states, int slot) {
+  if (threadIdx.x != 0) return;
+  SlotState& S = states[slot];
+  S.evaluations = 0;
+  S.nn_passes = 0;
+  S.have_last = 0;
+  if (S.sm == SM_QUERY) {
+    request_T(S, S.Tkm1, 1.0);
+  } else if (S.sm == SM_EVAL) {
+    if (S.mode == P2PL_WELSCH) {
+      twist_log(S.Tkm1, S.xkm1);
+      request_xi(S, S.xkm1, S.nu_max);
+    } else {
+      request_T(S, S.Tkm1, S.nu_max);
+    }
+  } else if (S.mode == P2PL_WELSCH) {
+    twist_log(S.Tkm1, S.xkm1);
+    request_xi(S, S.xkm1, S.nu_auto ? 1.0 : S.nu_max);
+  } else {
+    request_T(S, S.Tkm1, (S.mode == P2P_L2 || S.nu_auto) ? 1.0 : S.nu_max);
+  }
+  S.status = ST_RUNNING;
+}
+
+// Exact median (element of rank floor(M/2)) of the non-negative FP64 keys of
+// one slot by 8-bit radix selection on the bit patterns.
+__global__ __launch_bounds__(1024) void median_kernel(const SlotDesc* __restrict__ descs,
+                                                      SlotState* __restrict__ states, int capacity) {
+  const int slot = blockIdx.x;
+  if (slot >= capacity) return;
+  SlotState& S = states[slot];
+  if (S.status != ST_RUNNING || !S.want_median) return;
+  const SlotDesc& D = descs[slot];
+  __shared__ unsigned hist[256];
+  __shared__ unsigned long long s_prefix, s_mask;
+  __shared__ long long s_k;
+  if (threadIdx.x == 0) {
+    s_prefix = 0ull;
+    s_mask = 0ull;
+    s_k = D.M / 2;
+  }
+  __syncthreads();
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const unsigned long long pre = s_prefix, msk = s_mask;
+    for (int i = threadIdx.x; i < D.M; i += blockDim.x) {
+      const unsigned long long key = (unsigned long long)__double_as_longlong(D.medkey[i]);
+      if ((key & msk) == pre) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long k = s_k;
+      int d = 0;
+      for (; d < 256; ++d) {
+        if (k < (long long)hist[d]) break;
+        k -= hist[d];
+      }
+      s_k = k;
+      s_prefix = pre | ((unsigned long long)d << shift);
+      s_mask = msk | (255ull << shift);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) S.median = __longlong_as_double((long long)s_prefix);
+}
+
+void launch_solver(const SlotDesc* descs, SlotState* states, int capacity, int* done,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(solver_kernel, dim3(capacity), dim3(64), 0, st, descs, states, capacity, done);
+}
+
+void launch_boot(SlotState* states, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(boot_kernel, dim3(1), dim3(64), 0, st, states, slot);
+}
+
+void launch_median(const SlotDesc* descs, SlotState* states, int capacity, hipStream_t st) {
+  hipLaunchKernelGGL(median_kernel, dim3(capacity), dim3(1024), 0, st, descs, states, capacity);
+}
+
+}  // namespace icp

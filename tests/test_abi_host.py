@@ -1,0 +1,54 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, every
+symbol declared in include/icp.h is exported, struct layouts agree, and
+argument validation fails cleanly before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2007_07627_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "icp.h")).read()
+    return sorted(set(re.findall(r"\b(icp_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_params_default_matches_paper():
+    p = B.icp_params_default(B.ICP_P2P_WELSCH)
+    assert p.anderson_m == 5 and p.eps == 1e-5 and p.iter_first == 1000 and p.iter_cap == 1000
+    q = B.icp_params_default(B.ICP_P2PL_WELSCH)
+    assert (q.iter_first, q.iter_inc, q.iter_cap, q.max_line_search) == (6, 1, 10, 10)
+    assert list(q.T0) == list(np.eye(4).reshape(16))
+    assert B.lib().icp_params_default(7, C.byref(B.icp_params())) == B.ICP_ERR_INVALID_ARG
+
+
+def test_struct_sizes():
+    assert C.sizeof(B.icp_params) == 192
+    assert C.sizeof(B.icp_result) == 184
+
+
+def test_status_strings():
+    for s in range(9):
+        assert B.icp_status_str(s)
+
+
+def test_null_context_and_bad_device_fail_cleanly():
+    L = B.lib()
+    assert L.icp_destroy(None) == B.ICP_ERR_INVALID_ARG
+    h = C.c_void_p()
+    assert L.icp_create(-1, 0, C.byref(h)) == B.ICP_ERR_DEVICE
+    assert L.icp_poll(None, 1, None) == B.ICP_ERR_INVALID_ARG

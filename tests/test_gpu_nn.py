@@ -1,0 +1,100 @@
+"""Closest-point parity: the HIP search through the C ABI against the oracle's
+exhaustive scan, bit for bit (indices and FP32 squared distances)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_07627_amd import binding as B
+from paper_2007_07627_amd import synth
+
+from gpu_common import announce, ctx  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+METHODS = [B.ICP_NN_BRUTE, B.ICP_NN_CLUSTER]
+
+
+def _motion(seed, ang=20.0, tr=0.1):
+    R, t = synth.random_motion(np.random.default_rng(seed), ang, tr)
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = t
+    return T
+
+
+def _check(ctx, P, Q, T, method, tag):
+    announce(f"nn {tag} M={len(P)} N={len(Q)} method={method}")
+    gi, gd = B.icp_nn_query(ctx, P, Q, T, method)
+    oi, od = oracle.nn_query(P, Q, T)
+    bad = np.flatnonzero((gi != oi) | (gd.view(np.uint32) != od.view(np.uint32)))
+    assert bad.size == 0, f"{tag}: {bad.size} mismatches, first {bad[:5]} gpu {gi[bad[:5]]} oracle {oi[bad[:5]]}"
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 300), (63, 129), (64, 128), (65, 127), (1000, 3001),
+                                 (4096, 4096), (5000, 777)])
+def test_nn_random_shapes(ctx, method, m, n):
+    rng = np.random.default_rng(m * 7 + n)
+    Q = rng.uniform(-1, 1, (n, 3)).astype(np.float32)
+    P = rng.uniform(-1.3, 1.3, (m, 3)).astype(np.float32)
+    _check(ctx, P, Q, _motion(m + n), method, "random")
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_nn_surface_with_outliers(ctx, method):
+    d = synth.partial_sphere_pair(synth.rng_for(2, 11), m=20000, n=30000)
+    _check(ctx, d["P"], d["Q"], d["T_gt"], method, "sphere")
+    _check(ctx, d["P"], d["Q"], np.eye(4), method, "sphere-identity")
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_nn_height_field(ctx, method):
+    d = synth.height_field_pair(synth.rng_for(3, 11), m=20000, n=40000)
+    _check(ctx, d["P"], d["Q"], d["T_gt"], method, "heightfield")
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_nn_ties_duplicates_and_grid_points(ctx, method):
+    # integer lattice: exact ties everywhere; duplicated targets at several indices
+    g = np.arange(-4, 5, dtype=np.float32)
+    Q = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    Q = np.concatenate([Q, Q[::7], Q[::3]])  # duplicates with higher indices
+    rng = np.random.default_rng(3)
+    P = (rng.integers(-5, 6, (3000, 3)) * 0.5).astype(np.float32)  # on cell faces / midpoints
+    _check(ctx, P, Q, np.eye(4), method, "lattice")
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_nn_far_points_and_clusters(ctx, method):
+    rng = np.random.default_rng(5)
+    Q = np.concatenate([rng.normal(0, 0.01, (5000, 3)), rng.normal(50, 0.01, (5000, 3))]).astype(np.float32)
+    P = np.concatenate([rng.normal(25, 30, (3000, 3)), rng.normal(0, 1, (1000, 3))]).astype(np.float32)
+    _check(ctx, P, Q, np.eye(4), method, "far")
+
+
+def test_nn_empty_and_invalid(ctx):
+    Q = np.zeros((10, 3), np.float32)
+    idx, d2 = B.icp_nn_query(ctx, np.zeros((0, 3), np.float32), Q)
+    assert idx.size == 0
+    rc, _, _ = B.icp_nn_query(ctx, np.zeros((5, 3), np.float32), np.zeros((0, 3), np.float32), raw=True)
+    assert rc == B.ICP_ERR_INVALID_ARG
+    P = np.zeros((5, 3), np.float32)
+    P[2, 1] = np.nan
+    rc, _, _ = B.icp_nn_query(ctx, P, Q, raw=True)
+    assert rc == B.ICP_ERR_NONFINITE
+    T = np.eye(4)
+    T[0, 0] = 1.1
+    rc, _, _ = B.icp_nn_query(ctx, np.zeros((5, 3), np.float32), Q, T, raw=True)
+    assert rc == B.ICP_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_nn_full_size_sampled(ctx, method):
+    """Config-2 scale (M = N = 100k) in one call; the oracle checks a seeded
+    sample of 3000 sources."""
+    d = synth.partial_sphere_pair(synth.rng_for(2, 0))
+    announce(f"nn full-size sampled method={method}")
+    gi, gd = B.icp_nn_query(ctx, d["P"], d["Q"], d["T_gt"], method)
+    sel = np.random.default_rng(0).choice(len(d["P"]), 3000, replace=False)
+    oi, od = oracle.nn_query(d["P"][sel], d["Q"], d["T_gt"])
+    assert np.array_equal(gi[sel], oi) and np.array_equal(gd[sel], od)
