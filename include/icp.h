@@ -98,7 +98,21 @@ typedef struct {
   int aa_accepted, aa_rejected, line_search_trials, stages;
   unsigned status_flags; /* ICP_FLAG_* */
   double latency_ms;     /* batch engine: submit -> done; synchronous calls: wall time */
+  double nn_pairs;       /* (source, target) pairs run through the search's filter */
+  double nn_exact_pairs; /* pairs evaluated with the exact FP32 definition */
 } icp_result;
+
+/* Accumulated device time of the pass kernels since icp_profile(ctx, 1),
+ * measured with HIP events recorded around the kernels on the library's own
+ * stream: the closest-point search (cull + slice kernels), the
+ * weight-and-reduce pass, and the median + solver kernels; passes counted.
+ * While profiling, the graph engine launches the same passes directly on its
+ * stream (same kernels and host synchronisation cadence) instead of replaying
+ * the captured graph. */
+typedef struct {
+  double nn_ms, reduce_ms, solve_ms;
+  long long passes;
+} icp_profile_stats;
 
 typedef struct {
   const float *P;        /* M x 3 host source */
@@ -149,6 +163,13 @@ icp_status icp_register_trace(icp_ctx *ctx, const float *P, int64_t M, const flo
                               icp_result *out, double *trace_out, int trace_cap,
                               int *trace_len);
 
+/* Diagnostics of the last icp_register_trace call: for every closest-point
+ * work item of its last pass, 8 ints [device cycles, clusters run through the
+ * filter, candidate clusters, flags (1 warm start, 2 candidate list, 4 exact
+ * re-pass), cycles of: warm start, candidate search, list refinement, filter]
+ * into out (capacity cap items); *len = number of items. */
+icp_status icp_trace_items(icp_ctx *ctx, int *out, int cap, int *len);
+
 /* Same with device-resident AoS inputs (no host copy); `stream` is ordered
  * before and after the work (NULL = the null stream). Synchronous. */
 icp_status icp_register_dev(icp_ctx *ctx, const float *P_dev, int64_t M, const float *Q_dev,
@@ -188,6 +209,11 @@ icp_status icp_batch_wait_all(icp_ctx *ctx);
 /* Scheduler knobs: passes per graph replay (>= 1) and the maximum number of
  * concurrently resident pairs (1..1024). */
 icp_status icp_batch_config(icp_ctx *ctx, int passes_per_replay, int max_slots);
+
+/* Enable (1) or disable (0) per-pass kernel timing; resets the counters.
+ * Applies to passes launched afterwards. */
+icp_status icp_profile(icp_ctx *ctx, int enable);
+icp_status icp_profile_read(icp_ctx *ctx, icp_profile_stats *out);
 
 const char *icp_status_str(icp_status s);
 

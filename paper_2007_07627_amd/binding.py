@@ -22,10 +22,11 @@ ICP_FLAG_CONVERGED, ICP_FLAG_MAX_ITER, ICP_FLAG_ZERO_WEIGHT = 1, 2, 4
 ICP_FLAG_DEGENERATE, ICP_FLAG_AA_SINGULAR = 8, 16
 
 EXPORTED = ["icp_create", "icp_destroy", "icp_params_default", "icp_register", "icp_register_trace",
-            "icp_eval",
+            "icp_eval", "icp_trace_items",
             "icp_register_dev",
             "icp_nn_query", "icp_nn_query_dev", "icp_batch_submit", "icp_poll",
-            "icp_batch_wait_all", "icp_batch_config", "icp_status_str"]
+            "icp_batch_wait_all", "icp_batch_config", "icp_profile", "icp_profile_read",
+            "icp_status_str"]
 
 
 class icp_params(C.Structure):
@@ -41,7 +42,13 @@ class icp_result(C.Structure):
                 ("iterations", C.c_int), ("nn_passes", C.c_int), ("evaluations", C.c_int),
                 ("aa_accepted", C.c_int), ("aa_rejected", C.c_int),
                 ("line_search_trials", C.c_int), ("stages", C.c_int),
-                ("status_flags", C.c_uint), ("latency_ms", C.c_double)]
+                ("status_flags", C.c_uint), ("latency_ms", C.c_double),
+                ("nn_pairs", C.c_double), ("nn_exact_pairs", C.c_double)]
+
+
+class icp_profile_stats(C.Structure):
+    _fields_ = [("nn_ms", C.c_double), ("reduce_ms", C.c_double), ("solve_ms", C.c_double),
+                ("passes", C.c_longlong)]
 
 
 class icp_request(C.Structure):
@@ -75,6 +82,7 @@ def lib():
                                          C.POINTER(icp_result), vp, i32, C.POINTER(C.c_int)]
         L.icp_eval.argtypes = [vp, vp, i64, vp, vp, i64, i32, vp, C.c_double,
                                C.POINTER(C.c_double), vp, C.POINTER(C.c_uint)]
+        L.icp_trace_items.argtypes = [vp, vp, i32, C.POINTER(C.c_int)]
         L.icp_register_dev.argtypes = [vp, vp, i64, vp, vp, i64, C.POINTER(icp_params),
                                        C.POINTER(icp_result), vp]
         L.icp_nn_query.argtypes = [vp, vp, i64, vp, i64, vp, i32, vp, vp]
@@ -83,6 +91,8 @@ def lib():
         L.icp_poll.argtypes = [vp, C.c_uint64, C.POINTER(icp_result)]
         L.icp_batch_wait_all.argtypes = [vp]
         L.icp_batch_config.argtypes = [vp, i32, i32]
+        L.icp_profile.argtypes = [vp, i32]
+        L.icp_profile_read.argtypes = [vp, C.POINTER(icp_profile_stats)]
         L.icp_status_str.argtypes = [i32]
         L.icp_status_str.restype = C.c_char_p
         for n in EXPORTED:
@@ -183,6 +193,14 @@ def icp_eval(ctx, P, Q, Qn, mode, T, nu=0.0, raw=False):
     return E.value, Tn, fl.value
 
 
+def icp_trace_items(ctx, cap: int = 1 << 20):
+    """Per-work-item diagnostics of the last traced registration's last pass."""
+    out = np.zeros((cap, 8), np.int32)
+    n = C.c_int(0)
+    _check(lib().icp_trace_items(ctx, out.ctypes.data, cap, C.byref(n)), "icp_trace_items")
+    return out[: min(n.value, cap)].copy()
+
+
 def icp_register_dev(ctx, P_t, Q_t, Qn_t=None, params: icp_params | None = None, stream=None):
     """Device variant: torch tensors (contiguous float32, shape (n, 3)) in HBM."""
     params = params or icp_params_default()
@@ -249,3 +267,13 @@ def icp_batch_wait_all(ctx):
 
 def icp_batch_config(ctx, passes_per_replay: int, max_slots: int):
     _check(lib().icp_batch_config(ctx, passes_per_replay, max_slots), "icp_batch_config")
+
+
+def icp_profile(ctx, enable: bool):
+    _check(lib().icp_profile(ctx, 1 if enable else 0), "icp_profile")
+
+
+def icp_profile_read(ctx) -> dict:
+    st = icp_profile_stats()
+    _check(lib().icp_profile_read(ctx, C.byref(st)), "icp_profile_read")
+    return {f: getattr(st, f) for f, _ in icp_profile_stats._fields_}

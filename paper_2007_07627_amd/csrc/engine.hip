@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -118,7 +119,8 @@ struct Layout {
   size_t o_px, o_py, o_pz, o_perm, o_tsph, o_pox, o_poy, o_poz;
   size_t o_qx, o_qy, o_qz, o_nx, o_ny, o_nz;
   size_t o_qloc, o_qorg, o_ccen, o_clo, o_chi, o_slo, o_shi;
-  size_t o_keys, o_nnidx, o_nnd2, o_part, o_med, o_idx, o_d2, o_scratch, o_trace;
+  size_t o_clist, o_tinfo, o_squeue, o_scount;
+  size_t o_keys, o_nnidx, o_nnd2, o_part, o_med, o_idx, o_d2, o_scratch, o_trace, o_stats, o_items;
   int trace_cap = 0;
   size_t add(size_t bytes) {
     const size_t o = total;
@@ -145,6 +147,10 @@ struct Layout {
     o_ccen = add(16ull * ncl); o_clo = add(16ull * ncl); o_chi = add(16ull * ncl);
     o_slo = add(16ull * nsup); o_shi = add(16ull * nsup);
     o_keys = add(8ull * M);
+    o_clist = add(4ull * kListCap * ntile);
+    o_tinfo = add(16ull * ntile);
+    o_squeue = add(8ull * kMaxSlices * ntile);
+    o_scount = add(16);
     o_nnidx = add(4ull * M);
     o_nnd2 = add(4ull * M);
     o_part = add(8ull * kPartStride * nepi);
@@ -154,6 +160,8 @@ struct Layout {
     const size_t sw = std::max(sort_scratch_words(std::max(M, N)) * 4, (size_t)12 * std::max(M, N));
     o_scratch = add(sw);
     o_trace = add(8ull * kTraceRow * tcap);
+    o_stats = add(16);
+    o_items = add(tcap > 0 ? 32ull * ntile * kMaxSlices : 0);
   }
 };
 
@@ -187,6 +195,15 @@ struct OwnedRequest {
   Clock::time_point t_submit;
 };
 
+static void fill_stats(const HostSlot& h, hipStream_t st, icp_result* r) {
+  unsigned long long v[2] = {0ull, 0ull};
+  if (h.mem && hipMemcpyAsync(v, h.mem + h.L.o_stats, sizeof v, hipMemcpyDeviceToHost, st) == hipSuccess &&
+      hipStreamSynchronize(st) == hipSuccess) {
+    r->nn_pairs = (double)v[0];
+    r->nn_exact_pairs = (double)v[1];
+  }
+}
+
 static void fill_result(const SlotState& S, icp_result* r) {
   std::memcpy(r->T, S.Tres, sizeof r->T);
   r->energy = S.energy;
@@ -219,8 +236,14 @@ struct Engine {
   hipGraph_t graph = nullptr;
   int gphases = 0;
   int gcap = 0;
+  bool gprof = false;
   int nn_grid = 4096, epi_grid = 1024;
   Arena* arena = nullptr;
+  // profiling: timing events around the kernels of every pass
+  bool prof = false;
+  std::vector<hipEvent_t> pev;  // 4 per pass
+  double prof_ms[3] = {0.0, 0.0, 0.0};  // closest point, reduction, median + solver
+  long long prof_passes = 0;
 
   bool init(int device, int cap, Arena* a, int items) {
     dev = device;
@@ -255,6 +278,8 @@ struct Engine {
     gexec = nullptr; graph = nullptr;
     for (auto& h : hs)
       if (h.used && h.mem) arena->release(h.mem);
+    for (auto e : pev) (void)hipEventDestroy(e);
+    pev.clear();
     if (d_desc) (void)hipFree(d_desc);
     if (d_state) (void)hipFree(d_state);
     if (d_wl) (void)hipFree(d_wl);
@@ -266,24 +291,64 @@ struct Engine {
     st = nullptr; side = nullptr;
   }
 
-  void enqueue_pass(hipStream_t s) {
+  bool ensure_events(int passes) {
+    while ((int)pev.size() < 4 * passes) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      pev.push_back(e);
+    }
+    return true;
+  }
+
+  // capturing: the events become event-record nodes of the graph
+  void mark(int k, hipStream_t s, bool capturing) {
+    if (!prof) return;
+    if (capturing) (void)hipEventRecordWithFlags(pev[k], s, hipEventRecordExternal);
+    else (void)hipEventRecord(pev[k], s);
+  }
+
+  void enqueue_pass(hipStream_t s, int i = 0, bool capturing = false) {
     launch_plan(d_desc, d_state, d_wl, capacity, s);
+    mark(4 * i, s, capturing);
     launch_nn(d_desc, d_state, d_wl, nn_grid, s);
+    mark(4 * i + 1, s, capturing);
     launch_epi(d_desc, d_state, d_wl, epi_grid, s);
+    mark(4 * i + 2, s, capturing);
     launch_median(d_desc, d_state, capacity, s);
     launch_solver(d_desc, d_state, capacity, d_done, s);
+    mark(4 * i + 3, s, capturing);
+  }
+
+  // after the stream has been synchronised
+  void collect_profile(int passes) {
+    if (!prof) return;
+    for (int i = 0; i < passes; ++i) {
+      float a = 0.f, b = 0.f, c = 0.f;
+      if (hipEventElapsedTime(&a, pev[4 * i], pev[4 * i + 1]) == hipSuccess &&
+          hipEventElapsedTime(&b, pev[4 * i + 1], pev[4 * i + 2]) == hipSuccess &&
+          hipEventElapsedTime(&c, pev[4 * i + 2], pev[4 * i + 3]) == hipSuccess) {
+        prof_ms[0] += a;
+        prof_ms[1] += b;
+        prof_ms[2] += c;
+        prof_passes++;
+      } else {
+        (void)hipGetLastError();  // do not leave a timing failure as the sticky error
+      }
+    }
   }
 
   bool build_graph(int phases) {
-    if (gexec && gphases == phases && gcap == capacity) return true;
+    if (gexec && gphases == phases && gcap == capacity && gprof == prof) return true;
+    if (prof && !ensure_events(phases)) return false;
     if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
     if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
     HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < phases; ++i) enqueue_pass(st);
+    for (int i = 0; i < phases; ++i) enqueue_pass(st, i, true);
     HIP_OK(hipStreamEndCapture(st, &graph));
     HIP_OK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
     gphases = phases;
     gcap = capacity;
+    gprof = prof;
     return true;
   }
 
@@ -303,6 +368,7 @@ struct Engine {
   // false on a HIP error; OOM is reported through *oom.
   bool admit(int s, const OwnedRequest& r, bool* oom) {
     *oom = false;
+    (void)hipGetLastError();  // launch errors below are checked against a clean slate
     HostSlot& h = hs[s];
     const bool p2pl = !r.query && r.prm.mode == ICP_P2PL_WELSCH;
     h.L.plan(r.M, r.N, p2pl, r.query && !r.idx_dev_out, r.trace_cap);
@@ -373,6 +439,9 @@ struct Engine {
                        F(L.o_py), F(L.o_pz), reinterpret_cast<int*>(b + L.o_perm),
                        reinterpret_cast<double4*>(b + L.o_tsph), ss);
     launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_keys), L.M, ~0ull, ss);
+    launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_stats), 2, 0ull, ss);
+    // no previous closest point yet (int32 -1 everywhere)
+    launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_nnidx), (L.M + 1) / 2, ~0ull, ss);
     // descriptor (rho_max is written by build_super above, so copy the rest around it)
     SlotDesc D;
     std::memset(&D, 0, sizeof D);
@@ -386,6 +455,10 @@ struct Engine {
     D.qloc = F4(L.o_qloc); D.qorg = F4(L.o_qorg); D.ccen = F4(L.o_ccen);
     D.clo = F4(L.o_clo); D.chi = F4(L.o_chi); D.slo = F4(L.o_slo); D.shi = F4(L.o_shi);
     D.keys = reinterpret_cast<unsigned long long*>(b + L.o_keys);
+    D.clist = reinterpret_cast<int*>(b + L.o_clist);
+    D.tinfo = reinterpret_cast<int4*>(b + L.o_tinfo);
+    D.squeue = reinterpret_cast<int2*>(b + L.o_squeue);
+    D.scount = reinterpret_cast<int*>(b + L.o_scount);
     D.nnidx = reinterpret_cast<int32_t*>(b + L.o_nnidx);
     D.nnd2 = F(L.o_nnd2);
     D.part = reinterpret_cast<double*>(b + L.o_part);
@@ -394,6 +467,8 @@ struct Engine {
       D.idx_out = r.idx_dev_out ? r.idx_dev_out : reinterpret_cast<int32_t*>(b + L.o_idx);
       D.d2_out = r.d2_dev_out ? r.d2_dev_out : F(L.o_d2);
     }
+    D.stats = reinterpret_cast<unsigned long long*>(b + L.o_stats);
+    D.item_stats = L.trace_cap > 0 ? reinterpret_cast<int*>(b + L.o_items) : nullptr;
     D.trace = L.trace_cap > 0 ? reinterpret_cast<double*>(b + L.o_trace) : nullptr;
     D.trace_cap = L.trace_cap;
     D.M = L.M; D.N = L.N; D.ntile = L.ntile; D.ncl = L.ncl; D.nsup = L.nsup; D.nepi = L.nepi;
@@ -464,6 +539,7 @@ struct icp_ctx {
   int passes_per_replay = 4;
   int max_slots = 256;
   int running = 0;
+  std::vector<int> last_items;  // per NN work item of the last traced registration's last pass
 };
 
 static const size_t kQueueCap = 1 << 20;
@@ -512,7 +588,7 @@ static icp_status check_sizes(int64_t M, int64_t N) {
 // Run one slot of the synchronous engine to completion.
 static icp_status run_sync(icp_ctx* ctx, OwnedRequest& r, icp_result* out, void* ustream,
                            int32_t* host_idx, float* host_d2, double* host_trace = nullptr,
-                           int* trace_len = nullptr) {
+                           int* trace_len = nullptr, std::vector<int>* item_stats_out = nullptr) {
   Engine& E = ctx->sync_eng;
   const auto t0 = Clock::now();
   hipStream_t us = reinterpret_cast<hipStream_t>(ustream);
@@ -538,19 +614,27 @@ static icp_status run_sync(icp_ctx* ctx, OwnedRequest& r, icp_result* out, void*
   if (plain) {
     for (;; ++passes) {
       if (passes > kMaxPasses) { rc = ICP_ERR_DEVICE; break; }
-      E.enqueue_pass(E.st);
+      if (E.prof && !E.ensure_events(1)) { rc = ICP_ERR_DEVICE; break; }
+      E.enqueue_pass(E.st, 0);
       if (hipMemcpyAsync(E.h_done, E.d_done, sizeof(int), hipMemcpyDeviceToHost, E.st) != hipSuccess ||
           hipStreamSynchronize(E.st) != hipSuccess) { rc = ICP_ERR_DEVICE; break; }
+      E.collect_profile(1);
       if (E.h_done[0]) break;
     }
   } else {
     const int R = (r.query || r.eval) ? 1 : 8;
-    if (!E.build_graph(R)) { E.release(0); return ICP_ERR_DEVICE; }
+    // profiling: the same passes launched directly (timing events around each
+    // kernel); otherwise replays of the captured graph
+    if (!E.prof && !E.build_graph(R)) { E.release(0); return ICP_ERR_DEVICE; }
+    if (E.prof && !E.ensure_events(R)) { E.release(0); return ICP_ERR_DEVICE; }
     for (;; passes += R) {
       if (passes > kMaxPasses) { rc = ICP_ERR_DEVICE; break; }
-      if (hipGraphLaunch(E.gexec, E.st) != hipSuccess ||
+      if (E.prof)
+        for (int i = 0; i < R; ++i) E.enqueue_pass(E.st, i, false);
+      if ((!E.prof && hipGraphLaunch(E.gexec, E.st) != hipSuccess) ||
           hipMemcpyAsync(E.h_done, E.d_done, sizeof(int), hipMemcpyDeviceToHost, E.st) != hipSuccess ||
           hipStreamSynchronize(E.st) != hipSuccess) { rc = ICP_ERR_DEVICE; break; }
+      E.collect_profile(R);
       if (E.h_done[0]) break;
     }
   }
@@ -559,11 +643,19 @@ static icp_status run_sync(icp_ctx* ctx, OwnedRequest& r, icp_result* out, void*
     if (!E.read_state(0, &S)) rc = ICP_ERR_DEVICE;
     else if (out) {
       fill_result(S, out);
+      fill_stats(E.hs[0], E.st, out);
       out->latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
     }
     if (rc == ICP_OK && host_trace && trace_len) {
       const Layout& L = E.hs[0].L;
       *trace_len = std::min(S.trace_len, L.trace_cap);
+      if (item_stats_out) {
+        const SlotDesc* dd = nullptr;
+        (void)dd;
+        item_stats_out->resize(8ull * L.ntile * kMaxSlices);
+        (void)hipMemcpy(item_stats_out->data(), E.hs[0].mem + L.o_items, 32ull * L.ntile * kMaxSlices,
+                        hipMemcpyDeviceToHost);
+      }
       if (*trace_len > 0 &&
           hipMemcpy(host_trace, E.hs[0].mem + L.o_trace, 8ull * kTraceRow * *trace_len,
                     hipMemcpyDeviceToHost) != hipSuccess)
@@ -607,7 +699,14 @@ static void scheduler(icp_ctx* ctx) {
     }
     bool ok = true;
     // 1) advance every resident pair by R passes (asynchronous)
-    if (running > 0) ok = E.build_graph(R) && hipGraphLaunch(E.gexec, E.st) == hipSuccess;
+    if (running > 0) {
+      if (E.prof) {
+        ok = E.ensure_events(R);
+        for (int i = 0; ok && i < R; ++i) E.enqueue_pass(E.st, i, false);
+      } else {
+        ok = E.build_graph(R) && hipGraphLaunch(E.gexec, E.st) == hipSuccess;
+      }
+    }
     // 2) meanwhile set up queued requests on the side stream (FIFO; a request
     //    that does not fit waits for memory unless nothing else is resident)
     for (; ok;) {
@@ -648,6 +747,7 @@ static void scheduler(icp_ctx* ctx) {
       ok = hipMemcpyAsync(E.h_done, E.d_done, sizeof(int) * E.capacity, hipMemcpyDeviceToHost, E.st) ==
                hipSuccess &&
            hipStreamSynchronize(E.st) == hipSuccess;
+    if (ok && running > 0) E.collect_profile(R);
     if (!ok) {
       std::lock_guard<std::mutex> lk(ctx->mu);
       ctx->failed = true;
@@ -662,6 +762,7 @@ static void scheduler(icp_ctx* ctx) {
       icp_result res;
       std::memset(&res, 0, sizeof res);
       if (E.read_state(s, &S)) fill_result(S, &res);
+      fill_stats(E.hs[s], E.st, &res);
       res.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - E.hs[s].t_submit).count();
       const int zero = 0;
       const int st_free = ST_FREE;
@@ -732,7 +833,11 @@ icp_status icp_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
   c->device = device;
   if (hbm_budget_bytes == 0) hbm_budget_bytes = size_t(8) << 30;
   if (!c->arena.init(hbm_budget_bytes)) { delete c; return ICP_ERR_OOM; }
-  if (!c->sync_eng.init(device, 1, &c->arena, 4096) || !c->batch_eng.init(device, c->max_slots, &c->arena, 64)) {
+  // closest-point work items aimed for per pass when splitting source tiles
+  // over target subsets (tunable: ICP_NN_TARGET_ITEMS)
+  int items = 4096;
+  if (const char* e = std::getenv("ICP_NN_TARGET_ITEMS")) items = std::max(1, std::atoi(e));
+  if (!c->sync_eng.init(device, 1, &c->arena, items) || !c->batch_eng.init(device, c->max_slots, &c->arena, 64)) {
     c->sync_eng.destroy();
     c->batch_eng.destroy();
     delete c;
@@ -836,7 +941,16 @@ icp_status icp_register_trace(icp_ctx* ctx, const float* P, int64_t M, const flo
   r.M = M; r.N = N; r.prm = *params;
   r.trace_cap = trace_cap;
   std::lock_guard<std::mutex> g(ctx->sync_mu);
-  return run_sync(ctx, r, out, nullptr, nullptr, nullptr, trace_out, trace_len);
+  return run_sync(ctx, r, out, nullptr, nullptr, nullptr, trace_out, trace_len, &ctx->last_items);
+}
+
+icp_status icp_trace_items(icp_ctx* ctx, int* out, int cap, int* len) {
+  if (!ctx || !len || cap < 0 || (cap > 0 && !out)) return ICP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  const int n = (int)(ctx->last_items.size() / 8);
+  *len = n;
+  std::memcpy(out, ctx->last_items.data(), sizeof(int) * 8 * (size_t)std::min(n, cap));
+  return ICP_OK;
 }
 
 icp_status icp_register_dev(icp_ctx* ctx, const float* P_dev, int64_t M, const float* Q_dev,
@@ -963,6 +1077,32 @@ icp_status icp_poll(icp_ctx* ctx, uint64_t ticket, icp_result* out) {
   if (st == 4) { if (r != ctx->results.end()) ctx->results.erase(r); return ICP_ERR_DEVICE; }
   if (out && r != ctx->results.end()) *out = r->second;
   if (r != ctx->results.end()) ctx->results.erase(r);
+  return ICP_OK;
+}
+
+icp_status icp_profile(icp_ctx* ctx, int enable) {
+  if (!ctx) return ICP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (Engine* E : {&ctx->sync_eng, &ctx->batch_eng}) {
+    E->prof = enable != 0;
+    E->prof_ms[0] = E->prof_ms[1] = E->prof_ms[2] = 0.0;
+    E->prof_passes = 0;
+  }
+  return ICP_OK;
+}
+
+icp_status icp_profile_read(icp_ctx* ctx, icp_profile_stats* out) {
+  if (!ctx || !out) return ICP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  std::memset(out, 0, sizeof *out);
+  for (Engine* E : {&ctx->sync_eng, &ctx->batch_eng}) {
+    out->nn_ms += E->prof_ms[0];
+    out->reduce_ms += E->prof_ms[1];
+    out->solve_ms += E->prof_ms[2];
+    out->passes += E->prof_passes;
+  }
   return ICP_OK;
 }
 

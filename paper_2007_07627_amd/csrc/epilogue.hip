@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ d
         const float d2 = __uint_as_float((unsigned)(key >> 32));
         D.nnidx[si] = idx;
         D.nnd2[si] = d2;
-        if (D.split > 1) D.keys[si] = ~0ull;
+        D.keys[si] = ~0ull;  // ready for the next pass's atomic min
         if (D.idx_out) {
           const int o = D.perm[si];
           D.idx_out[o] = idx;

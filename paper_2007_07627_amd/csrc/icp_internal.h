@@ -19,6 +19,12 @@ constexpr int kHist = 8;         // Anderson ring capacity (m <= 6 needs m + 1)
 constexpr int kCandCap = 1024;   // LDS candidate list capacity per NN work item
 constexpr int kSupCap = 512;     // LDS candidate super-cluster capacity per NN work item
 constexpr int kMaxSplit = 8;
+constexpr int kListCap = 512;    // candidate clusters stored per tile
+constexpr int kMaxSlices = 16;   // slices per tile in cluster mode
+constexpr int kSliceMin = 8;     // clusters per slice at least (cluster mode)
+
+// tile record flags (cull kernel -> slice kernel)
+enum TileFlags { TI_WARM = 1, TI_LIST = 2, TI_RANGE = 4, TI_LANETEST = 8 };
 
 enum Mode { P2P_L2 = 0, P2P_WELSCH = 1, P2PL_WELSCH = 2 };
 enum NNMethod { NN_AUTO = 0, NN_BRUTE = 1, NN_CLUSTER = 2 };
@@ -68,17 +74,24 @@ struct SlotDesc {
   const float4* chi;          // cluster AABB max
   const float4* slo;          // super-cluster AABB min
   const float4* shi;          // super-cluster AABB max
-  unsigned long long* keys;   // per sorted source: (bits(d2) << 32) | index
+  unsigned long long* keys;   // per sorted source: (bits(d2) << 32) | index, merged by atomic min
+  int* clist;                 // per tile: kListCap candidate cluster ids
+  int4* tinfo;                // per tile: (flags, count, slice length, nearest cluster or -1)
+  int2* squeue;               // slices queued by the cull kernel: (tile, slice)
+  int* scount;                // number of queued slices (reset by the planner)
   int32_t* nnidx;             // per sorted source: closest original target index
   float* nnd2;                // per sorted source: its FP32 squared distance
   double* part;               // nepi x kPartStride
   double* medkey;             // per sorted source (setup pass only)
   int32_t* idx_out;           // optional: original-order outputs (queries)
   float* d2_out;
+  unsigned long long* stats;  // [0] pairs through the filter, [1] pairs scanned exactly
   double* trace;              // optional per-pass rows [E, nu, sm, reuse, T(16)]
+  int* item_stats;            // optional, last pass: per NN work item
+                              // [cycles, clusters filtered, candidates, flags]
   int trace_cap;
   int M, N, ntile, ncl, nsup, nepi;
-  int split;                  // target splits per source tile
+  int split;                  // brute mode: slices per tile
   int method;                 // NN_BRUTE or NN_CLUSTER
   int mode;
   float rho_max;              // max cluster radius (upper bound)
@@ -126,12 +139,15 @@ struct WorkList {
   int n_active;
   int nn_total;
   int epi_total;
-  int nn_counter;             // dynamic work counters (reset by the planner)
+  int nn_counter;             // dynamic work counters (reset by the planners)
   int epi_counter;
-  int pad[3];
+  int s_total;                // closest-point slices queued this pass
+  int s_counter;
+  int pad;
   int slot[1024];             // compacted active slot ids
   int nn_base[1025];          // prefix of NN items over the compacted list
   int epi_base[1025];
+  int s_base[1025];           // prefix of queued slices over the compacted list
 };
 
 constexpr int kMaxSlots = 1024;

@@ -21,8 +21,14 @@
 //    tile, transformed per pass, against super-cluster and cluster AABBs gives
 //    a candidate list; per lane, a cluster whose AABB distance exceeds the
 //    current best by more than the error bound is skipped wave-uniformly.
-//  * Optionally the candidate list of a tile is split over several work
-//    items whose keys merge with a 64-bit atomic min (order independent).
+//  * Two kernels: the cull kernel (one wavefront per 64-source tile) builds
+//    the tile's candidate list and appends slices of it to a per-pair queue;
+//    the slice kernel (persistent, dynamic) filters one slice and merges its
+//    exact result into the key with a 64-bit atomic min (order independent),
+//    so tiles with many candidates (outliers) spread over many wavefronts.
+//  * Warm start: the previous pass's closest target bounds each lane's exact
+//    minimum before any cluster is read; the candidate list keeps only the
+//    clusters some lane of the tile can still need.
 #include "icp_internal.h"
 
 namespace icp {
@@ -30,6 +36,12 @@ namespace icp {
 __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
   return v;
 }
 
@@ -41,23 +53,12 @@ __device__ __forceinline__ void xform_f32(const double* T, float x, float y, flo
   oz = (float)__builtin_fma(T[10], Z, __builtin_fma(T[9], Y, __builtin_fma(T[8], X, T[11])));
 }
 
-// Bound on |filter value - exact squared distance| for a target whose exact
-// squared distance is at most x, with rho the cluster radius: a 4x margin
-// over u (7 (sqrt(x) + 2 rho)^2 + x), u = 2^-24, which covers the rounding of
-// the centred coordinates, of h, of the three FMAs and of the final FMA.
-__device__ __forceinline__ float err_bound(float x, float rho) {
-  const float s = sqrtf(x) + 2.0f * rho;
-  return 0x1.0p-22f * (7.0f * s * s + x) * 1.001f;
-}
-
-// Threshold on the filter value above which a target can neither beat nor tie
-// the exact winner (gamma = 1e-6 bounds the relative error of the exact FP32
-// form, 5u).
-__device__ __forceinline__ float ambiguity_threshold(float best, float rho) {
-  const float X = fmaxf(best, 0.0f);
-  const float Xp = X + err_bound(X, rho);
-  const float slack = 2.0f * err_bound(Xp * 1.00001f, rho) + 2.2e-6f * Xp;
-  return X + slack * 1.01f + 1e-37f;
+// Relative error bound of the exact FP32 form d2 = fma(dz,dz, fma(dy,dy, dx*dx))
+// against the exact squared distance (5 roundings: |d2 - e| <= 5u e, u =
+// 2^-24), with margin: gamma = 1e-6. A target j can equal or beat the winner
+// only if e_j <= e_min (1 + 2.1 gamma).
+__device__ __forceinline__ float winner_threshold(float H) {
+  return H + 2.2e-6f * fabsf(H) + 1e-37f;
 }
 
 __device__ __forceinline__ unsigned long long make_key(float d2, int idx) {
@@ -65,9 +66,10 @@ __device__ __forceinline__ unsigned long long make_key(float d2, int idx) {
 }
 
 // Exact FP32 scan of n targets of the original-coordinate array.
-__device__ __forceinline__ unsigned long long exact_scan(const float4* __restrict__ qorg, int base,
+__device__ __forceinline__ unsigned long long exact_scan(const float4* qorg, int base,
                                                          int n, float px, float py, float pz,
                                                          unsigned long long key) {
+#pragma unroll 8
   for (int j = 0; j < n; ++j) {
     const float4 q = qorg[base + j];
     const int id = __float_as_int(q.w);
@@ -94,16 +96,28 @@ __device__ __forceinline__ float box_ub2(float px, float py, float pz, float4 lo
   return dx * dx + dy * dy + dz * dz;
 }
 
+// Per lane, over the chunks run through the filter: H = min over chunks of a
+// certified upper bound on the exact squared distance of the chunk's best
+// target, A = the chunk attaining H, loA = that chunk's certified lower bound,
+// S = min certified lower bound over all other chunks.
 struct LaneBest {
-  float best, second;
-  int bc;  // global chunk id (cluster * 4 + chunk)
+  float H, loA, S;
+  int A;  // global chunk id (cluster * 4 + chunk)
 };
 
-// Process one cluster with the filter (all 128 targets, 4 chunks).
+// Process one cluster with the filter (all 128 targets, 4 chunks). The filter
+// value of a target is v = 2 (h - pl . ql) + |pl|^2 with pl = p' - cc; its
+// distance to the exact squared distance is at most
+// u (7 (|pl| + rho)^2 + |v|) (rounding of the centred coordinates, of h, of
+// the three FMAs and of the last FMA); 4u is used, so for the chunk minimum v:
+// lo = v - 2^-22 |v| - delta, hi = v + 2^-22 |v| + delta,
+// delta = 2^-22 7 (|pl| + rho)^2.
 __device__ __forceinline__ void filter_cluster(const float4* __restrict__ lds, int c, float plx,
-                                               float ply, float plz, LaneBest& L) {
+                                               float ply, float plz, float rho_c, LaneBest& L) {
   const float npx = -plx, npy = -ply, npz = -plz;
   const float pp = __builtin_fmaf(plz, plz, __builtin_fmaf(ply, ply, plx * plx));
+  const float t = sqrtf(pp) + rho_c;
+  const float delta = 0x1.0p-22f * 7.0f * 1.0001f * t * t;
 #pragma unroll
   for (int ch = 0; ch < kChunksPerCluster; ++ch) {
     float m0 = __builtin_inff(), m1 = __builtin_inff();
@@ -120,55 +134,81 @@ __device__ __forceinline__ void filter_cluster(const float4* __restrict__ lds, i
       m0 = fminf(m0, fminf(sa, sb));
       m1 = fminf(m1, fminf(sc, sd));
     }
-    const float me = __builtin_fmaf(2.0f, fminf(m0, m1), pp);
-    L.second = __builtin_amdgcn_fmed3f(L.second, me, L.best);
-    const bool lt = me < L.best;
-    L.bc = lt ? (c * kChunksPerCluster + ch) : L.bc;
-    L.best = fminf(L.best, me);
+    const float v = __builtin_fmaf(2.0f, fminf(m0, m1), pp);
+    // an all-padding chunk has v = +inf: keep lo = hi = +inf (no inf - inf)
+    const float e = fminf(0x1.0p-22f * fabsf(v) + delta, 1e38f);
+    const float lo = v - e, hi = v + e;
+    const bool better = hi < L.H;
+    L.S = fminf(L.S, better ? L.loA : lo);
+    L.loA = better ? lo : L.loA;
+    L.A = better ? (c * kChunksPerCluster + ch) : L.A;
+    L.H = fminf(L.H, hi);
   }
 }
 
-__global__ __launch_bounds__(64) void nn_kernel(const SlotDesc* __restrict__ descs,
-                                                const SlotState* __restrict__ states,
-                                                WorkList* __restrict__ wl) {
-  __shared__ float4 s_tgt[kCluster];
+
+__device__ __forceinline__ int find_slot(const int* __restrict__ base, int n_active, int g) {
+  int lo = 0, hi = n_active - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Transformed source point of this lane and its warm-start bound W (the exact
+// FP32 squared distance to the previous pass's closest target, inflated so
+// that it bounds the exact minimum: d2 >= e (1 - gamma)).
+__device__ __forceinline__ void lane_point(const SlotDesc& D, const double* T, int si, bool valid,
+                                           bool use_prev, float& ptx, float& pty, float& ptz,
+                                           float& W) {
+  ptx = pty = ptz = 0.f;
+  W = __builtin_inff();
+  if (!valid) return;
+  xform_f32(T, D.px[si], D.py[si], D.pz[si], ptx, pty, ptz);
+  if (use_prev) {
+    const int prev = D.nnidx[si];
+    if (prev >= 0 && prev < D.N) {
+      const float dx = ptx - D.qx[prev], dy = pty - D.qy[prev], dz = ptz - D.qz[prev];
+      const float d = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+      W = d * (1.0f + 4e-6f) + 1e-37f;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ cull kernel
+// One wavefront per tile of 64 sources. Cluster mode: candidate clusters from
+// the transformed tile sphere against super-cluster and cluster AABBs, then
+// (with warm bounds) only the clusters some lane can still need, tested per
+// lane against the boxes staged in LDS. Writes the list and the tile record
+// (flags, count, slice length, nearest cluster) and queues the slices.
+__global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict__ descs,
+                                                     const SlotState* __restrict__ states,
+                                                     WorkList* __restrict__ wl) {
+  __shared__ float4 s_box[kCluster];
   __shared__ int s_cand[kCandCap];
   __shared__ int s_sup[kSupCap];
-
   const int lane = threadIdx.x;
   for (;;) {
     int g = 0;
     if (lane == 0) g = atomicAdd(&wl->nn_counter, 1);
     g = __shfl(g, 0, 64);
     if (g >= wl->nn_total) break;
-    // decode (slot, tile, split) by binary search over the active prefix
-    int lo = 0, hi = wl->n_active - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (wl->nn_base[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    const int slot = wl->slot[lo];
-    const SlotDesc& D = descs[slot];
-    const SlotState& S = states[slot];
-    const int local = g - wl->nn_base[lo];
-    const int split = D.split;
-    const int tile = local / split;
-    const int sp = local - tile * split;
+    const int a = find_slot(wl->nn_base, wl->n_active, g);
+    const SlotDesc& D = descs[wl->slot[a]];
+    const SlotState& S = states[wl->slot[a]];
+    const int tile = g - wl->nn_base[a];
     const int si = tile * kTile + lane;
     const bool valid = si < D.M;
     const double* T = S.Teval;
-
-    float ptx = 0.f, pty = 0.f, ptz = 0.f;
-    if (valid) xform_f32(T, D.px[si], D.py[si], D.pz[si], ptx, pty, ptz);
-
-    LaneBest L{__builtin_inff(), __builtin_inff(), -1};
-    const float rho = D.rho_max;
-
-    // ----------------------------------------------------------------- candidates
-    int ncand = 0;       // list length (cluster mode)
-    bool use_list = false;
-    int first = -1;      // nearest cluster (processed first by every split)
-    if (D.method == NN_CLUSTER) {
+    int flags = 0, n = 0, first = -1;
+    if (D.method == NN_BRUTE) {
+      flags = TI_RANGE;
+      n = D.ncl;
+    } else {
+      float ptx, pty, ptz, W;
+      lane_point(D, T, si, valid, true, ptx, pty, ptz, W);
+      const bool warm = __all(!valid || W < __builtin_inff());
       const double4 ts = D.tsph[tile];
       float cx, cy, cz;
       {
@@ -179,154 +219,280 @@ __global__ __launch_bounds__(64) void nn_kernel(const SlotDesc* __restrict__ des
       }
       const float cn = sqrtf(cx * cx + cy * cy + cz * cz);
       const float r = (float)ts.w * 1.00001f + 1e-5f * cn + 1e-30f;
-      // level 1: upper bound from super-cluster boxes
-      float U = __builtin_inff();
-      for (int s = lane; s < D.nsup; s += 64) {
-        const float ub = sqrtf(box_ub2(cx, cy, cz, D.slo[s], D.shi[s])) * 1.000001f + r;
-        U = fminf(U, ub);
-      }
+      // every lane's winner lies within U of the tile centre's sphere
+      float U = warm ? sqrtf(wave_max(valid ? winner_threshold(W) : 0.0f)) * 1.000001f + 1e-30f
+                     : __builtin_inff();
+      for (int s2 = lane; s2 < D.nsup; s2 += 64)
+        U = fminf(U, sqrtf(box_ub2(cx, cy, cz, D.slo[s2], D.shi[s2])) * 1.000001f + r);
       U = wave_min(U);
-      // candidate super-clusters
       int nsc = 0;
-      bool overflow = false;
       for (int base = 0; base < D.nsup; base += 64) {
-        const int s = base + lane;
+        const int s2 = base + lane;
         bool c = false;
-        if (s < D.nsup) {
-          const float lb = sqrtf(box_lb2(cx, cy, cz, D.slo[s], D.shi[s])) * 0.999999f - r;
-          c = lb <= U * 1.00001f;
-        }
+        if (s2 < D.nsup) c = sqrtf(box_lb2(cx, cy, cz, D.slo[s2], D.shi[s2])) * 0.999999f - r <= U * 1.00001f;
         const unsigned long long bal = __ballot(c);
         const int pos = nsc + __popcll(bal & ((1ull << lane) - 1ull));
-        if (c && pos < kSupCap) s_sup[pos] = s;
+        if (c && pos < kSupCap) s_sup[pos] = s2;
         nsc += __popcll(bal);
       }
-      if (nsc > kSupCap) overflow = true;
       __syncthreads();
-      // expand candidate super-clusters to clusters
-      float bestub = __builtin_inff();
-      int bestc = 0x7fffffff;
-      const int nflat = overflow ? 0 : nsc * kSuper;
-      for (int base = 0; base < nflat; base += 64) {
-        const int f = base + lane;
-        bool c = false;
-        int cid = 0;
-        if (f < nflat) {
-          cid = s_sup[f / kSuper] * kSuper + (f % kSuper);
-          if (cid < D.ncl) {
+      const int nflat = nsc > kSupCap ? D.ncl : nsc * kSuper;  // all clusters on overflow
+      auto flat_cluster = [&](int f) -> int {
+        if (nsc > kSupCap) return f;
+        const int c = s_sup[f / kSuper] * kSuper + (f % kSuper);
+        return c < D.ncl ? c : -1;
+      };
+      if (warm) {
+        // Stream the candidate clusters in batches of 64: tile-level test, then
+        // every lane tests the batch's boxes (staged in LDS) against its own
+        // bound; the clusters some lane needs are appended to the list.
+        const float thr = winner_threshold(W);
+        int n2 = 0;
+        for (int base = 0; base < nflat; base += 64) {
+          const int f = base + lane;
+          int cid = f < nflat ? flat_cluster(f) : -1;
+          float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = blo;
+          if (cid >= 0) {
+            blo = D.clo[cid];
+            bhi = D.chi[cid];
+            if (!(sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r <= U * 1.00001f)) cid = -1;
+          }
+          const unsigned long long cand = __ballot(cid >= 0);
+          if (cand == 0ull) continue;
+          __syncthreads();
+          s_box[lane] = blo;
+          s_box[64 + lane] = bhi;
+          __syncthreads();
+          unsigned long long need = 0ull;
+          for (unsigned long long m = cand; m; m &= m - 1ull) {
+            const int j = __builtin_ctzll(m);
+            const float lb2 = box_lb2(ptx, pty, ptz, s_box[j], s_box[64 + j]);
+            if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr)) need |= 1ull << j;
+          }
+          const int pos = n2 + __popcll(need & ((1ull << lane) - 1ull));
+          if (((need >> lane) & 1ull) && pos < kListCap) D.clist[(size_t)tile * kListCap + pos] = cid;
+          n2 += __popcll(need);
+        }
+        if (n2 > kListCap || n2 == 0) {
+          // more needed clusters than a list holds (or none, which valid lanes
+          // exclude): slices over all clusters, tested per lane
+          flags = TI_RANGE | TI_LANETEST | TI_WARM;
+          n = D.ncl;
+        } else {
+          flags = TI_LIST | TI_WARM;
+          n = n2;
+        }
+      } else {
+        // No warm start (first pass): tile-level candidates, tightened by the
+        // best cluster upper bound; the nearest cluster seeds every slice.
+        float bestub = __builtin_inff();
+        int bestc = 0x7fffffff;
+        int ncand = 0;
+        for (int base = 0; base < nflat; base += 64) {
+          const int f = base + lane;
+          bool c = false;
+          const int cid = f < nflat ? flat_cluster(f) : -1;
+          if (cid >= 0) {
             const float4 blo = D.clo[cid], bhi = D.chi[cid];
             const float lb = sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r;
             const float ub = sqrtf(box_ub2(cx, cy, cz, blo, bhi)) * 1.000001f + r;
             if (ub < bestub || (ub == bestub && cid < bestc)) { bestub = ub; bestc = cid; }
             c = lb <= U * 1.00001f;
           }
+          const unsigned long long bal = __ballot(c);
+          const int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
+          if (c && pos < kCandCap) s_cand[pos] = cid;
+          ncand += __popcll(bal);
         }
-        const unsigned long long bal = __ballot(c);
-        const int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
-        if (c && pos < kCandCap) s_cand[pos] = cid;
-        ncand += __popcll(bal);
-      }
-      // tightest upper bound and the cluster achieving it
-      float Uc = wave_min(bestub);
-      int cand_first = (bestub == Uc) ? bestc : 0x7fffffff;
-      // lowest cluster id among lanes achieving the minimum
-      for (int o = 32; o > 0; o >>= 1) cand_first = min(cand_first, __shfl_xor(cand_first, o, 64));
-      if (overflow || ncand > kCandCap || nflat == 0) {
-        use_list = false;
-        first = 0;
-      } else {
-        use_list = true;
-        first = cand_first;
-        U = fminf(U, Uc);
-        // compact: keep clusters whose lower bound is within the final bound
-        __syncthreads();
-        int n2 = 0;
-        for (int base = 0; base < ncand; base += 64) {
-          const int f = base + lane;
-          int cid = 0;
-          bool keep = false;
-          if (f < ncand) {
-            cid = s_cand[f];
-            const float lb = sqrtf(box_lb2(cx, cy, cz, D.clo[cid], D.chi[cid])) * 0.999999f - r;
-            keep = lb <= U * 1.00001f && cid != first;
+        const float Uc = wave_min(bestub);
+        int cfirst = (bestub == Uc) ? bestc : 0x7fffffff;
+        for (int o = 32; o > 0; o >>= 1) cfirst = min(cfirst, __shfl_xor(cfirst, o, 64));
+        first = cfirst;
+        if (ncand > kListCap) {
+          flags = TI_RANGE | TI_LANETEST;
+          n = D.ncl;
+        } else {
+          U = fminf(U, Uc);
+          __syncthreads();
+          int n2 = 0;
+          for (int base = 0; base < ncand; base += 64) {
+            const int f = base + lane;
+            int cid = -1;
+            if (f < ncand) {
+              cid = s_cand[f];
+              const float lb = sqrtf(box_lb2(cx, cy, cz, D.clo[cid], D.chi[cid])) * 0.999999f - r;
+              if (!(lb <= U * 1.00001f) || cid == first) cid = -1;
+            }
+            const unsigned long long keep = __ballot(cid >= 0);
+            const int pos = n2 + __popcll(keep & ((1ull << lane) - 1ull));
+            if (cid >= 0) D.clist[(size_t)tile * kListCap + pos] = cid;
+            n2 += __popcll(keep);
           }
-          const unsigned long long bal = __ballot(keep);
-          const int pos = n2 + __popcll(bal & ((1ull << lane) - 1ull));
-          __syncthreads();
-          if (keep) s_cand[pos] = cid;
-          n2 += __popcll(bal);
-          __syncthreads();
+          flags = TI_LIST | TI_LANETEST;
+          n = n2;
         }
-        ncand = n2;
       }
       __syncthreads();
     }
+    // slices: brute mode uses the pair's split count, cluster mode a length
+    int len, nsl;
+    if (D.method == NN_BRUTE) {
+      len = (n + D.split - 1) / D.split;
+      nsl = (n + len - 1) / len;
+    } else {
+      len = max(kSliceMin, (n + kMaxSlices - 1) / kMaxSlices);
+      nsl = max(1, (n + len - 1) / len);
+    }
+    int base = 0;
+    if (lane == 0) {
+      D.tinfo[tile] = make_int4(flags, n, len, first);
+      base = atomicAdd(D.scount, nsl);
+    }
+    base = __shfl(base, 0, 64);
+    for (int k = lane; k < nsl; k += 64) D.squeue[base + k] = make_int2(tile, k);
+  }
+}
 
-    // ----------------------------------------------------------------- filter pass
-    const float4* __restrict__ qloc = D.qloc;
-    const bool culled = D.method == NN_CLUSTER;
-    // iteration space: position -1 is the nearest cluster (cluster mode), then
-    // this split's share of the list (or of all clusters)
-    const int count = culled ? (use_list ? ncand : D.ncl) : D.ncl;
-    int it = culled ? -1 : sp;
-    const int step = culled ? 1 : split;
-    // in cluster mode the split takes list positions sp, sp + split, ...
-    for (;;) {
-      int c;
-      if (culled) {
-        if (it < 0) {
-          c = first;
-        } else {
-          const int pos = sp + it * split;
-          if (pos >= count) break;
-          c = use_list ? s_cand[pos] : pos;
-          if (!use_list && c == first) { it += step; continue; }
-        }
-      } else {
-        if (it >= count) break;
-        c = it;
-      }
+// Exclusive prefix of the per-pair slice counts (one block).
+__global__ __launch_bounds__(1024) void slice_plan_kernel(const SlotDesc* __restrict__ descs,
+                                                          WorkList* __restrict__ wl) {
+  __shared__ int s[1024];
+  const int t = threadIdx.x;
+  const int na = wl->n_active;
+  int v = 0;
+  if (t < na && wl->nn_base[t + 1] > wl->nn_base[t]) v = *descs[wl->slot[t]].scount;
+  s[t] = v;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int x = t >= o ? s[t - o] : 0;
+    __syncthreads();
+    s[t] += x;
+    __syncthreads();
+  }
+  if (t < na) wl->s_base[t] = s[t] - v;
+  if (t == 1023) {
+    wl->s_base[na] = s[1023];
+    wl->s_total = s[1023];
+    wl->s_counter = 0;
+  }
+}
+
+// ------------------------------------------------------------------ slice kernel
+__global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict__ descs,
+                                                      const SlotState* __restrict__ states,
+                                                      WorkList* __restrict__ wl) {
+  __shared__ float4 s_tgt[kCluster];
+  const int lane = threadIdx.x;
+  for (;;) {
+    int g = 0;
+    if (lane == 0) g = atomicAdd(&wl->s_counter, 1);
+    g = __shfl(g, 0, 64);
+    if (g >= wl->s_total) break;
+    const int a = find_slot(wl->s_base, wl->n_active, g);
+    const SlotDesc& D = descs[wl->slot[a]];
+    const SlotState& S = states[wl->slot[a]];
+    const int local = g - wl->s_base[a];
+    const long long t_begin = D.item_stats ? (long long)__builtin_readcyclecounter() : 0ll;
+    const int2 q = D.squeue[local];
+    const int tile = q.x, sl = q.y;
+    const int4 ti = D.tinfo[tile];
+    const int flags = ti.x, n = ti.y, len = ti.z, first = ti.w;
+    const int si = tile * kTile + lane;
+    const bool valid = si < D.M;
+    float ptx, pty, ptz, W;
+    lane_point(D, S.Teval, si, valid, (flags & TI_WARM) != 0, ptx, pty, ptz, W);
+    const int p0 = sl * len, p1 = min(n, p0 + len);
+    const int* __restrict__ list = D.clist + (size_t)tile * kListCap;
+    const bool from_list = (flags & TI_LIST) != 0;
+    const bool lane_test = (flags & TI_LANETEST) != 0;
+    // cluster sequence of this slice: [nearest first,] positions p0 .. p1 - 1
+    auto cluster_at = [&](int k) -> int {
+      if (k < 0) return first;
+      const int pos = p0 + k;
+      if (pos >= p1) return -2;
+      const int c = from_list ? list[pos] : pos;
+      return (!from_list && c == first) ? -1 : c;
+    };
+    const int k0 = first >= 0 ? -1 : 0;
+
+    LaneBest L{__builtin_inff(), __builtin_inff(), __builtin_inff(), -1};
+    int nproc = 0;
+    for (int k = k0;; ++k) {
+      const int c = cluster_at(k);
+      if (c == -2) break;
+      if (c < 0) continue;
       const float4 cc = D.ccen[c];
       const float plx = ptx - cc.x, ply = pty - cc.y, plz = ptz - cc.z;
-      if (culled && it >= 0) {
+      if (lane_test && k >= 0) {
+        // every target of the cluster is at exact squared distance >= lb2
         const float lb2 = box_lb2(ptx, pty, ptz, D.clo[c], D.chi[c]);
-        const float pl = sqrtf(__builtin_fmaf(plz, plz, __builtin_fmaf(ply, ply, plx * plx))) + cc.w;
-        const float lbv = lb2 * (1.0f - 0x1.0p-20f) - 0x1.0p-20f * 8.0f * pl * pl;
-        const bool need = valid && lbv <= ambiguity_threshold(L.best, rho);
-        if (!__any(need)) { it += step; continue; }
+        const bool need = valid && lb2 * (1.0f - 0x1.0p-20f) <= winner_threshold(fminf(L.H, W));
+        if (!__any(need)) continue;
       }
       __syncthreads();
-      s_tgt[lane] = qloc[c * kCluster + lane];
-      s_tgt[lane + 64] = qloc[c * kCluster + 64 + lane];
+      s_tgt[lane] = D.qloc[c * kCluster + lane];
+      s_tgt[lane + 64] = D.qloc[c * kCluster + 64 + lane];
       __syncthreads();
-      filter_cluster(s_tgt, c, plx, ply, plz, L);
-      it += step;
+      filter_cluster(s_tgt, c, plx, ply, plz, cc.w, L);
+      ++nproc;
     }
+    const long long t_filter = D.item_stats ? (long long)__builtin_readcyclecounter() : 0ll;
 
-    // ----------------------------------------------------------------- exact resolution
-    if (valid && L.bc >= 0) {
-      unsigned long long key = ~0ull;
-      const bool amb = L.second <= ambiguity_threshold(L.best, rho);
-      if (!amb) {
-        key = exact_scan(D.qorg, L.bc * kChunk, kChunk, ptx, pty, ptz, key);
-      } else {
-        // rescan every cluster this work item could have visited
-        if (culled) {
-          key = exact_scan(D.qorg, first * kCluster, kCluster, ptx, pty, ptz, key);
-          for (int i2 = 0;; ++i2) {
-            const int pos = sp + i2 * split;
-            if (pos >= count) break;
-            const int c = use_list ? s_cand[pos] : pos;
-            if (!use_list && c == first) continue;
-            key = exact_scan(D.qorg, c * kCluster, kCluster, ptx, pty, ptz, key);
-          }
-        } else {
-          for (int c = sp; c < D.ncl; c += split)
-            key = exact_scan(D.qorg, c * kCluster, kCluster, ptx, pty, ptz, key);
+    // Resolution. A slice matters for a lane only if one of its chunks can
+    // hold the lane's winner (certified lower bound within the warm bound).
+    // Then: a unique winning chunk is rescanned with the exact definition;
+    // otherwise (near-ties, duplicates) the wavefront re-runs the slice's
+    // clusters through LDS with the exact definition for those lanes.
+    const bool has = valid && L.A >= 0 && fminf(L.loA, L.S) <= winner_threshold(W);
+    const bool amb = has && L.S <= winner_threshold(L.H);
+    unsigned long long key = ~0ull;
+    int nexact = 0;
+    if (has && !amb) {
+      key = exact_scan(D.qorg, L.A * kChunk, kChunk, ptx, pty, ptz, key);
+      nexact = kChunk;
+    }
+    if (__any(amb)) {
+      const float thr = winner_threshold(fminf(L.H, W));
+      for (int k = k0;; ++k) {
+        const int c = cluster_at(k);
+        if (c == -2) break;
+        if (c < 0) continue;
+        const float lb2 = box_lb2(ptx, pty, ptz, D.clo[c], D.chi[c]);
+        const bool need = amb && lb2 * (1.0f - 0x1.0p-20f) <= thr;
+        if (!__any(need)) continue;
+        __syncthreads();
+        s_tgt[lane] = D.qorg[c * kCluster + lane];
+        s_tgt[lane + 64] = D.qorg[c * kCluster + 64 + lane];
+        __syncthreads();
+        if (need) {
+          key = exact_scan(s_tgt, 0, kCluster, ptx, pty, ptz, key);
+          nexact += kCluster;
         }
       }
-      if (split == 1) D.keys[si] = key;
-      else atomicMin(&D.keys[si], key);
+    }
+    if (has) atomicMin(&D.keys[si], key);
+    {
+      int nv = valid ? 1 : 0;
+      int ne = nexact;
+      for (int o = 32; o > 0; o >>= 1) {
+        nv += __shfl_xor(nv, o, 64);
+        ne += __shfl_xor(ne, o, 64);
+      }
+      if (lane == 0 && D.stats) {
+        atomicAdd(&D.stats[0], (unsigned long long)nproc * kCluster * (unsigned long long)nv);
+        atomicAdd(&D.stats[1], (unsigned long long)ne);
+      }
+      if (lane == 0 && D.item_stats && local < D.ntile * kMaxSlices) {
+        int* row = D.item_stats + 8 * (size_t)local;
+        row[0] = (int)((long long)__builtin_readcyclecounter() - t_begin);
+        row[1] = nproc;
+        row[2] = n;
+        row[3] = flags | (__any(amb) ? 64 : 0);
+        row[4] = sl;
+        row[5] = len;
+        row[6] = (int)(t_filter - t_begin);
+        row[7] = S.phases;
+      }
     }
     __syncthreads();
   }
@@ -334,7 +500,9 @@ __global__ __launch_bounds__(64) void nn_kernel(const SlotDesc* __restrict__ des
 
 void launch_nn(const SlotDesc* descs, const SlotState* states, WorkList* wl, int grid,
                hipStream_t st) {
-  hipLaunchKernelGGL(nn_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
+  hipLaunchKernelGGL(nn_cull_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
+  hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, wl);
+  hipLaunchKernelGGL(nn_slice_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
 }
 
 }  // namespace icp

@@ -305,7 +305,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__
   int act = 0, nn = 0, ep = 0;
   if (t < capacity && states[t].status == ST_RUNNING) {
     act = 1;
-    nn = states[t].reuse ? 0 : descs[t].ntile * descs[t].split;
+    nn = states[t].reuse ? 0 : descs[t].ntile;
+    if (nn) *descs[t].scount = 0;
     ep = descs[t].nepi;
   }
   s_act[t] = act; s_nn[t] = nn; s_epi[t] = ep;

@@ -38,7 +38,8 @@ def test_params_default_matches_paper():
 
 def test_struct_sizes():
     assert C.sizeof(B.icp_params) == 192
-    assert C.sizeof(B.icp_result) == 184
+    assert C.sizeof(B.icp_result) == 200
+    assert C.sizeof(B.icp_profile_stats) == 32
 
 
 def test_status_strings():
