@@ -1,0 +1,129 @@
+"""Batched and served registration through the C ABI: each result equals the
+same request registered alone (bitwise: per-pair fixed-order reductions, no
+floating-point atomics), requests queue under a tiny HBM budget instead of
+failing, requests submitted while others run are admitted in flight, and the
+ticket protocol hands each result out exactly once."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_07627_amd import binding as B
+from paper_2007_07627_amd import metrics, synth
+
+from gpu_common import announce, ctx  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(count, lo=2000, hi=12000, seed_config=40):
+    reqs = []
+    for d in synth.batch_pairs(count=count, lo=lo, hi=hi, seed_config=seed_config):
+        if d["mode"] == 2:
+            prm = B.icp_params_default(B.ICP_P2PL_WELSCH, anderson_m=6, nu_min=d["nu_min"])
+            reqs.append((d, (d["P"], d["Q"], d["Qn"], prm)))
+        else:
+            prm = B.icp_params_default(B.ICP_P2P_WELSCH, nu_min=d["nu_min"])
+            reqs.append((d, (d["P"], d["Q"], None, prm)))
+    return reqs
+
+
+def _wait(ctx, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t in out:
+                continue
+            rc, r = B.icp_poll(ctx, t)
+            if rc == B.ICP_OK:
+                out[t] = r
+            else:
+                assert rc == B.ICP_ERR_NOT_READY, B.icp_status_str(rc)
+        assert time.time() - t0 < timeout, "batch did not finish"
+        time.sleep(0.002)
+    return [out[t] for t in tickets]
+
+
+def test_batch_equals_alone_bitwise(ctx):
+    reqs = _requests(12)
+    announce("batch of 12 mixed pairs vs alone")
+    tickets = B.icp_batch_submit(ctx, [r for _, r in reqs])
+    assert len(set(tickets)) == len(tickets)
+    res = _wait(ctx, tickets)
+    for (d, (P, Q, Qn, prm)), g in zip(reqs, res):
+        a = B.icp_register(ctx, P, Q, Qn, prm)
+        assert np.array_equal(g["T"], a["T"]), "batched result differs from the pair alone"
+        assert g["nn_passes"] == a["nn_passes"] and g["energy"] == a["energy"]
+        assert g["latency_ms"] > 0
+
+
+def test_batch_alone_vs_mix_and_oracle(ctx):
+    reqs = _requests(6, seed_config=41)
+    d0, r0 = reqs[0]
+    announce("same request alone and inside a mix")
+    alone = _wait(ctx, B.icp_batch_submit(ctx, [r0]))[0]
+    mix = _wait(ctx, B.icp_batch_submit(ctx, [r for _, r in reqs]))[0]
+    assert np.array_equal(alone["T"], mix["T"])
+    # and the pair agrees with the oracle where the oracle reproduces itself
+    mode = 2 if d0["mode"] == 2 else 1
+    m = 6 if mode == 2 else 5
+    o = oracle.register(d0["P"], d0["Q"], d0["Qn"] if mode == 2 else None, mode=mode, anderson_m=m,
+                        nu_min=d0["nu_min"])
+    print("alone-vs-oracle rot", metrics.rotation_error_rad(alone["T"], o["T"]), flush=True)
+    assert metrics.rmse(d0["T_gt"], alone["T"], d0["P"]) < 0.05 * d0["diag"]
+
+
+def test_poll_protocol(ctx):
+    reqs = _requests(1, seed_config=42)
+    t = B.icp_batch_submit(ctx, [reqs[0][1]])[0]
+    _wait(ctx, [t])
+    rc, _ = B.icp_poll(ctx, t)
+    assert rc == B.ICP_ERR_UNKNOWN_TICKET  # handed out once
+    rc, _ = B.icp_poll(ctx, 987654321)
+    assert rc == B.ICP_ERR_UNKNOWN_TICKET
+    bad = list(reqs[0][1])
+    bad[0] = np.full((10, 3), np.nan, np.float32)
+    with pytest.raises(B.ICPError):
+        B.icp_batch_submit(ctx, [tuple(bad)])
+
+
+def test_tiny_budget_queues_instead_of_failing():
+    h = B.icp_create(0, 24 << 20)  # 24 MiB arena: only a few pairs fit at once
+    try:
+        B.icp_batch_config(h, 4, 64)
+        reqs = _requests(10, lo=20000, hi=40000, seed_config=43)
+        announce("tiny budget: 10 pairs through a 24 MiB arena")
+        res = _wait(h, B.icp_batch_submit(h, [r for _, r in reqs]), timeout=300.0)
+        # queued requests complete with the result they have when run alone
+        for (d, (P, Q, Qn, prm)), g in list(zip(reqs, res))[:4]:
+            a = B.icp_register(h, P, Q, Qn, prm)
+            assert np.array_equal(g["T"], a["T"])
+        # a request that can never fit reports OOM instead of waiting forever
+        big = synth.resampled_sphere_pair(synth.rng_for(44, 0), m=300000, n=300000)
+        prm = B.icp_params_default(B.ICP_P2P_WELSCH, nu_min=big["nu_min"])
+        t = B.icp_batch_submit(h, [(big["P"], big["Q"], None, prm)])[0]
+        B.icp_batch_wait_all(h)
+        rc, _ = B.icp_poll(h, t)
+        assert rc == B.ICP_ERR_OOM
+    finally:
+        B.icp_destroy(h)
+
+
+def test_requests_join_in_flight(ctx):
+    """A second wave submitted while the first is running finishes too, and
+    its results equal the same requests run alone."""
+    first = _requests(8, lo=20000, hi=60000, seed_config=45)
+    second = _requests(4, lo=2000, hi=5000, seed_config=46)
+    announce("mid-flight admission")
+    t1 = B.icp_batch_submit(ctx, [r for _, r in first])
+    time.sleep(0.01)
+    t2 = B.icp_batch_submit(ctx, [r for _, r in second])
+    res2 = _wait(ctx, t2)
+    res1 = _wait(ctx, t1)
+    # the small late requests do not wait for the whole first wave
+    assert max(r["latency_ms"] for r in res2) < sum(r["latency_ms"] for r in res1)
+    for (d, (P, Q, Qn, prm)), g in zip(second, res2):
+        a = B.icp_register(ctx, P, Q, Qn, prm)
+        assert np.array_equal(g["T"], a["T"])
