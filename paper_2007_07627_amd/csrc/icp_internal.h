@@ -10,7 +10,7 @@ namespace icp {
 
 constexpr int kTile = 64;        // sources per NN work item (one wavefront)
 constexpr int kCluster = 128;    // targets per cluster of the Morton-ordered index
-constexpr int kChunk = 32;       // targets per deferred-argmin chunk
+constexpr int kChunk = 16;       // targets per deferred-argmin chunk
 constexpr int kChunksPerCluster = kCluster / kChunk;
 constexpr int kSuper = 16;       // clusters per super-cluster (coarse culling level)
 constexpr int kEpiTile = 256;    // sources per reduction work item
@@ -20,7 +20,7 @@ constexpr int kCandCap = 1024;   // LDS candidate list capacity per NN work item
 constexpr int kSupCap = 512;     // LDS candidate super-cluster capacity per NN work item
 constexpr int kMaxSplit = 8;
 constexpr int kListCap = 512;    // candidate clusters stored per tile
-constexpr int kMaxSlices = 16;   // slices per tile in cluster mode
+constexpr int kMaxSlices = 32;   // slices per tile in cluster mode
 constexpr int kSliceMin = 8;     // clusters per slice at least (cluster mode)
 
 // tile record flags (cull kernel -> slice kernel)

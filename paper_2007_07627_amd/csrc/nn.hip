@@ -66,17 +66,30 @@ __device__ __forceinline__ unsigned long long make_key(float d2, int idx) {
 }
 
 // Exact FP32 scan of n targets of the original-coordinate array.
+// Pointers read from a slot descriptor are generic; loading through a global
+// pointer makes the load count only against the vector memory counter
+// (generic loads also hold the LDS counter, which would serialise a prefetch
+// with the LDS work behind it).
+typedef float gv4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 load_global(const float4* p, size_t i) {
+  const gv4f v = ((const __attribute__((address_space(1))) gv4f*)p)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+template <bool kGlobal>
 __device__ __forceinline__ unsigned long long exact_scan(const float4* qorg, int base,
                                                          int n, float px, float py, float pz,
                                                          unsigned long long key) {
-#pragma unroll 8
+  // each target is one 16-byte load issued unconditionally (padding is masked
+  // after the load), so the loads of an unrolled group are in flight together
+#pragma unroll 16
   for (int j = 0; j < n; ++j) {
-    const float4 q = qorg[base + j];
+    const float4 q = kGlobal ? load_global(qorg, (size_t)(base + j)) : qorg[base + j];
     const int id = __float_as_int(q.w);
-    if (id < 0) continue;
     const float dx = px - q.x, dy = py - q.y, dz = pz - q.z;
     const float d = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-    const unsigned long long k = make_key(d, id);
+    // padding (id < 0) maps to the all-ones key by a sign mask, not a branch
+    const unsigned long long k = make_key(d, id) | (unsigned long long)(long long)(id >> 31);
     key = k < key ? k : key;
   }
   return key;
@@ -105,34 +118,39 @@ struct LaneBest {
   int A;  // global chunk id (cluster * 4 + chunk)
 };
 
-// Process one cluster with the filter (all 128 targets, 4 chunks). The filter
-// value of a target is v = 2 (h - pl . ql) + |pl|^2 with pl = p' - cc; its
-// distance to the exact squared distance is at most
-// u (7 (|pl| + rho)^2 + |v|) (rounding of the centred coordinates, of h, of
-// the three FMAs and of the last FMA); 4u is used, so for the chunk minimum v:
+// Lane j's value of a float, as a wave-uniform scalar.
+__device__ __forceinline__ float lane_f(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
+// Process one cluster with the filter (all kCluster targets, in chunks of
+// kChunk) from its copy staged in LDS; every lane reads the same target, so
+// each read is a broadcast. The filter value of a target is
+// v = 2 (pl.(-ql) + h) + |pl|^2 with pl = p' - cc, evaluated as
+// mul, fma, fma, add (4 roundings) then the final fma; its distance to the
+// exact squared distance is at most u (6.6 (|pl| + rho)^2 + |v|); 4u is used
+// with coefficient 7, so for the chunk minimum v:
 // lo = v - 2^-22 |v| - delta, hi = v + 2^-22 |v| + delta,
 // delta = 2^-22 7 (|pl| + rho)^2.
-__device__ __forceinline__ void filter_cluster(const float4* __restrict__ lds, int c, float plx,
+__device__ __forceinline__ void filter_cluster(const float4* __restrict__ tg, int c, float plx,
                                                float ply, float plz, float rho_c, LaneBest& L) {
   const float npx = -plx, npy = -ply, npz = -plz;
   const float pp = __builtin_fmaf(plz, plz, __builtin_fmaf(ply, ply, plx * plx));
   const float t = sqrtf(pp) + rho_c;
   const float delta = 0x1.0p-22f * 7.0f * 1.0001f * t * t;
-#pragma unroll
+#pragma unroll 1
   for (int ch = 0; ch < kChunksPerCluster; ++ch) {
+    const float4* qc = tg + ch * kChunk;
     float m0 = __builtin_inff(), m1 = __builtin_inff();
 #pragma unroll
     for (int j = 0; j < kChunk; j += 4) {
-      const float4 a = lds[ch * kChunk + j];
-      const float4 b = lds[ch * kChunk + j + 1];
-      const float4 c2 = lds[ch * kChunk + j + 2];
-      const float4 d = lds[ch * kChunk + j + 3];
-      const float sa = __builtin_fmaf(npx, a.x, __builtin_fmaf(npy, a.y, __builtin_fmaf(npz, a.z, a.w)));
-      const float sb = __builtin_fmaf(npx, b.x, __builtin_fmaf(npy, b.y, __builtin_fmaf(npz, b.z, b.w)));
-      const float sc = __builtin_fmaf(npx, c2.x, __builtin_fmaf(npy, c2.y, __builtin_fmaf(npz, c2.z, c2.w)));
-      const float sd = __builtin_fmaf(npx, d.x, __builtin_fmaf(npy, d.y, __builtin_fmaf(npz, d.z, d.w)));
+      const float4 a = qc[j], b = qc[j + 1], d = qc[j + 2], e = qc[j + 3];
+      const float sa = __builtin_fmaf(npx, a.x, __builtin_fmaf(npy, a.y, npz * a.z)) + a.w;
+      const float sb = __builtin_fmaf(npx, b.x, __builtin_fmaf(npy, b.y, npz * b.z)) + b.w;
+      const float sd = __builtin_fmaf(npx, d.x, __builtin_fmaf(npy, d.y, npz * d.z)) + d.w;
+      const float se = __builtin_fmaf(npx, e.x, __builtin_fmaf(npy, e.y, npz * e.z)) + e.w;
       m0 = fminf(m0, fminf(sa, sb));
-      m1 = fminf(m1, fminf(sc, sd));
+      m1 = fminf(m1, fminf(sd, se));
     }
     const float v = __builtin_fmaf(2.0f, fminf(m0, m1), pp);
     // an all-padding chunk has v = +inf: keep lo = hi = +inf (no inf - inf)
@@ -192,11 +210,13 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
   for (;;) {
     int g = 0;
     if (lane == 0) g = atomicAdd(&wl->nn_counter, 1);
-    g = __shfl(g, 0, 64);
+    g = __builtin_amdgcn_readfirstlane(__shfl(g, 0, 64));
     if (g >= wl->nn_total) break;
-    const int a = find_slot(wl->nn_base, wl->n_active, g);
-    const SlotDesc& D = descs[wl->slot[a]];
-    const SlotState& S = states[wl->slot[a]];
+    const int a = __builtin_amdgcn_readfirstlane(find_slot(wl->nn_base, wl->n_active, g));
+    // a wave-uniform slot keeps the descriptor's fields in scalar registers
+    const int slot = __builtin_amdgcn_readfirstlane(wl->slot[a]);
+    const SlotDesc& D = descs[slot];
+    const SlotState& S = states[slot];
     const int tile = g - wl->nn_base[a];
     const int si = tile * kTile + lane;
     const bool valid = si < D.M;
@@ -225,12 +245,34 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
       for (int s2 = lane; s2 < D.nsup; s2 += 64)
         U = fminf(U, sqrtf(box_ub2(cx, cy, cz, D.slo[s2], D.shi[s2])) * 1.000001f + r);
       U = wave_min(U);
+      // candidate super-clusters: tile-level test, then (warm) each lane's own
+      // bound against the boxes staged in LDS
       int nsc = 0;
       for (int base = 0; base < D.nsup; base += 64) {
         const int s2 = base + lane;
         bool c = false;
-        if (s2 < D.nsup) c = sqrtf(box_lb2(cx, cy, cz, D.slo[s2], D.shi[s2])) * 0.999999f - r <= U * 1.00001f;
-        const unsigned long long bal = __ballot(c);
+        float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = blo;
+        if (s2 < D.nsup) {
+          blo = D.slo[s2];
+          bhi = D.shi[s2];
+          c = sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r <= U * 1.00001f;
+        }
+        unsigned long long bal = __ballot(c);
+        if (warm && bal) {
+          __syncthreads();
+          s_box[lane] = blo;
+          s_box[64 + lane] = bhi;
+          __syncthreads();
+          const float thr = winner_threshold(W);
+          unsigned long long need = 0ull;
+          for (unsigned long long m = bal; m; m &= m - 1ull) {
+            const int j = __builtin_ctzll(m);
+            const float lb2 = box_lb2(ptx, pty, ptz, s_box[j], s_box[64 + j]);
+            if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr)) need |= 1ull << j;
+          }
+          bal = need;
+          c = (bal >> lane) & 1ull;
+        }
         const int pos = nsc + __popcll(bal & ((1ull << lane) - 1ull));
         if (c && pos < kSupCap) s_sup[pos] = s2;
         nsc += __popcll(bal);
@@ -386,17 +428,19 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
   for (;;) {
     int g = 0;
     if (lane == 0) g = atomicAdd(&wl->s_counter, 1);
-    g = __shfl(g, 0, 64);
+    g = __builtin_amdgcn_readfirstlane(__shfl(g, 0, 64));
     if (g >= wl->s_total) break;
-    const int a = find_slot(wl->s_base, wl->n_active, g);
-    const SlotDesc& D = descs[wl->slot[a]];
-    const SlotState& S = states[wl->slot[a]];
+    const int a = __builtin_amdgcn_readfirstlane(find_slot(wl->s_base, wl->n_active, g));
+    const int slot = __builtin_amdgcn_readfirstlane(wl->slot[a]);
+    const SlotDesc& D = descs[slot];
+    const SlotState& S = states[slot];
     const int local = g - wl->s_base[a];
     const long long t_begin = D.item_stats ? (long long)__builtin_readcyclecounter() : 0ll;
     const int2 q = D.squeue[local];
-    const int tile = q.x, sl = q.y;
+    const int tile = __builtin_amdgcn_readfirstlane(q.x), sl = __builtin_amdgcn_readfirstlane(q.y);
     const int4 ti = D.tinfo[tile];
-    const int flags = ti.x, n = ti.y, len = ti.z, first = ti.w;
+    const int flags = __builtin_amdgcn_readfirstlane(ti.x), n = __builtin_amdgcn_readfirstlane(ti.y);
+    const int len = __builtin_amdgcn_readfirstlane(ti.z), first = __builtin_amdgcn_readfirstlane(ti.w);
     const int si = tile * kTile + lane;
     const bool valid = si < D.M;
     float ptx, pty, ptz, W;
@@ -405,36 +449,73 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     const int* __restrict__ list = D.clist + (size_t)tile * kListCap;
     const bool from_list = (flags & TI_LIST) != 0;
     const bool lane_test = (flags & TI_LANETEST) != 0;
-    // cluster sequence of this slice: [nearest first,] positions p0 .. p1 - 1
-    auto cluster_at = [&](int k) -> int {
-      if (k < 0) return first;
-      const int pos = p0 + k;
-      if (pos >= p1) return -2;
+    // cluster sequence of this slice: entry 0 is the nearest cluster when the
+    // tile has one, then positions p0 .. p1 - 1 (-1: skip)
+    const int lead = first >= 0 ? 1 : 0;
+    const int nent = lead + max(0, p1 - p0);
+    auto cluster_at = [&](int e) -> int {
+      if (e < lead) return first;
+      const int pos = p0 + e - lead;
       const int c = from_list ? list[pos] : pos;
       return (!from_list && c == first) ? -1 : c;
     };
-    const int k0 = first >= 0 ? -1 : 0;
 
     LaneBest L{__builtin_inff(), __builtin_inff(), __builtin_inff(), -1};
     int nproc = 0;
-    for (int k = k0;; ++k) {
-      const int c = cluster_at(k);
-      if (c == -2) break;
-      if (c < 0) continue;
-      const float4 cc = D.ccen[c];
-      const float plx = ptx - cc.x, ply = pty - cc.y, plz = ptz - cc.z;
-      if (lane_test && k >= 0) {
-        // every target of the cluster is at exact squared distance >= lb2
-        const float lb2 = box_lb2(ptx, pty, ptz, D.clo[c], D.chi[c]);
-        const bool need = valid && lb2 * (1.0f - 0x1.0p-20f) <= winner_threshold(fminf(L.H, W));
-        if (!__any(need)) continue;
+    // Up to 64 entries at a time: lane j fetches entry j's cluster id, centre
+    // and box in one round trip; the loop reads them across lanes. The next
+    // cluster's targets are loaded into registers while the current one,
+    // staged in LDS, is filtered.
+    for (int gb = 0; gb < nent; gb += 64) {
+      const int e = gb + lane;
+      int myc = -1;
+      float4 mcc = make_float4(0.f, 0.f, 0.f, 0.f), mlo = mcc, mhi = mcc;
+      if (e < nent) {
+        myc = cluster_at(e);
+        if (myc >= 0) {
+          mcc = D.ccen[myc];
+          if (lane_test) {
+            mlo = D.clo[myc];
+            mhi = D.chi[myc];
+          }
+        }
       }
-      __syncthreads();
-      s_tgt[lane] = D.qloc[c * kCluster + lane];
-      s_tgt[lane + 64] = D.qloc[c * kCluster + 64 + lane];
-      __syncthreads();
-      filter_cluster(s_tgt, c, plx, ply, plz, cc.w, L);
-      ++nproc;
+      const int gn = min(64, nent - gb);
+      const unsigned long long live = __ballot(lane < gn && myc >= 0);
+      if (live == 0ull) continue;
+      int j = __builtin_ctzll(live);
+      int c = __builtin_amdgcn_readlane(myc, j);
+      float4 r0 = load_global(D.qloc, (size_t)c * kCluster + lane);
+      float4 r1 = load_global(D.qloc, (size_t)c * kCluster + 64 + lane);
+      for (unsigned long long rest = live & (live - 1ull);; rest &= rest - 1ull) {
+        __syncthreads();
+        s_tgt[lane] = r0;
+        s_tgt[lane + 64] = r1;
+        __syncthreads();
+        const int jn = rest ? __builtin_ctzll(rest) : -1;
+        const int cn = rest ? __builtin_amdgcn_readlane(myc, jn) : -1;
+        if (cn >= 0) {
+          r0 = load_global(D.qloc, (size_t)cn * kCluster + lane);
+          r1 = load_global(D.qloc, (size_t)cn * kCluster + 64 + lane);
+        }
+        bool run = true;
+        if (lane_test && gb + j >= lead) {
+          // every target of the cluster is at exact squared distance >= lb2
+          const float4 blo = make_float4(lane_f(mlo.x, j), lane_f(mlo.y, j), lane_f(mlo.z, j), 0.f);
+          const float4 bhi = make_float4(lane_f(mhi.x, j), lane_f(mhi.y, j), lane_f(mhi.z, j), 0.f);
+          const float lb2 = box_lb2(ptx, pty, ptz, blo, bhi);
+          run = __any(valid && lb2 * (1.0f - 0x1.0p-20f) <= winner_threshold(fminf(L.H, W)));
+        }
+        if (run) {
+          const float plx = ptx - lane_f(mcc.x, j), ply = pty - lane_f(mcc.y, j),
+                      plz = ptz - lane_f(mcc.z, j);
+          filter_cluster(s_tgt, c, plx, ply, plz, lane_f(mcc.w, j), L);
+          ++nproc;
+        }
+        if (cn < 0) break;
+        j = jn;
+        c = cn;
+      }
     }
     const long long t_filter = D.item_stats ? (long long)__builtin_readcyclecounter() : 0ll;
 
@@ -448,14 +529,13 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     unsigned long long key = ~0ull;
     int nexact = 0;
     if (has && !amb) {
-      key = exact_scan(D.qorg, L.A * kChunk, kChunk, ptx, pty, ptz, key);
+      key = exact_scan<true>(D.qorg, L.A * kChunk, kChunk, ptx, pty, ptz, key);
       nexact = kChunk;
     }
     if (__any(amb)) {
       const float thr = winner_threshold(fminf(L.H, W));
-      for (int k = k0;; ++k) {
-        const int c = cluster_at(k);
-        if (c == -2) break;
+      for (int e = 0; e < nent; ++e) {
+        const int c = __builtin_amdgcn_readfirstlane(cluster_at(e));
         if (c < 0) continue;
         const float lb2 = box_lb2(ptx, pty, ptz, D.clo[c], D.chi[c]);
         const bool need = amb && lb2 * (1.0f - 0x1.0p-20f) <= thr;
@@ -465,7 +545,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
         s_tgt[lane + 64] = D.qorg[c * kCluster + 64 + lane];
         __syncthreads();
         if (need) {
-          key = exact_scan(s_tgt, 0, kCluster, ptx, pty, ptz, key);
+          key = exact_scan<false>(s_tgt, 0, kCluster, ptx, pty, ptz, key);
           nexact += kCluster;
         }
       }

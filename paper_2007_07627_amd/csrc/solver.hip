@@ -195,7 +195,7 @@ __device__ void sym4_top(double A[16], double q[4], double& l0, double& l1) {
         tot += A[4 * i + j] * A[4 * i + j];
         if (i != j) off += A[4 * i + j] * A[4 * i + j];
       }
-    if (off <= 1e-32 * tot || off == 0.0) break;
+    if (off <= 1e-30 * tot || off == 0.0) break;
     for (int p = 0; p < 3; ++p)
       for (int r = p + 1; r < 4; ++r) {
         const double apr = A[4 * p + r];
@@ -250,19 +250,11 @@ __device__ unsigned align_p2p(const double* mom, const double cP[3], const doubl
                   Sxy - Syx,       Szx + Sxz,        Syz + Szy,        -Sxx - Syy + Szz};
   double q[4], l0, l1;
   sym4_top(N, q, l0, l1);
+  // rank test: for a proper optimum the two largest eigenvalues of the
+  // quaternion matrix differ by 2 (s1 + s2) (singular values of S), so a
+  // vanishing gap means rank(S) <= 1 and the rotation is not determined
   unsigned flags = 0;
-  // rank test on S through S^T S (singular values squared)
-  {
-    double M[9];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        M[3 * i + j] = S[i] * S[j] + S[3 + i] * S[3 + j] + S[6 + i] * S[6 + j];
-    // eigenvalues of the symmetric 3x3 via the 4x4 routine on a padded matrix
-    double P[16] = {M[0], M[1], M[2], 0, M[3], M[4], M[5], 0, M[6], M[7], M[8], 0, 0, 0, 0, -1.0};
-    double qq[4], e0, e1;
-    sym4_top(P, qq, e0, e1);
-    if (!(e1 > 1e-24 * e0)) flags |= F_DEGENERATE;
-  }
+  if (!(l0 - l1 > 1e-12 * fabs(l0))) flags |= F_DEGENERATE;
   const double q0 = q[0], qx = q[1], qy = q[2], qz = q[3];
   double R[9] = {q0 * q0 + qx * qx - qy * qy - qz * qz, 2.0 * (qx * qy - q0 * qz), 2.0 * (qx * qz + q0 * qy),
                  2.0 * (qy * qx + q0 * qz), q0 * q0 - qx * qx + qy * qy - qz * qz, 2.0 * (qy * qz - q0 * qx),
