@@ -28,7 +28,7 @@ namespace icp {
 void launch_nn(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
 void launch_epi(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
 void launch_solver(const SlotDesc*, SlotState*, int, int*, hipStream_t);
-void launch_boot(SlotState*, int, hipStream_t);
+void launch_boot(const SlotDesc*, SlotState*, int, hipStream_t);
 void launch_median(const SlotDesc*, SlotState*, int, hipStream_t);
 void launch_plan(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
 void launch_aos_to_soa(const float*, int, float*, float*, float*, hipStream_t);
@@ -160,7 +160,7 @@ struct Layout {
     const size_t sw = std::max(sort_scratch_words(std::max(M, N)) * 4, (size_t)12 * std::max(M, N));
     o_scratch = add(sw);
     o_trace = add(8ull * kTraceRow * tcap);
-    o_stats = add(16);
+    o_stats = add(8ull * kQueues * kStatStride);
     o_items = add(tcap > 0 ? 32ull * ntile * kMaxSlices : 0);
   }
 };
@@ -196,11 +196,16 @@ struct OwnedRequest {
 };
 
 static void fill_stats(const HostSlot& h, hipStream_t st, icp_result* r) {
-  unsigned long long v[2] = {0ull, 0ull};
+  unsigned long long v[kQueues * kStatStride] = {};
   if (h.mem && hipMemcpyAsync(v, h.mem + h.L.o_stats, sizeof v, hipMemcpyDeviceToHost, st) == hipSuccess &&
       hipStreamSynchronize(st) == hipSuccess) {
-    r->nn_pairs = (double)v[0];
-    r->nn_exact_pairs = (double)v[1];
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < kQueues; ++q) {
+      a += (double)v[q * kStatStride];
+      b += (double)v[q * kStatStride + 1];
+    }
+    r->nn_pairs = a;
+    r->nn_exact_pairs = b;
   }
 }
 
@@ -439,7 +444,7 @@ struct Engine {
                        F(L.o_py), F(L.o_pz), reinterpret_cast<int*>(b + L.o_perm),
                        reinterpret_cast<double4*>(b + L.o_tsph), ss);
     launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_keys), L.M, ~0ull, ss);
-    launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_stats), 2, 0ull, ss);
+    launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_stats), kQueues * kStatStride, 0ull, ss);
     // no previous closest point yet (int32 -1 everywhere)
     launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_nnidx), (L.M + 1) / 2, ~0ull, ss);
     // descriptor (rho_max is written by build_super above, so copy the rest around it)
@@ -494,7 +499,7 @@ struct Engine {
     HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     HIP_OK(hipEventRecord(ev, side));
     HIP_OK(hipStreamWaitEvent(st, ev, 0));
-    launch_boot(d_state, s, st);
+    launch_boot(d_desc, d_state, s, st);
     (void)hipEventDestroy(ev);
     return hipGetLastError() == hipSuccess;
   }

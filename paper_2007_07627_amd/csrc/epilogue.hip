@@ -42,8 +42,8 @@ __global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ d
                                                   const SlotState* __restrict__ states,
                                                   WorkList* __restrict__ wl) {
   __shared__ int s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&wl->epi_counter, 1);
+  for (int round = 0;; ++round) {
+    if (threadIdx.x == 0) s_item = queue_item(wl->q_epi, round);
     __syncthreads();
     const int g = s_item;
     __syncthreads();

@@ -22,6 +22,7 @@ constexpr int kMaxSplit = 8;
 constexpr int kListCap = 512;    // candidate clusters stored per tile
 constexpr int kMaxSlices = 32;   // slices per tile in cluster mode
 constexpr int kSliceMin = 8;     // clusters per slice at least (cluster mode)
+constexpr float kVerletFrac = 0.08f;  // candidate-list margin / median cluster radius
 
 // tile record flags (cull kernel -> slice kernel)
 enum TileFlags { TI_WARM = 1, TI_LIST = 2, TI_RANGE = 4, TI_LANETEST = 8 };
@@ -85,7 +86,8 @@ struct SlotDesc {
   double* medkey;             // per sorted source (setup pass only)
   int32_t* idx_out;           // optional: original-order outputs (queries)
   float* d2_out;
-  unsigned long long* stats;  // [0] pairs through the filter, [1] pairs scanned exactly
+  unsigned long long* stats;  // kQueues lines of kStatStride: [0] pairs through the
+                              // filter, [1] pairs scanned exactly (summed on the host)
   double* trace;              // optional per-pass rows [E, nu, sm, reuse, T(16)]
   int* item_stats;            // optional, last pass: per NN work item
                               // [cycles, clusters filtered, candidates, flags]
@@ -95,6 +97,8 @@ struct SlotDesc {
   int method;                 // NN_BRUTE or NN_CLUSTER
   int mode;
   float rho_max;              // max cluster radius (upper bound)
+  float verlet;               // candidate-list margin: lists built with this
+                              // slack stay valid while no source moves farther
 };
 
 // Per-slot mutable state (device resident; the solver wave owns it).
@@ -124,6 +128,10 @@ struct SlotState {
   int have_last;
   double median;              // written by the median kernel
   double cP[3], cQ[3];        // fixed centring of the moments (bbox centres)
+  double Tref[16];            // transform of the last candidate-list build
+  double verlet;              // list margin (copied from the descriptor at boot)
+  int cull;                   // 1: this pass rebuilds the candidate lists
+  int cull_pad;
   float bbP[6], bbQ[6];       // bounding boxes (min xyz, max xyz)
   // ---- results
   double Tres[16];
@@ -134,21 +142,37 @@ struct SlotState {
   int trace_len;
 };
 
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 64;  // ints between sub-queue counters
+constexpr int kStatStride = 32;  // u64 between per-die statistics lines
+
 // Active-slot work lists rebuilt before every phase.
 struct WorkList {
   int n_active;
   int nn_total;
   int epi_total;
-  int nn_counter;             // dynamic work counters (reset by the planners)
-  int epi_counter;
   int s_total;                // closest-point slices queued this pass
-  int s_counter;
-  int pad;
+  int pad[2];
   int slot[1024];             // compacted active slot ids
   int nn_base[1025];          // prefix of NN items over the compacted list
   int epi_base[1025];
   int s_base[1025];           // prefix of queued slices over the compacted list
+  // dynamic work counters (reset by the planners): kQueues sub-queues each
+  int q_nn[kQueues * kQueueStride];
+  int q_epi[kQueues * kQueueStride];
+  int q_s[kQueues * kQueueStride];
 };
+
+// Work distribution of the persistent kernels. Workgroup b takes item b first
+// without an atomic; later items come from kQueues sub-queues, sub-queue
+// b mod kQueues serving the items gridDim + x + kQueues k. The hardware deals
+// workgroups to its dies in this order, and each counter sits on its own
+// 256-byte line, so the counters' atomics do not serialise on one address.
+__device__ __forceinline__ int queue_item(int* q, int round) {
+  if (round == 0) return (int)blockIdx.x;
+  const int x = (int)(blockIdx.x % kQueues);
+  return (int)gridDim.x + x + kQueues * atomicAdd(&q[x * kQueueStride], 1);
+}
 
 constexpr int kMaxSlots = 1024;
 constexpr int kTraceRow = 20;

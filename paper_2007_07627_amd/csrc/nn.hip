@@ -207,9 +207,9 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
   __shared__ int s_cand[kCandCap];
   __shared__ int s_sup[kSupCap];
   const int lane = threadIdx.x;
-  for (;;) {
+  for (int round = 0;; ++round) {
     int g = 0;
-    if (lane == 0) g = atomicAdd(&wl->nn_counter, 1);
+    if (lane == 0) g = queue_item(wl->q_nn, round);
     g = __builtin_amdgcn_readfirstlane(__shfl(g, 0, 64));
     if (g >= wl->nn_total) break;
     const int a = __builtin_amdgcn_readfirstlane(find_slot(wl->nn_base, wl->n_active, g));
@@ -245,6 +245,15 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
       for (int s2 = lane; s2 < D.nsup; s2 += 64)
         U = fminf(U, sqrtf(box_ub2(cx, cy, cz, D.slo[s2], D.shi[s2])) * 1.000001f + r);
       U = wave_min(U);
+      // Warm lists are kept for later passes while every source stays within
+      // the margin of its position now; a later pass's winner is then within
+      // its bound here plus twice the margin (the point and its winner's
+      // distance each move by at most the margin).
+      const float margin = warm ? 2.0f * D.verlet : 0.0f;
+      U += margin;
+      // per-lane bound with the margin: (sqrt(thr(W)) + margin)^2, rounded up
+      const float bw = sqrtf(winner_threshold(W)) * (1.0f + 0x1.0p-20f) + margin;
+      const float thr_m = bw * bw * (1.0f + 0x1.0p-20f);
       // candidate super-clusters: tile-level test, then (warm) each lane's own
       // bound against the boxes staged in LDS
       int nsc = 0;
@@ -263,7 +272,7 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
           s_box[lane] = blo;
           s_box[64 + lane] = bhi;
           __syncthreads();
-          const float thr = winner_threshold(W);
+          const float thr = thr_m;
           unsigned long long need = 0ull;
           for (unsigned long long m = bal; m; m &= m - 1ull) {
             const int j = __builtin_ctzll(m);
@@ -288,7 +297,7 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
         // Stream the candidate clusters in batches of 64: tile-level test, then
         // every lane tests the batch's boxes (staged in LDS) against its own
         // bound; the clusters some lane needs are appended to the list.
-        const float thr = winner_threshold(W);
+        const float thr = thr_m;
         int n2 = 0;
         for (int base = 0; base < nflat; base += 64) {
           const int f = base + lane;
@@ -397,12 +406,15 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
 
 // Exclusive prefix of the per-pair slice counts (one block).
 __global__ __launch_bounds__(1024) void slice_plan_kernel(const SlotDesc* __restrict__ descs,
+                                                          const SlotState* __restrict__ states,
                                                           WorkList* __restrict__ wl) {
   __shared__ int s[1024];
   const int t = threadIdx.x;
   const int na = wl->n_active;
   int v = 0;
-  if (t < na && wl->nn_base[t + 1] > wl->nn_base[t]) v = *descs[wl->slot[t]].scount;
+  // slots that search this pass: their slices from this pass's cull or, when
+  // the lists are reused, from the last one
+  if (t < na && !states[wl->slot[t]].reuse) v = *descs[wl->slot[t]].scount;
   s[t] = v;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -411,11 +423,11 @@ __global__ __launch_bounds__(1024) void slice_plan_kernel(const SlotDesc* __rest
     s[t] += x;
     __syncthreads();
   }
+  if (t < kQueues) wl->q_s[t * kQueueStride] = 0;
   if (t < na) wl->s_base[t] = s[t] - v;
   if (t == 1023) {
     wl->s_base[na] = s[1023];
     wl->s_total = s[1023];
-    wl->s_counter = 0;
   }
 }
 
@@ -425,9 +437,9 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
                                                       WorkList* __restrict__ wl) {
   __shared__ float4 s_tgt[kCluster];
   const int lane = threadIdx.x;
-  for (;;) {
+  for (int round = 0;; ++round) {
     int g = 0;
-    if (lane == 0) g = atomicAdd(&wl->s_counter, 1);
+    if (lane == 0) g = queue_item(wl->q_s, round);
     g = __builtin_amdgcn_readfirstlane(__shfl(g, 0, 64));
     if (g >= wl->s_total) break;
     const int a = __builtin_amdgcn_readfirstlane(find_slot(wl->s_base, wl->n_active, g));
@@ -559,8 +571,10 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
         ne += __shfl_xor(ne, o, 64);
       }
       if (lane == 0 && D.stats) {
-        atomicAdd(&D.stats[0], (unsigned long long)nproc * kCluster * (unsigned long long)nv);
-        atomicAdd(&D.stats[1], (unsigned long long)ne);
+        // one statistics line per die keeps these atomics off a single address
+        unsigned long long* st = D.stats + (blockIdx.x % kQueues) * kStatStride;
+        atomicAdd(&st[0], (unsigned long long)nproc * kCluster * (unsigned long long)nv);
+        atomicAdd(&st[1], (unsigned long long)ne);
       }
       if (lane == 0 && D.item_stats && local < D.ntile * kMaxSlices) {
         int* row = D.item_stats + 8 * (size_t)local;
@@ -581,7 +595,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
 void launch_nn(const SlotDesc* descs, const SlotState* states, WorkList* wl, int grid,
                hipStream_t st) {
   hipLaunchKernelGGL(nn_cull_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
-  hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, wl);
+  hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl);
   hipLaunchKernelGGL(nn_slice_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
 }
 

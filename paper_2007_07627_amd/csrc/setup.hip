@@ -249,7 +249,28 @@ __global__ __launch_bounds__(64) void build_super_kernel(const float4* __restric
     shi[s] = hi;
   }
   for (int o = 32; o > 0; o >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, o, 64));
-  if (threadIdx.x == 0) *rho_out = rmax;
+  // Median cluster radius from a histogram with four bins per octave; the
+  // candidate-list margin is a fixed fraction of it (about half the sample
+  // spacing of a surface cluster).
+  __shared__ int hist[256];
+  for (int b = threadIdx.x; b < 256; b += 64) hist[b] = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncl; c += 64) {
+    const float r = ccen[c].w;
+    const int b = r > 0.0f ? (int)floorf((log2f(r) + 48.0f) * 4.0f) : 0;
+    atomicAdd(&hist[min(255, max(0, b))], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0, b = 0;
+    for (; b < 255; ++b) {
+      acc += hist[b];
+      if (2 * acc >= ncl) break;
+    }
+    const float rmed = exp2f((b + 1) * 0.25f - 48.0f);  // upper edge of the median bin
+    rho_out[0] = rmax;
+    rho_out[1] = kVerletFrac * rmed;
+  }
 }
 
 // Sorted source copy and the bounding sphere of each 64-source tile.
@@ -305,7 +326,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__
   int act = 0, nn = 0, ep = 0;
   if (t < capacity && states[t].status == ST_RUNNING) {
     act = 1;
-    nn = states[t].reuse ? 0 : descs[t].ntile;
+    nn = (states[t].reuse || !states[t].cull) ? 0 : descs[t].ntile;
     if (nn) *descs[t].scount = 0;
     ep = descs[t].nepi;
   }
@@ -317,6 +338,10 @@ __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__
     __syncthreads();
     s_act[t] += a; s_nn[t] += b; s_epi[t] += c;
     __syncthreads();
+  }
+  if (t < kQueues) {
+    wl->q_nn[t * kQueueStride] = 0;
+    wl->q_epi[t * kQueueStride] = 0;
   }
   if (act) {
     const int pos = s_act[t] - 1;
@@ -330,8 +355,6 @@ __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__
     wl->epi_total = s_epi[t];
     wl->nn_base[s_act[t]] = s_nn[t];
     wl->epi_base[s_act[t]] = s_epi[t];
-    wl->nn_counter = 0;
-    wl->epi_counter = 0;
   }
 }
 

@@ -381,6 +381,39 @@ __device__ inline void set_nu(SlotState& S, double nu) {
   S.nu_eval = S.mode == P2P_L2 ? 0.0 : nu;
 }
 
+// Candidate lists are rebuilt on the first two passes (the first has no warm
+// bounds) and whenever some source may have moved farther than the margin
+// since the last build: |T p - Tref p| <= ||dR||_F r + |dR c + dt| with c, r
+// the centre and half-diagonal of the source box, plus an allowance for the
+// FP32 rounding of both transformed points.
+__device__ void plan_lists(SlotState& S) {
+  if (S.reuse) return;
+  bool rebuild = S.nn_passes <= 2 || !(S.verlet > 0.0);
+  if (!rebuild) {
+    double fro = 0.0, v2 = 0.0, r2 = 0.0, c2 = 0.0, tt = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double e = 0.5 * ((double)S.bbP[3 + k] - (double)S.bbP[k]);
+      r2 += e * e;
+      c2 += S.cP[k] * S.cP[k];
+      double v = S.Teval[4 * k + 3] - S.Tref[4 * k + 3];
+      for (int j = 0; j < 3; ++j) {
+        const double d = S.Teval[4 * k + j] - S.Tref[4 * k + j];
+        fro += d * d;
+        v += d * S.cP[j];
+      }
+      v2 += v * v;
+      tt += fabs(S.Teval[4 * k + 3]) + fabs(S.Tref[4 * k + 3]);
+    }
+    const double r = sqrt(r2);
+    const double disp = sqrt(fro) * r + sqrt(v2);
+    const double slack = 1e-6 * (sqrt(c2) + r + tt);
+    rebuild = !(disp + slack <= S.verlet);
+  }
+  S.cull = rebuild ? 1 : 0;
+  if (rebuild)
+    for (int i = 0; i < 16; ++i) S.Tref[i] = S.Teval[i];
+}
+
 __device__ void request_T(SlotState& S, const double T[16], double nu) {
   S.evaluations++;
   const bool same = S.have_last && same_bits(S.last_key, T, 16);
@@ -391,6 +424,7 @@ __device__ void request_T(SlotState& S, const double T[16], double nu) {
     S.nn_passes++;
   }
   for (int i = 0; i < 16; ++i) S.Teval[i] = T[i];
+  plan_lists(S);
   set_nu(S, nu);
 }
 
@@ -405,6 +439,7 @@ __device__ void request_xi(SlotState& S, const double xi[6], double nu) {
   }
   twist_exp(xi, S.Teval);
   twist_derivs(xi, S.K);
+  plan_lists(S);
   set_nu(S, nu);
 }
 
@@ -768,9 +803,11 @@ __global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__
 
 // First request of a freshly admitted slot: evaluation at T0 (point-to-plane:
 // at exp(log T0)), then the slot becomes RUNNING.
-__global__ void boot_kernel(SlotState* __restrict__ states, int slot) {
+__global__ void boot_kernel(const SlotDesc* __restrict__ descs, SlotState* __restrict__ states,
+                            int slot) {
   if (threadIdx.x != 0) return;
   SlotState& S = states[slot];
+  S.verlet = descs[slot].method == NN_CLUSTER ? (double)descs[slot].verlet : 0.0;
   S.evaluations = 0;
   S.nn_passes = 0;
   S.have_last = 0;
@@ -840,8 +877,8 @@ void launch_solver(const SlotDesc* descs, SlotState* states, int capacity, int* 
   hipLaunchKernelGGL(solver_kernel, dim3(capacity), dim3(64), 0, st, descs, states, capacity, done);
 }
 
-void launch_boot(SlotState* states, int slot, hipStream_t st) {
-  hipLaunchKernelGGL(boot_kernel, dim3(1), dim3(64), 0, st, states, slot);
+void launch_boot(const SlotDesc* descs, SlotState* states, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(boot_kernel, dim3(1), dim3(64), 0, st, descs, states, slot);
 }
 
 void launch_median(const SlotDesc* descs, SlotState* states, int capacity, hipStream_t st) {
