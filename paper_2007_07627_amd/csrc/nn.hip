@@ -113,9 +113,13 @@ __device__ __forceinline__ float box_ub2(float px, float py, float pz, float4 lo
 // certified upper bound on the exact squared distance of the chunk's best
 // target, A = the chunk attaining H, loA = that chunk's certified lower bound,
 // S = min certified lower bound over all other chunks.
+// Per-lane filter state over the chunks seen so far: A is the chunk with the
+// smallest upper bound H (its lower bound loA); B is the chunk with the
+// smallest lower bound S among the others, and S2 the smallest lower bound
+// of the rest. The winner lies in a chunk whose lower bound is at most H.
 struct LaneBest {
-  float H, loA, S;
-  int A;  // global chunk id (cluster * 4 + chunk)
+  float H, loA, S, S2;
+  int A, B;  // global chunk ids (cluster * kChunksPerCluster + chunk)
 };
 
 // Lane j's value of a float, as a wave-uniform scalar.
@@ -156,10 +160,16 @@ __device__ __forceinline__ void filter_cluster(const float4* __restrict__ tg, in
     // an all-padding chunk has v = +inf: keep lo = hi = +inf (no inf - inf)
     const float e = fminf(0x1.0p-22f * fabsf(v) + delta, 1e38f);
     const float lo = v - e, hi = v + e;
+    const int id = c * kChunksPerCluster + ch;
     const bool better = hi < L.H;
-    L.S = fminf(L.S, better ? L.loA : lo);
+    const float olo = better ? L.loA : lo;  // the chunk that is not (or no longer) A
+    const int oid = better ? L.A : id;
+    const bool nb = olo < L.S;
+    L.S2 = fminf(L.S2, nb ? L.S : olo);
+    L.B = nb ? oid : L.B;
+    L.S = nb ? olo : L.S;
     L.loA = better ? lo : L.loA;
-    L.A = better ? (c * kChunksPerCluster + ch) : L.A;
+    L.A = better ? id : L.A;
     L.H = fminf(L.H, hi);
   }
 }
@@ -472,7 +482,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
       return (!from_list && c == first) ? -1 : c;
     };
 
-    LaneBest L{__builtin_inff(), __builtin_inff(), __builtin_inff(), -1};
+    LaneBest L{__builtin_inff(), __builtin_inff(), __builtin_inff(), __builtin_inff(), -1, -1};
     int nproc = 0;
     // Up to 64 entries at a time: lane j fetches entry j's cluster id, centre
     // and box in one round trip; the loop reads them across lanes. The next
@@ -533,16 +543,23 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
 
     // Resolution. A slice matters for a lane only if one of its chunks can
     // hold the lane's winner (certified lower bound within the warm bound).
-    // Then: a unique winning chunk is rescanned with the exact definition;
-    // otherwise (near-ties, duplicates) the wavefront re-runs the slice's
-    // clusters through LDS with the exact definition for those lanes.
+    // Then the chunks that can hold it (lower bound within the threshold of
+    // H) are rescanned with the exact definition: chunk A, and B too when it
+    // qualifies; when a third chunk qualifies (near-ties, duplicates) the
+    // wavefront re-runs the slice's clusters through LDS for those lanes.
+    const float thr_h = winner_threshold(L.H);
     const bool has = valid && L.A >= 0 && fminf(L.loA, L.S) <= winner_threshold(W);
-    const bool amb = has && L.S <= winner_threshold(L.H);
+    const bool two = has && L.S <= thr_h;
+    const bool amb = two && L.S2 <= thr_h;
     unsigned long long key = ~0ull;
     int nexact = 0;
     if (has && !amb) {
       key = exact_scan<true>(D.qorg, L.A * kChunk, kChunk, ptx, pty, ptz, key);
       nexact = kChunk;
+      if (two) {
+        key = exact_scan<true>(D.qorg, L.B * kChunk, kChunk, ptx, pty, ptz, key);
+        nexact += kChunk;
+      }
     }
     if (__any(amb)) {
       const float thr = winner_threshold(fminf(L.H, W));

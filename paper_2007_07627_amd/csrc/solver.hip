@@ -196,7 +196,10 @@ __device__ void sym4_top(double A[16], double q[4], double& l0, double& l1) {
         if (i != j) off += A[4 * i + j] * A[4 * i + j];
       }
     if (off <= 1e-30 * tot || off == 0.0) break;
+    // fixed (p, r) order, unrolled so that A and V stay in registers
+#pragma unroll
     for (int p = 0; p < 3; ++p)
+#pragma unroll
       for (int r = p + 1; r < 4; ++r) {
         const double apr = A[4 * p + r];
         if (apr == 0.0) continue;
@@ -313,9 +316,14 @@ __device__ unsigned gn_p2pl(const double* mom, const double xi[6], double out[6]
 // Anderson mixing: theta = argmin || F^k - sum_j theta_j dF_j ||^2 in the given
 // metric by normal equations (Cholesky, pivot <= 1e-10 max diag = singular,
 // theta = 0); returns G^k - sum_j theta_j dG_j.
-__device__ bool anderson(const SlotState& S, int k, int mk, int metric, double out[6]) {
+// The history length is a template parameter so that every loop unrolls and
+// the small matrices live in registers.
+template <int mk>
+__device__ bool anderson_mk(const SlotState& S, int k, int metric, double out[6]) {
   double dF[6][6], dG[6][6];
+#pragma unroll
   for (int j = 1; j <= mk; ++j)
+#pragma unroll
     for (int a = 0; a < 6; ++a) {
       dF[j - 1][a] = S.F[(k - j + 1) % kHist][a] - S.F[(k - j) % kHist][a];
       dG[j - 1][a] = S.G[(k - j + 1) % kHist][a] - S.G[(k - j) % kHist][a];
@@ -323,49 +331,75 @@ __device__ bool anderson(const SlotState& S, int k, int mk, int metric, double o
   const double* Fk = S.F[k % kHist];
   const double wr = metric == 0 ? 2.0 : 1.0;
   double N[36], r[6], dmax = 0.0;
+#pragma unroll
   for (int i = 0; i < mk; ++i) {
     r[i] = wr * (dF[i][0] * Fk[0] + dF[i][1] * Fk[1] + dF[i][2] * Fk[2]) + dF[i][3] * Fk[3] +
            dF[i][4] * Fk[4] + dF[i][5] * Fk[5];
+#pragma unroll
     for (int j = 0; j < mk; ++j)
       N[6 * i + j] = wr * (dF[i][0] * dF[j][0] + dF[i][1] * dF[j][1] + dF[i][2] * dF[j][2]) +
                      dF[i][3] * dF[j][3] + dF[i][4] * dF[j][4] + dF[i][5] * dF[j][5];
     dmax = fmax(dmax, N[7 * i]);
   }
   double L[36], th[6];
+#pragma unroll
   for (int i = 0; i < 36; ++i) L[i] = 0.0;
   bool sing = !(dmax > 0.0);
-  for (int j = 0; j < mk && !sing; ++j) {
+#pragma unroll
+  for (int j = 0; j < mk; ++j) {
     double s = N[7 * j];
+#pragma unroll
     for (int kk = 0; kk < j; ++kk) s -= L[6 * j + kk] * L[6 * j + kk];
-    if (!(s > 1e-10 * dmax)) { sing = true; break; }
-    L[7 * j] = sqrt(s);
+    if (!(s > 1e-10 * dmax)) sing = true;
+    L[7 * j] = sing ? 1.0 : sqrt(s);
+#pragma unroll
     for (int i = j + 1; i < mk; ++i) {
       double v = N[6 * i + j];
+#pragma unroll
       for (int kk = 0; kk < j; ++kk) v -= L[6 * i + kk] * L[6 * j + kk];
       L[6 * i + j] = v / L[7 * j];
     }
   }
   if (sing) {
+#pragma unroll
     for (int i = 0; i < mk; ++i) th[i] = 0.0;
   } else {
     double y[6];
+#pragma unroll
     for (int i = 0; i < mk; ++i) {
       double v = r[i];
+#pragma unroll
       for (int kk = 0; kk < i; ++kk) v -= L[6 * i + kk] * y[kk];
       y[i] = v / L[7 * i];
     }
+#pragma unroll
     for (int i = mk - 1; i >= 0; --i) {
       double v = y[i];
+#pragma unroll
       for (int kk = i + 1; kk < mk; ++kk) v -= L[6 * kk + i] * th[kk];
       th[i] = v / L[7 * i];
     }
   }
+#pragma unroll
   for (int a = 0; a < 6; ++a) {
     double v = S.G[k % kHist][a];
+#pragma unroll
     for (int j = 1; j <= mk; ++j) v -= th[j - 1] * dG[j - 1][a];
     out[a] = v;
   }
   return sing;
+}
+
+__device__ bool anderson(const SlotState& S, int k, int mk, int metric, double out[6]) {
+  switch (mk) {
+    case 0: return anderson_mk<0>(S, k, metric, out);
+    case 1: return anderson_mk<1>(S, k, metric, out);
+    case 2: return anderson_mk<2>(S, k, metric, out);
+    case 3: return anderson_mk<3>(S, k, metric, out);
+    case 4: return anderson_mk<4>(S, k, metric, out);
+    case 5: return anderson_mk<5>(S, k, metric, out);
+    default: return anderson_mk<6>(S, k, metric, out);  // m <= 6 is validated at submission
+  }
 }
 
 // ------------------------------------------------------------------ requests
@@ -745,28 +779,67 @@ stage_end:
 
 // Merge the partials of one slot in a fixed order (lane-strided sums, then a
 // fixed shuffle tree) and advance the state machine on lane 0.
+// Sum of the per-tile partial moments in a fixed order: lane l adds tiles
+// l, l + 64, ... in turn, then a fixed butterfly combines the lanes (lane 0
+// holds the result). The value count is a template parameter so that the
+// accumulators stay in registers.
+template <int NV>
+__device__ __forceinline__ void merge_partials(const SlotDesc& D, double* acc) {
+  const int lane = threadIdx.x;
+  double a[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) a[v] = 0.0;
+  for (int e = lane; e < D.nepi; e += 64) {
+    const double* p = D.part + (size_t)e * kPartStride;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a[v] += p[v];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double x = a[v];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    acc[v] = x;
+  }
+#pragma unroll
+  for (int v = NV; v < kP2PLVals; ++v) acc[v] = 0.0;
+}
+
+__device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc);
+
 __global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__ descs,
                                                     SlotState* __restrict__ states, int capacity,
                                                     int* __restrict__ done) {
   const int slot = blockIdx.x;
   if (slot >= capacity) return;
-  SlotState& S = states[slot];
-  if (S.status != ST_RUNNING) return;
+  if (states[slot].status != ST_RUNNING) return;
+  // The state machine runs on an LDS copy of the slot state: its many
+  // dependent reads and writes then cost LDS latency instead of a memory
+  // round trip each. The wavefront copies it in and out cooperatively.
+  static_assert(sizeof(SlotState) % 8 == 0, "slot state is copied in 8-byte words");
+  constexpr int kWords = (int)(sizeof(SlotState) / 8);
+  __shared__ unsigned long long s_state[kWords];
+  {
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(states + slot);
+    for (int i = threadIdx.x; i < kWords; i += 64) s_state[i] = src[i];
+  }
+  __syncthreads();
+  SlotState& S = *reinterpret_cast<SlotState*>(s_state);
   const SlotDesc& D = descs[slot];
-  const int nv = D.mode == P2PL_WELSCH ? kP2PLVals : kP2PVals;
   const int lane = threadIdx.x;
   double acc[kP2PLVals];
-  for (int v = 0; v < kP2PLVals; ++v) acc[v] = 0.0;
-  for (int e = lane; e < D.nepi; e += 64) {
-    const double* p = D.part + (size_t)e * kPartStride;
-    for (int v = 0; v < nv; ++v) acc[v] += p[v];
+  if (D.mode == P2PL_WELSCH) merge_partials<kP2PLVals>(D, acc);
+  else merge_partials<kP2PVals>(D, acc);
+  if (lane == 0) solver_step(D, S, acc);
+  __syncthreads();
+  {
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(states + slot);
+    for (int i = threadIdx.x; i < kWords; i += 64) dst[i] = s_state[i];
   }
-  for (int v = 0; v < kP2PLVals; ++v) {
-    double x = acc[v];
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-    acc[v] = x;
-  }
-  if (lane != 0) return;
+  if (lane == 0 && S.status == ST_DONE) done[slot] = 1;
+}
+
+// One pass of the state machine for a slot (lane 0 of the solver wavefront).
+__device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc) {
   S.phases++;
   if (D.trace && S.trace_len < D.trace_cap) {
     double* row = D.trace + (size_t)S.trace_len * kTraceRow;
@@ -798,7 +871,6 @@ __global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__
   } else {
     step_p2p(S, acc);
   }
-  if (S.status == ST_DONE) done[slot] = 1;
 }
 
 // First request of a freshly admitted slot: evaluation at T0 (point-to-plane:
