@@ -20,8 +20,8 @@ constexpr int kCandCap = 1024;   // LDS candidate list capacity per NN work item
 constexpr int kSupCap = 512;     // LDS candidate super-cluster capacity per NN work item
 constexpr int kMaxSplit = 8;
 constexpr int kListCap = 512;    // candidate clusters stored per tile
-constexpr int kMaxSlices = 32;   // slices per tile in cluster mode
-constexpr int kSliceMin = 8;     // clusters per slice at least (cluster mode)
+constexpr int kMaxSlices = 64;   // slices per tile in cluster mode
+constexpr int kSliceMin = 6;     // clusters per slice at least (cluster mode)
 constexpr float kVerletFrac = 0.08f;  // candidate-list margin / median cluster radius
 
 // tile record flags (cull kernel -> slice kernel)

@@ -130,11 +130,11 @@ __device__ __forceinline__ float lane_f(float v, int j) {
 // Process one cluster with the filter (all kCluster targets, in chunks of
 // kChunk) from its copy staged in LDS; every lane reads the same target, so
 // each read is a broadcast. The filter value of a target is
-// v = 2 (pl.(-ql) + h) + |pl|^2 with pl = p' - cc, evaluated as
-// mul, fma, fma, add (4 roundings) then the final fma; its distance to the
-// exact squared distance is at most u (6.6 (|pl| + rho)^2 + |v|); 4u is used
-// with coefficient 7, so for the chunk minimum v:
-// lo = v - 2^-22 |v| - delta, hi = v + 2^-22 |v| + delta,
+// v = 2 (h - pl . ql) + |pl|^2 with pl = p' - cc, h = |ql|^2 / 2, evaluated as
+// three FMAs and a final FMA; its distance to the exact squared distance is at
+// most u (7 (|pl| + rho)^2 + |v|) (rounding of the centred coordinates, of h,
+// of the three FMAs and of the last FMA); 4u is used, so for the chunk
+// minimum v: lo = v - 2^-22 |v| - delta, hi = v + 2^-22 |v| + delta,
 // delta = 2^-22 7 (|pl| + rho)^2.
 __device__ __forceinline__ void filter_cluster(const float4* __restrict__ tg, int c, float plx,
                                                float ply, float plz, float rho_c, LaneBest& L) {
@@ -145,17 +145,21 @@ __device__ __forceinline__ void filter_cluster(const float4* __restrict__ tg, in
 #pragma unroll 1
   for (int ch = 0; ch < kChunksPerCluster; ++ch) {
     const float4* qc = tg + ch * kChunk;
-    float m0 = __builtin_inff(), m1 = __builtin_inff();
+    static_assert(kChunk == 16, "the min tree below covers 16 targets");
+    float sv[kChunk];
 #pragma unroll
-    for (int j = 0; j < kChunk; j += 4) {
-      const float4 a = qc[j], b = qc[j + 1], d = qc[j + 2], e = qc[j + 3];
-      const float sa = __builtin_fmaf(npx, a.x, __builtin_fmaf(npy, a.y, npz * a.z)) + a.w;
-      const float sb = __builtin_fmaf(npx, b.x, __builtin_fmaf(npy, b.y, npz * b.z)) + b.w;
-      const float sd = __builtin_fmaf(npx, d.x, __builtin_fmaf(npy, d.y, npz * d.z)) + d.w;
-      const float se = __builtin_fmaf(npx, e.x, __builtin_fmaf(npy, e.y, npz * e.z)) + e.w;
-      m0 = fminf(m0, fminf(sa, sb));
-      m1 = fminf(m1, fminf(sd, se));
+    for (int j = 0; j < kChunk; ++j) {
+      const float4 a = qc[j];
+      sv[j] = __builtin_fmaf(npx, a.x, __builtin_fmaf(npy, a.y, __builtin_fmaf(npz, a.z, a.w)));
     }
+    // balanced tree of three-way minima (8 instructions for 16 values)
+    const float t0 = fminf(fminf(sv[0], sv[1]), sv[2]);
+    const float t1 = fminf(fminf(sv[3], sv[4]), sv[5]);
+    const float t2 = fminf(fminf(sv[6], sv[7]), sv[8]);
+    const float t3 = fminf(fminf(sv[9], sv[10]), sv[11]);
+    const float t4 = fminf(fminf(sv[12], sv[13]), sv[14]);
+    const float m0 = fminf(fminf(t0, t1), t2);
+    const float m1 = fminf(fminf(t3, t4), sv[15]);
     const float v = __builtin_fmaf(2.0f, fminf(m0, m1), pp);
     // an all-padding chunk has v = +inf: keep lo = hi = +inf (no inf - inf)
     const float e = fminf(0x1.0p-22f * fabsf(v) + delta, 1e38f);
