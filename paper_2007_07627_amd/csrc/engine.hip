@@ -25,10 +25,10 @@
 namespace icp {
 
 // kernels launched from the other translation units
-void launch_nn(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
+void launch_nn(const SlotDesc*, const SlotState*, WorkList*, int, bool, hipStream_t);
 void launch_epi(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
-void launch_solver(const SlotDesc*, SlotState*, int, int*, hipStream_t);
-void launch_boot(const SlotDesc*, SlotState*, int, hipStream_t);
+void launch_solver(const SlotDesc*, SlotState*, int, int*, WorkList*, bool, hipStream_t);
+void launch_boot(const SlotDesc*, SlotState*, int, WorkList*, bool, hipStream_t);
 void launch_median(const SlotDesc*, SlotState*, int, hipStream_t);
 void launch_plan(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
 void launch_aos_to_soa(const float*, int, float*, float*, float*, hipStream_t);
@@ -167,6 +167,7 @@ struct Layout {
 
 struct HostSlot {
   bool used = false;
+  bool want_median = false;   // the first pass computes the median
   char* mem = nullptr;
   Layout L;
   uint64_t ticket = 0;
@@ -228,6 +229,7 @@ static void fill_result(const SlotState& S, icp_result* r) {
 struct Engine {
   int dev = 0;
   int capacity = 1;
+  bool single = false;       // one slot at a time, planned by its own solver
   int target_items = 4096;   // NN work items aimed for when choosing splits
   hipStream_t st = nullptr;  // passes
   hipStream_t side = nullptr;  // admission / setup
@@ -312,15 +314,20 @@ struct Engine {
     else (void)hipEventRecord(pev[k], s);
   }
 
-  void enqueue_pass(hipStream_t s, int i = 0, bool capturing = false) {
-    launch_plan(d_desc, d_state, d_wl, capacity, s);
+  // One pass. The one-slot engine is planned by its solver (and boot) kernel,
+  // so a pass is cull, slices, reduction, solver, with the median only on
+  // the pass that needs it (the first); the multi-slot engine plans its work
+  // lists on the device and runs the median kernel every pass (it returns at
+  // once for slots that do not need it).
+  void enqueue_pass(hipStream_t s, int i = 0, bool capturing = false, bool median = false) {
+    if (!single) launch_plan(d_desc, d_state, d_wl, capacity, s);
     mark(4 * i, s, capturing);
-    launch_nn(d_desc, d_state, d_wl, nn_grid, s);
+    launch_nn(d_desc, d_state, d_wl, nn_grid, single, s);
     mark(4 * i + 1, s, capturing);
     launch_epi(d_desc, d_state, d_wl, epi_grid, s);
     mark(4 * i + 2, s, capturing);
-    launch_median(d_desc, d_state, capacity, s);
-    launch_solver(d_desc, d_state, capacity, d_done, s);
+    if (!single || median) launch_median(d_desc, d_state, capacity, s);
+    launch_solver(d_desc, d_state, capacity, d_done, d_wl, single, s);
     mark(4 * i + 3, s, capturing);
   }
 
@@ -412,6 +419,7 @@ struct Engine {
     S.nu_max = r.prm.nu_max;
     S.nu_auto = (!r.query && !r.eval && r.prm.mode != ICP_P2P_L2 && !(r.prm.nu_max > 0)) ? 1 : 0;
     S.want_median = S.nu_auto;
+    hs[s].want_median = S.want_median != 0;
     S.k = 1;
     std::memcpy(S.Tkm1, (r.query || r.eval) ? r.Tq : r.prm.T0, sizeof S.Tkm1);
     HIP_OK(hipMemcpyAsync(d_state + s, &S, sizeof S, hipMemcpyHostToDevice, ss));
@@ -499,7 +507,7 @@ struct Engine {
     HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     HIP_OK(hipEventRecord(ev, side));
     HIP_OK(hipStreamWaitEvent(st, ev, 0));
-    launch_boot(d_desc, d_state, s, st);
+    launch_boot(d_desc, d_state, s, d_wl, single, st);
     (void)hipEventDestroy(ev);
     return hipGetLastError() == hipSuccess;
   }
@@ -616,7 +624,25 @@ static icp_status run_sync(icp_ctx* ctx, OwnedRequest& r, icp_result* out, void*
   icp_status rc = ICP_OK;
   const long kMaxPasses = 200000;  // host guard against a runaway state machine
   long passes = 0;
-  if (plain) {
+  E.h_done[0] = 0;
+  if (E.hs[0].want_median) {
+    // the first pass computes the median for the initial nu: launched
+    // directly with the median kernel, the later passes without it
+    if (E.prof && !E.ensure_events(1)) rc = ICP_ERR_DEVICE;
+    if (rc == ICP_OK) {
+      E.enqueue_pass(E.st, 0, false, true);
+      if (hipMemcpyAsync(E.h_done, E.d_done, sizeof(int), hipMemcpyDeviceToHost, E.st) != hipSuccess ||
+          hipStreamSynchronize(E.st) != hipSuccess)
+        rc = ICP_ERR_DEVICE;
+      else
+        E.collect_profile(1);
+    }
+    passes = 1;
+    if (rc != ICP_OK) { E.release(0); return rc; }
+  }
+  if (E.h_done[0]) {
+    // finished in the first pass
+  } else if (plain) {
     for (;; ++passes) {
       if (passes > kMaxPasses) { rc = ICP_ERR_DEVICE; break; }
       if (E.prof && !E.ensure_events(1)) { rc = ICP_ERR_DEVICE; break; }
@@ -842,6 +868,7 @@ icp_status icp_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
   // over target subsets (tunable: ICP_NN_TARGET_ITEMS)
   int items = 4096;
   if (const char* e = std::getenv("ICP_NN_TARGET_ITEMS")) items = std::max(1, std::atoi(e));
+  c->sync_eng.single = true;
   if (!c->sync_eng.init(device, 1, &c->arena, items) || !c->batch_eng.init(device, c->max_slots, &c->arena, 64)) {
     c->sync_eng.destroy();
     c->batch_eng.destroy();

@@ -152,7 +152,8 @@ struct WorkList {
   int nn_total;
   int epi_total;
   int s_total;                // closest-point slices queued this pass
-  int pad[2];
+  int single;                 // 1: one-slot engine, planned by the solver itself
+  int s_from_scount;          // 1: the slice total is the slot's slice count
   int slot[1024];             // compacted active slot ids
   int nn_base[1025];          // prefix of NN items over the compacted list
   int epi_base[1025];

@@ -451,11 +451,15 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
                                                       WorkList* __restrict__ wl) {
   __shared__ float4 s_tgt[kCluster];
   const int lane = threadIdx.x;
+  // one-slot engine: the slice total is the slot's count (from this pass's
+  // cull or, with reused lists, from the last one)
+  const int s_total = __builtin_amdgcn_readfirstlane(
+      wl->s_from_scount ? *descs[wl->slot[0]].scount : wl->s_total);
   for (int round = 0;; ++round) {
     int g = 0;
     if (lane == 0) g = queue_item(wl->q_s, round);
     g = __builtin_amdgcn_readfirstlane(__shfl(g, 0, 64));
-    if (g >= wl->s_total) break;
+    if (g >= s_total) break;
     const int a = __builtin_amdgcn_readfirstlane(find_slot(wl->s_base, wl->n_active, g));
     const int slot = __builtin_amdgcn_readfirstlane(wl->slot[a]);
     const SlotDesc& D = descs[slot];
@@ -614,9 +618,9 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
 }
 
 void launch_nn(const SlotDesc* descs, const SlotState* states, WorkList* wl, int grid,
-               hipStream_t st) {
+               bool single, hipStream_t st) {
   hipLaunchKernelGGL(nn_cull_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
-  hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl);
+  if (!single) hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl);
   hipLaunchKernelGGL(nn_slice_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
 }
 

@@ -350,6 +350,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__
     wl->epi_base[pos] = s_epi[t] - ep;
   }
   if (t == 1023) {
+    wl->single = 0;
+    wl->s_from_scount = 0;
     wl->n_active = s_act[t];
     wl->nn_total = s_nn[t];
     wl->epi_total = s_epi[t];

@@ -779,130 +779,8 @@ stage_end:
 
 // Merge the partials of one slot in a fixed order (lane-strided sums, then a
 // fixed shuffle tree) and advance the state machine on lane 0.
-// Sum of the per-tile partial moments in a fixed order: lane l adds tiles
-// l, l + 64, ... in turn, then a fixed butterfly combines the lanes (lane 0
-// holds the result). The value count is a template parameter so that the
-// accumulators stay in registers.
-template <int NV>
-__device__ __forceinline__ void merge_partials(const SlotDesc& D, double* acc) {
-  const int lane = threadIdx.x;
-  double a[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) a[v] = 0.0;
-  for (int e = lane; e < D.nepi; e += 64) {
-    const double* p = D.part + (size_t)e * kPartStride;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) a[v] += p[v];
-  }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double x = a[v];
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-    acc[v] = x;
-  }
-#pragma unroll
-  for (int v = NV; v < kP2PLVals; ++v) acc[v] = 0.0;
-}
-
-__device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc);
-
-__global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__ descs,
-                                                    SlotState* __restrict__ states, int capacity,
-                                                    int* __restrict__ done) {
-  const int slot = blockIdx.x;
-  if (slot >= capacity) return;
-  if (states[slot].status != ST_RUNNING) return;
-  // The state machine runs on an LDS copy of the slot state: its many
-  // dependent reads and writes then cost LDS latency instead of a memory
-  // round trip each. The wavefront copies it in and out cooperatively.
-  static_assert(sizeof(SlotState) % 8 == 0, "slot state is copied in 8-byte words");
-  constexpr int kWords = (int)(sizeof(SlotState) / 8);
-  __shared__ unsigned long long s_state[kWords];
-  {
-    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(states + slot);
-    for (int i = threadIdx.x; i < kWords; i += 64) s_state[i] = src[i];
-  }
-  __syncthreads();
-  SlotState& S = *reinterpret_cast<SlotState*>(s_state);
-  const SlotDesc& D = descs[slot];
-  const int lane = threadIdx.x;
-  double acc[kP2PLVals];
-  if (D.mode == P2PL_WELSCH) merge_partials<kP2PLVals>(D, acc);
-  else merge_partials<kP2PVals>(D, acc);
-  if (lane == 0) solver_step(D, S, acc);
-  __syncthreads();
-  {
-    unsigned long long* dst = reinterpret_cast<unsigned long long*>(states + slot);
-    for (int i = threadIdx.x; i < kWords; i += 64) dst[i] = s_state[i];
-  }
-  if (lane == 0 && S.status == ST_DONE) done[slot] = 1;
-}
-
-// One pass of the state machine for a slot (lane 0 of the solver wavefront).
-__device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc) {
-  S.phases++;
-  if (D.trace && S.trace_len < D.trace_cap) {
-    double* row = D.trace + (size_t)S.trace_len * kTraceRow;
-    row[0] = acc[0];
-    row[1] = S.nu_eval;
-    row[2] = S.sm;
-    row[3] = S.reuse;
-    for (int i = 0; i < 16; ++i) row[4 + i] = S.Teval[i];
-    S.trace_len++;
-  }
-  if (S.sm == SM_QUERY) {
-    S.status = ST_DONE;
-  } else if (S.sm == SM_EVAL) {
-    // energy at the requested transform and the MM update from it
-    double T[16];
-    unsigned f;
-    if (D.mode == P2PL_WELSCH) {
-      double xp[6];
-      f = gn_p2pl(acc, S.last_key, xp);
-      twist_exp(xp, T);
-    } else {
-      f = align_p2p(acc, S.cP, S.cQ, T);
-    }
-    S.flags = f;
-    S.nu = S.nu_eval;
-    finish(S, T, acc[0]);
-  } else if (D.mode == P2PL_WELSCH) {
-    step_p2pl(S, acc);
-  } else {
-    step_p2p(S, acc);
-  }
-}
-
-// First request of a freshly admitted slot: evaluation at T0 (point-to-plane:
-// at exp(log T0)), then the slot becomes RUNNING.
-__global__ void boot_kernel(const SlotDesc* __restrict__ descs, SlotState* __restrict__ states,
-                            int slot) {
-  if (threadIdx.x != 0) return;
-  SlotState& S = states[slot];
-  S.verlet = descs[slot].method == NN_CLUSTER ? (double)descs[slot].verlet : 0.0;
-  S.evaluations = 0;
-  S.nn_passes = 0;
-  S.have_last = 0;
-  if (S.sm == SM_QUERY) {
-    request_T(S, S.Tkm1, 1.0);
-  } else if (S.sm == SM_EVAL) {
-    if (S.mode == P2PL_WELSCH) {
-      twist_log(S.Tkm1, S.xkm1);
-      request_xi(S, S.xkm1, S.nu_max);
-    } else {
-      request_T(S, S.Tkm1, S.nu_max);
-    }
-  } else if (S.mode == P2PL_WELSCH) {
-    twist_log(S.Tkm1, S.xkm1);
-    request_xi(S, S.xkm1, S.nu_auto ? 1.0 : S.nu_max);
-  } else {
-    request_T(S, S.Tkm1, (S.mode == P2P_L2 || S.nu_auto) ? 1.0 : S.nu_max);
-  }
-  S.status = ST_RUNNING;
-}
-
-// Exact median (element of rank floor(M/2)) of the non-negative FP64 keys of
-// one slot by 8-bit radix selection on the bit patterns.
+// Median of the slot's median keys (the element of rank M/2 of non-negative
+// FP64 values, ordered by their bit patterns) by an 8-bit radix select.
 __global__ __launch_bounds__(1024) void median_kernel(const SlotDesc* __restrict__ descs,
                                                       SlotState* __restrict__ states, int capacity) {
   const int slot = blockIdx.x;
@@ -944,17 +822,174 @@ __global__ __launch_bounds__(1024) void median_kernel(const SlotDesc* __restrict
   if (threadIdx.x == 0) S.median = __longlong_as_double((long long)s_prefix);
 }
 
-void launch_solver(const SlotDesc* descs, SlotState* states, int capacity, int* done,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(solver_kernel, dim3(capacity), dim3(64), 0, st, descs, states, capacity, done);
+// Work list of the next pass for the one-slot engine (written by the solver
+// and by the boot kernel, so that no planning kernels run between passes).
+__device__ void plan_single(const SlotDesc& D, const SlotState& S, WorkList* wl, int slot) {
+  const bool run = S.status == ST_RUNNING;
+  const int nn = (run && !S.reuse && S.cull) ? D.ntile : 0;
+  if (nn) *D.scount = 0;
+  wl->single = 1;
+  wl->n_active = run ? 1 : 0;
+  wl->slot[0] = slot;
+  wl->nn_total = nn;
+  wl->nn_base[0] = 0;
+  wl->nn_base[1] = nn;
+  const int ep = run ? D.nepi : 0;
+  wl->epi_total = ep;
+  wl->epi_base[0] = 0;
+  wl->epi_base[1] = ep;
+  wl->s_from_scount = (run && !S.reuse) ? 1 : 0;
+  wl->s_total = 0;
+  wl->s_base[0] = 0;
+  wl->s_base[1] = 0;
+  for (int q = 0; q < kQueues; ++q) {
+    wl->q_nn[q * kQueueStride] = 0;
+    wl->q_epi[q * kQueueStride] = 0;
+    wl->q_s[q * kQueueStride] = 0;
+  }
 }
 
-void launch_boot(const SlotDesc* descs, SlotState* states, int slot, hipStream_t st) {
-  hipLaunchKernelGGL(boot_kernel, dim3(1), dim3(64), 0, st, descs, states, slot);
+// Sum of the per-tile partial moments in a fixed order: lane l adds tiles
+// l, l + 64, ... in turn, then a fixed butterfly combines the lanes (lane 0
+// holds the result). The value count is a template parameter so that the
+// accumulators stay in registers.
+template <int NV>
+__device__ __forceinline__ void merge_partials(const SlotDesc& D, double* acc) {
+  const int lane = threadIdx.x;
+  double a[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) a[v] = 0.0;
+  for (int e = lane; e < D.nepi; e += 64) {
+    const double* p = D.part + (size_t)e * kPartStride;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a[v] += p[v];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double x = a[v];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    acc[v] = x;
+  }
+#pragma unroll
+  for (int v = NV; v < kP2PLVals; ++v) acc[v] = 0.0;
+}
+
+__device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc);
+
+__global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__ descs,
+                                                    SlotState* __restrict__ states, int capacity,
+                                                    int* __restrict__ done, WorkList* __restrict__ wl,
+                                                    int single) {
+  const int slot = blockIdx.x;
+  if (slot >= capacity) return;
+  if (states[slot].status != ST_RUNNING) return;
+  // The state machine runs on an LDS copy of the slot state: its many
+  // dependent reads and writes then cost LDS latency instead of a memory
+  // round trip each. The wavefront copies it in and out cooperatively.
+  static_assert(sizeof(SlotState) % 8 == 0, "slot state is copied in 8-byte words");
+  constexpr int kWords = (int)(sizeof(SlotState) / 8);
+  __shared__ unsigned long long s_state[kWords];
+  {
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(states + slot);
+    for (int i = threadIdx.x; i < kWords; i += 64) s_state[i] = src[i];
+  }
+  __syncthreads();
+  SlotState& S = *reinterpret_cast<SlotState*>(s_state);
+  const SlotDesc& D = descs[slot];
+  const int lane = threadIdx.x;
+  double acc[kP2PLVals];
+  if (D.mode == P2PL_WELSCH) merge_partials<kP2PLVals>(D, acc);
+  else merge_partials<kP2PVals>(D, acc);
+  if (lane == 0) solver_step(D, S, acc);
+  __syncthreads();
+  {
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(states + slot);
+    for (int i = threadIdx.x; i < kWords; i += 64) dst[i] = s_state[i];
+  }
+  if (lane == 0 && S.status == ST_DONE) done[slot] = 1;
+  if (lane == 0 && single) plan_single(D, S, wl, slot);
+}
+
+// One pass of the state machine for a slot (lane 0 of the solver wavefront).
+__device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc) {
+  S.phases++;
+  if (D.trace && S.trace_len < D.trace_cap) {
+    double* row = D.trace + (size_t)S.trace_len * kTraceRow;
+    row[0] = acc[0];
+    row[1] = S.nu_eval;
+    row[2] = S.sm;
+    row[3] = S.reuse;
+    for (int i = 0; i < 16; ++i) row[4 + i] = S.Teval[i];
+    S.trace_len++;
+  }
+  if (S.sm == SM_QUERY) {
+    S.status = ST_DONE;
+  } else if (S.sm == SM_EVAL) {
+    // energy at the requested transform and the MM update from it
+    double T[16];
+    unsigned f;
+    if (D.mode == P2PL_WELSCH) {
+      double xp[6];
+      f = gn_p2pl(acc, S.last_key, xp);
+      twist_exp(xp, T);
+    } else {
+      f = align_p2p(acc, S.cP, S.cQ, T);
+    }
+    S.flags = f;
+    S.nu = S.nu_eval;
+    finish(S, T, acc[0]);
+  } else if (D.mode == P2PL_WELSCH) {
+    step_p2pl(S, acc);
+  } else {
+    step_p2p(S, acc);
+  }
+}
+
+// First request of a freshly admitted slot: evaluation at T0 (point-to-plane:
+// at exp(log T0)), then the slot becomes RUNNING.
+__global__ void boot_kernel(const SlotDesc* __restrict__ descs, SlotState* __restrict__ states,
+                            int slot, WorkList* __restrict__ wl, int single) {
+  if (threadIdx.x != 0) return;
+  SlotState& S = states[slot];
+  S.verlet = descs[slot].method == NN_CLUSTER ? (double)descs[slot].verlet : 0.0;
+  S.evaluations = 0;
+  S.nn_passes = 0;
+  S.have_last = 0;
+  if (S.sm == SM_QUERY) {
+    request_T(S, S.Tkm1, 1.0);
+  } else if (S.sm == SM_EVAL) {
+    if (S.mode == P2PL_WELSCH) {
+      twist_log(S.Tkm1, S.xkm1);
+      request_xi(S, S.xkm1, S.nu_max);
+    } else {
+      request_T(S, S.Tkm1, S.nu_max);
+    }
+  } else if (S.mode == P2PL_WELSCH) {
+    twist_log(S.Tkm1, S.xkm1);
+    request_xi(S, S.xkm1, S.nu_auto ? 1.0 : S.nu_max);
+  } else {
+    request_T(S, S.Tkm1, (S.mode == P2P_L2 || S.nu_auto) ? 1.0 : S.nu_max);
+  }
+  S.status = ST_RUNNING;
+  if (single) plan_single(descs[slot], S, wl, slot);
+}
+
+// Exact median (element of rank floor(M/2)) of the non-negative FP64 keys of
+// one slot by 8-bit radix selection on the bit patterns.
+
+void launch_solver(const SlotDesc* descs, SlotState* states, int capacity, int* done,
+                   WorkList* wl, bool single, hipStream_t st) {
+  hipLaunchKernelGGL(solver_kernel, dim3(capacity), dim3(64), 0, st, descs, states, capacity, done,
+                     wl, single ? 1 : 0);
 }
 
 void launch_median(const SlotDesc* descs, SlotState* states, int capacity, hipStream_t st) {
   hipLaunchKernelGGL(median_kernel, dim3(capacity), dim3(1024), 0, st, descs, states, capacity);
+}
+
+void launch_boot(const SlotDesc* descs, SlotState* states, int slot, WorkList* wl, bool single,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(boot_kernel, dim3(1), dim3(64), 0, st, descs, states, slot, wl, single ? 1 : 0);
 }
 
 }  // namespace icp
