@@ -185,8 +185,197 @@ __device__ void twist_derivs(const double xi[6], double K[45]) {
 
 // Symmetric 4x4 eigen-decomposition by cyclic Jacobi rotations; returns the
 // unit eigenvector of the largest eigenvalue and the two largest eigenvalues.
-__device__ void sym4_top(double A[16], double q[4], double& l0, double& l1) {
-  double V[16];
+// One Jacobi rotation in the (p, r) plane of the symmetric 4x4 A, zeroing
+// A[p][r], accumulated onto the columns of V. A rotation by a negligible
+// angle is skipped (its square is far below the stopping threshold on the
+// off-diagonal mass).
+__device__ __forceinline__ void jacobi_rot(double A[16], double V[16], int p, int r) {
+  const double apr = A[4 * p + r];
+  if (!(fabs(apr) > 1e-18 * (fabs(A[5 * p]) + fabs(A[5 * r])))) return;
+  const double theta = (A[4 * r + r] - A[4 * p + p]) / (2.0 * apr);
+  const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+  const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const double akp = A[4 * kk + p], akr = A[4 * kk + r];
+    A[4 * kk + p] = c * akp - s * akr;
+    A[4 * kk + r] = s * akp + c * akr;
+  }
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const double apk = A[4 * p + kk], ark = A[4 * r + kk];
+    A[4 * p + kk] = c * apk - s * ark;
+    A[4 * r + kk] = s * apk + c * ark;
+  }
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const double vkp = V[4 * kk + p], vkr = V[4 * kk + r];
+    V[4 * kk + p] = c * vkp - s * vkr;
+    V[4 * kk + r] = s * vkp + c * vkr;
+  }
+}
+
+// Solves M y = b for a 4x4 M by Gaussian elimination with partial pivoting
+// (row exchanges by selects, so that everything stays in registers); an exact
+// zero pivot is replaced by a tiny one (M is then an exactly singular shifted
+// matrix and any large solution along its null space is what is wanted).
+__device__ __forceinline__ void solve4(double M[16], double b[4], double tiny) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int p = k;
+    double best = fabs(M[5 * k]);
+#pragma unroll
+    for (int i = k + 1; i < 4; ++i)
+      if (fabs(M[4 * i + k]) > best) { best = fabs(M[4 * i + k]); p = i; }
+#pragma unroll
+    for (int i = k + 1; i < 4; ++i) {
+      const bool sw = i == p;
+#pragma unroll
+      for (int j = k; j < 4; ++j) {
+        const double a = M[4 * k + j], c = M[4 * i + j];
+        M[4 * k + j] = sw ? c : a;
+        M[4 * i + j] = sw ? a : c;
+      }
+      const double a = b[k], c = b[i];
+      b[k] = sw ? c : a;
+      b[i] = sw ? a : c;
+    }
+    if (M[5 * k] == 0.0) M[5 * k] = tiny;
+    const double inv = 1.0 / M[5 * k];
+#pragma unroll
+    for (int i = k + 1; i < 4; ++i) {
+      const double f = M[4 * i + k] * inv;
+#pragma unroll
+      for (int j = k + 1; j < 4; ++j) M[4 * i + j] -= f * M[4 * k + j];
+      b[i] -= f * b[k];
+    }
+  }
+#pragma unroll
+  for (int k = 3; k >= 0; --k) {
+    double v = b[k];
+#pragma unroll
+    for (int j = k + 1; j < 4; ++j) v -= M[4 * k + j] * b[j];
+    b[k] = v / M[5 * k];
+  }
+}
+
+// Top eigenpair of a symmetric 4x4 A by Rayleigh-quotient iteration from the
+// previous top eigenvector x (unit). Returns false unless the iteration
+// settles and the result is certified as the top eigenvector: with an
+// orthonormal basis of its complement (a Householder reflection), b I - B is
+// positive definite (Cholesky) for the complement block B and
+// b = l0 - 2e-12 |l0| - |residual|, so every other eigenvalue is below b,
+// which then stands in for l1 (the gap test is decided).
+__device__ bool top_eig_rqi(const double A[16], const double x0[4], double q[4], double& l0,
+                            double& l1) {
+  double nA = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) nA += A[i] * A[i];
+  nA = sqrt(nA);
+  if (!(nA > 0.0)) return false;
+  double x[4] = {x0[0], x0[1], x0[2], x0[3]};
+  double mu = 0.0, rn = 0.0;
+  bool settled = false;
+  for (int it = 0; it < 6; ++it) {
+    double Ax[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Ax[i] = A[4 * i] * x[0] + A[4 * i + 1] * x[1] + A[4 * i + 2] * x[2] + A[4 * i + 3] * x[3];
+    mu = x[0] * Ax[0] + x[1] * Ax[1] + x[2] * Ax[2] + x[3] * Ax[3];
+    double r2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r2 += (Ax[i] - mu * x[i]) * (Ax[i] - mu * x[i]);
+    rn = sqrt(r2);
+    if (settled) break;               // one polishing step after the residual settled
+    if (rn <= 1e-13 * nA) settled = true;
+    double M[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) M[i] = A[i] - ((i % 5 == 0) ? mu : 0.0);
+    double y[4] = {x[0], x[1], x[2], x[3]};
+    solve4(M, y, 1e-300 * nA);
+    const double ny = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
+    if (!(ny > 0.0) || !(ny < __builtin_inf())) return false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = y[i] / ny;
+  }
+  if (!settled || !(rn <= 1e-12 * nA)) return false;
+  // Householder reflection H = I - 2 v v^T / (v^T v), v = x + sign(x_m) e_m
+  int m = 0;
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (fabs(x[i]) > fabs(x[m])) m = i;
+  double v[4] = {x[0], x[1], x[2], x[3]};
+  double xm = x[0];
+#pragma unroll
+  for (int i = 1; i < 4; ++i) xm = (i == m) ? x[i] : xm;
+  const double sg = xm >= 0.0 ? 1.0 : -1.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] += (i == m) ? sg : 0.0;
+  const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
+  double H[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) H[4 * i + j] = ((i == j) ? 1.0 : 0.0) - 2.0 * v[i] * v[j] / vv;
+  // H A H; column m of H is -sg x, the other columns span its complement
+  double AH[16], C[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      AH[4 * i + j] = A[4 * i] * H[j] + A[4 * i + 1] * H[4 + j] + A[4 * i + 2] * H[8 + j] + A[4 * i + 3] * H[12 + j];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      C[4 * i + j] = H[i] * AH[j] + H[4 + i] * AH[4 + j] + H[8 + i] * AH[8 + j] + H[12 + i] * AH[12 + j];
+  // complement block rows/cols {0..3} \ {m}, gathered by selects
+  double B[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double val = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int ia = i < m ? i : i - 1, jc = j < m ? j : j - 1;
+          if (i != m && j != m && ia == a && jc == c) val = C[4 * i + j];
+        }
+      B[3 * a + c] = val;
+    }
+  l0 = mu;
+  const double b = mu - 2e-12 * fabs(mu) - rn;
+  const double c11 = b - B[0], c21 = -0.5 * (B[3] + B[1]), c31 = -0.5 * (B[6] + B[2]);
+  const double c22 = b - B[4], c32 = -0.5 * (B[7] + B[5]), c33 = b - B[8];
+  if (!(c11 > 0.0)) return false;
+  const double l11 = sqrt(c11);
+  const double l21 = c21 / l11, l31 = c31 / l11;
+  const double d22 = c22 - l21 * l21;
+  if (!(d22 > 0.0)) return false;
+  const double l22 = sqrt(d22);
+  const double l32 = (c32 - l31 * l21) / l22;
+  if (!(c33 - l31 * l31 - l32 * l32 > 0.0)) return false;
+  l1 = b;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] = x[i];
+  return true;
+}
+
+// Largest eigenpair of a symmetric 4x4 matrix (l1: second largest, or a
+// certified upper bound on it). Warm start: Rayleigh-quotient iteration from
+// the previous top eigenvector (column 0 of V); otherwise (first call,
+// uncertified) cyclic Jacobi rotations from the identity. Column 0 of V
+// keeps the top eigenvector for the next call.
+__device__ void sym4_top(double A[16], double V[16], double q[4], double& l0, double& l1) {
+  const double x0[4] = {V[0], V[4], V[8], V[12]};
+  const double n0 = x0[0] * x0[0] + x0[1] * x0[1] + x0[2] * x0[2] + x0[3] * x0[3];
+  if (n0 > 0.5 && top_eig_rqi(A, x0, q, l0, l1)) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) V[4 * i] = q[i];
+    return;
+  }
+#pragma unroll
   for (int i = 0; i < 16; ++i) V[i] = (i % 5 == 0) ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, tot = 0.0;
@@ -200,28 +389,7 @@ __device__ void sym4_top(double A[16], double q[4], double& l0, double& l1) {
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
-      for (int r = p + 1; r < 4; ++r) {
-        const double apr = A[4 * p + r];
-        if (apr == 0.0) continue;
-        const double theta = (A[4 * r + r] - A[4 * p + p]) / (2.0 * apr);
-        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int kk = 0; kk < 4; ++kk) {
-          const double akp = A[4 * kk + p], akr = A[4 * kk + r];
-          A[4 * kk + p] = c * akp - s * akr;
-          A[4 * kk + r] = s * akp + c * akr;
-        }
-        for (int kk = 0; kk < 4; ++kk) {
-          const double apk = A[4 * p + kk], ark = A[4 * r + kk];
-          A[4 * p + kk] = c * apk - s * ark;
-          A[4 * r + kk] = s * apk + c * ark;
-        }
-        for (int kk = 0; kk < 4; ++kk) {
-          const double vkp = V[4 * kk + p], vkr = V[4 * kk + r];
-          V[4 * kk + p] = c * vkp - s * vkr;
-          V[4 * kk + r] = s * vkp + c * vkr;
-        }
-      }
+      for (int r = p + 1; r < 4; ++r) jacobi_rot(A, V, p, r);
   }
   int b0 = 0;
   for (int i = 1; i < 4; ++i) if (A[5 * i] > A[5 * b0]) b0 = i;
@@ -230,6 +398,8 @@ __device__ void sym4_top(double A[16], double q[4], double& l0, double& l1) {
   l0 = A[5 * b0];
   l1 = A[5 * b1];
   for (int i = 0; i < 4; ++i) q[i] = V[4 * i + b0];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) V[4 * i] = q[i];
 }
 
 // Weighted absolute orientation from the merged moments by Horn's unit-
@@ -237,7 +407,7 @@ __device__ void sym4_top(double A[16], double q[4], double& l0, double& l1) {
 // S = sum w (p - pb)(q - qb)^T, the quaternion is the top eigenvector of the
 // symmetric 4x4 matrix built from S; t = qb - R pb.
 __device__ unsigned align_p2p(const double* mom, const double cP[3], const double cQ[3],
-                              double T[16]) {
+                              double V[16], double T[16]) {
   const double W = mom[1];
   if (!(W > 1e-300)) return F_ZERO_WEIGHT;
   const double pb[3] = {mom[2] / W, mom[3] / W, mom[4] / W};
@@ -252,7 +422,7 @@ __device__ unsigned align_p2p(const double* mom, const double cP[3], const doubl
                   Szx - Sxz,       Sxy + Syx,        -Sxx + Syy - Szz, Syz + Szy,
                   Sxy - Syx,       Szx + Sxz,        Syz + Szy,        -Sxx - Syy + Szz};
   double q[4], l0, l1;
-  sym4_top(N, q, l0, l1);
+  sym4_top(N, V, q, l0, l1);
   // rank test: for a proper optimum the two largest eigenvalues of the
   // quaternion matrix differ by 2 (s1 + s2) (singular values of S), so a
   // vanishing gap means rank(S) <= 1 and the rotation is not determined
@@ -505,7 +675,7 @@ __device__ inline void cpy(double* d, const double* s, int n) {
 __device__ void step_p2p(SlotState& S, const double* mom) {
   const double E = mom[0];
   double Tprop[16];
-  const unsigned pf = align_p2p(mom, S.cP, S.cQ, Tprop);
+  const unsigned pf = align_p2p(mom, S.cP, S.cQ, S.Vq, Tprop);
   const int m = S.m;
   int sm = S.sm;
   if (sm == SM_INIT) {
@@ -933,7 +1103,7 @@ __device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc) 
       f = gn_p2pl(acc, S.last_key, xp);
       twist_exp(xp, T);
     } else {
-      f = align_p2p(acc, S.cP, S.cQ, T);
+      f = align_p2p(acc, S.cP, S.cQ, S.Vq, T);
     }
     S.flags = f;
     S.nu = S.nu_eval;
