@@ -45,7 +45,9 @@ __global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ d
   for (int round = 0;; ++round) {
     if (threadIdx.x == 0) s_item = queue_item(wl->q_epi, round);
     __syncthreads();
-    const int g = s_item;
+    // the item (and so the slot) is uniform over the block: kept in scalar
+    // registers, the descriptor and state fields are scalar loads
+    const int g = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (g >= wl->epi_total) break;
     int lo = 0, hi = wl->n_active - 1;
@@ -53,7 +55,8 @@ __global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ d
       const int mid = (lo + hi + 1) >> 1;
       if (wl->epi_base[mid] <= g) lo = mid; else hi = mid - 1;
     }
-    const int slot = wl->slot[lo];
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const int slot = __builtin_amdgcn_readfirstlane(wl->slot[lo]);
     const SlotDesc& D = descs[slot];
     const SlotState& S = states[slot];
     const int e = g - wl->epi_base[lo];

@@ -1029,6 +1029,8 @@ __device__ __forceinline__ void merge_partials(const SlotDesc& D, double* acc) {
   double a[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) a[v] = 0.0;
+  // four tiles' loads in flight per lane; the sums stay in tile order
+#pragma unroll 4
   for (int e = lane; e < D.nepi; e += 64) {
     const double* p = D.part + (size_t)e * kPartStride;
 #pragma unroll
