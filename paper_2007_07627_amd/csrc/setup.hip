@@ -80,7 +80,33 @@ __global__ void morton_kernel(const float* __restrict__ x, const float* __restri
     q = q < 0 ? 0 : (q > 1023 ? 1023 : q);
     c[a] = (unsigned)q;
   }
-  keys[i] = spread10(c[0]) | (spread10(c[1]) << 1) | (spread10(c[2]) << 2);
+  // Hilbert index of the cell (Skilling's transpose form: undo the excess
+  // work, then Gray-encode; the index interleaves the transposed bits), a
+  // curve without the long jumps of the Morton order, so that runs of 64 or
+  // 128 consecutive points have tighter boxes.
+  unsigned X[3] = {c[0], c[1], c[2]};
+  for (unsigned Q = 1u << 9; Q > 1u; Q >>= 1) {
+    const unsigned P = Q - 1u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (X[a] & Q) {
+        X[0] ^= P;
+      } else {
+        const unsigned t = (X[0] ^ X[a]) & P;
+        X[0] ^= t;
+        X[a] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  unsigned t = 0u;
+  for (unsigned Q = 1u << 9; Q > 1u; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1u;
+  X[0] ^= t;
+  X[1] ^= t;
+  X[2] ^= t;
+  keys[i] = (spread10(X[0]) << 2) | (spread10(X[1]) << 1) | spread10(X[2]);
   vals[i] = (unsigned)i;
 }
 
