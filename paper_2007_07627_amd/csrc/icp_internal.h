@@ -9,7 +9,7 @@
 namespace icp {
 
 constexpr int kTile = 64;        // sources per NN work item (one wavefront)
-constexpr int kCluster = 128;    // targets per cluster of the Morton-ordered index
+constexpr int kCluster = 128;    // targets per cluster of the Hilbert-ordered index
 constexpr int kChunk = 16;       // targets per deferred-argmin chunk
 constexpr int kChunksPerCluster = kCluster / kChunk;
 constexpr int kSuper = 16;       // clusters per super-cluster (coarse culling level)

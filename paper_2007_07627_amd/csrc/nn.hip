@@ -217,7 +217,7 @@ __device__ __forceinline__ void lane_point(const SlotDesc& D, const double* T, i
 __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict__ descs,
                                                      const SlotState* __restrict__ states,
                                                      WorkList* __restrict__ wl) {
-  __shared__ float4 s_box[kCluster];
+  __shared__ float4 s_box[128];  // 64 candidate boxes: lo at [j], hi at [64 + j]
   __shared__ int s_cand[kCandCap];
   __shared__ int s_sup[kSupCap];
   const int lane = threadIdx.x;
@@ -515,18 +515,20 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
       if (live == 0ull) continue;
       int j = __builtin_ctzll(live);
       int c = __builtin_amdgcn_readlane(myc, j);
-      float4 r0 = load_global(D.qloc, (size_t)c * kCluster + lane);
-      float4 r1 = load_global(D.qloc, (size_t)c * kCluster + 64 + lane);
+      constexpr int kRows = kCluster / 64;
+      float4 r[kRows];
+#pragma unroll
+      for (int t = 0; t < kRows; ++t) r[t] = load_global(D.qloc, (size_t)c * kCluster + 64 * t + lane);
       for (unsigned long long rest = live & (live - 1ull);; rest &= rest - 1ull) {
         __syncthreads();
-        s_tgt[lane] = r0;
-        s_tgt[lane + 64] = r1;
+#pragma unroll
+        for (int t = 0; t < kRows; ++t) s_tgt[64 * t + lane] = r[t];
         __syncthreads();
         const int jn = rest ? __builtin_ctzll(rest) : -1;
         const int cn = rest ? __builtin_amdgcn_readlane(myc, jn) : -1;
         if (cn >= 0) {
-          r0 = load_global(D.qloc, (size_t)cn * kCluster + lane);
-          r1 = load_global(D.qloc, (size_t)cn * kCluster + 64 + lane);
+#pragma unroll
+          for (int t = 0; t < kRows; ++t) r[t] = load_global(D.qloc, (size_t)cn * kCluster + 64 * t + lane);
         }
         bool run = true;
         if (lane_test && gb + j >= lead) {
@@ -578,8 +580,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
         const bool need = amb && lb2 * (1.0f - 0x1.0p-20f) <= thr;
         if (!__any(need)) continue;
         __syncthreads();
-        s_tgt[lane] = D.qorg[c * kCluster + lane];
-        s_tgt[lane + 64] = D.qorg[c * kCluster + 64 + lane];
+        for (int t = 0; t < kCluster / 64; ++t) s_tgt[64 * t + lane] = D.qorg[c * kCluster + 64 * t + lane];
         __syncthreads();
         if (need) {
           key = exact_scan<false>(s_tgt, 0, kCluster, ptx, pty, ptz, key);

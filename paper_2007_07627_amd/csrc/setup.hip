@@ -208,11 +208,13 @@ __global__ __launch_bounds__(64) void build_clusters_kernel(
   const int c = blockIdx.x;
   if (c >= ncl) return;
   const int lane = threadIdx.x;
-  float p[2][3];
-  int id[2];
+  constexpr int kRows = kCluster / 64;
+  static_assert(kCluster % 64 == 0, "a cluster is whole rows of 64 targets");
+  float p[kRows][3];
+  int id[kRows];
   float mn[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
   float mx[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-  for (int r = 0; r < 2; ++r) {
+  for (int r = 0; r < kRows; ++r) {
     const int pos = c * kCluster + r * 64 + lane;
     id[r] = pos < n ? (int)order[pos] : -1;
     if (id[r] >= 0) {
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(64) void build_clusters_kernel(
     }
   const float cc[3] = {0.5f * (mn[0] + mx[0]), 0.5f * (mn[1] + mx[1]), 0.5f * (mn[2] + mx[2])};
   double rmax = 0.0;
-  for (int r = 0; r < 2; ++r) {
+  for (int r = 0; r < kRows; ++r) {
     const int pos = c * kCluster + r * 64 + lane;
     if (id[r] >= 0) {
       const double ex = (double)p[r][0] - cc[0], ey = (double)p[r][1] - cc[1],
