@@ -653,7 +653,7 @@ static icp_status run_sync(icp_ctx* ctx, OwnedRequest& r, icp_result* out, void*
       if (E.h_done[0]) break;
     }
   } else {
-    const int R = (r.query || r.eval) ? 1 : 8;
+    const int R = (r.query || r.eval) ? 1 : 16;
     // profiling: the same passes launched directly (timing events around each
     // kernel); otherwise replays of the captured graph
     if (!E.prof && !E.build_graph(R)) { E.release(0); return ICP_ERR_DEVICE; }

@@ -208,23 +208,38 @@ __device__ __forceinline__ void lane_point(const SlotDesc& D, const double* T, i
   }
 }
 
+// LDS written by some lanes of a wavefront and read by others: a wavefront's
+// LDS operations complete in order, so a compiler fence is all it needs.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kCullWaves = 4;
+
 // ------------------------------------------------------------------ cull kernel
-// One wavefront per tile of 64 sources. Cluster mode: candidate clusters from
-// the transformed tile sphere against super-cluster and cluster AABBs, then
-// (with warm bounds) only the clusters some lane can still need, tested per
-// lane against the boxes staged in LDS. Writes the list and the tile record
-// (flags, count, slice length, nearest cluster) and queues the slices.
-__global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict__ descs,
-                                                     const SlotState* __restrict__ states,
-                                                     WorkList* __restrict__ wl) {
-  __shared__ float4 s_box[128];  // 64 candidate boxes: lo at [j], hi at [64 + j]
+// One block of kCullWaves wavefronts per tile of 64 sources (every wavefront
+// holds the tile's 64 sources). Cluster mode: candidate clusters from the
+// transformed tile sphere against super-cluster and cluster AABBs, then (with
+// warm bounds) only the clusters some lane can still need, tested per lane
+// against the boxes staged in LDS, the cluster batches shared out among the
+// wavefronts. The first wavefront writes the tile record (flags, count, slice
+// length, nearest cluster) and queues the slices. Steps that are not shared
+// out run identically in every wavefront.
+__global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
+    const SlotDesc* __restrict__ descs, const SlotState* __restrict__ states,
+    WorkList* __restrict__ wl) {
+  __shared__ float4 s_boxes[kCullWaves][128];  // per wavefront: 64 boxes, lo at [j], hi at [64 + j]
   __shared__ int s_cand[kCandCap];
   __shared__ int s_sup[kSupCap];
-  const int lane = threadIdx.x;
+  __shared__ int s_item, s_n2;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float4* s_box = s_boxes[wv];
   for (int round = 0;; ++round) {
-    int g = 0;
-    if (lane == 0) g = queue_item(wl->q_nn, round);
-    g = __builtin_amdgcn_readfirstlane(__shfl(g, 0, 64));
+    if (threadIdx.x == 0) s_item = queue_item(wl->q_nn, round);
+    __syncthreads();
+    const int g = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
     if (g >= wl->nn_total) break;
     const int a = __builtin_amdgcn_readfirstlane(find_slot(wl->nn_base, wl->n_active, g));
     // a wave-uniform slot keeps the descriptor's fields in scalar registers
@@ -282,10 +297,10 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
         }
         unsigned long long bal = __ballot(c);
         if (warm && bal) {
-          __syncthreads();
+          wave_lds_sync();
           s_box[lane] = blo;
           s_box[64 + lane] = bhi;
-          __syncthreads();
+          wave_lds_sync();
           const float thr = thr_m;
           unsigned long long need = 0ull;
           for (unsigned long long m = bal; m; m &= m - 1ull) {
@@ -312,8 +327,12 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
         // every lane tests the batch's boxes (staged in LDS) against its own
         // bound; the clusters some lane needs are appended to the list.
         const float thr = thr_m;
-        int n2 = 0;
-        for (int base = 0; base < nflat; base += 64) {
+        // the candidate batches are shared out among the block's wavefronts;
+        // needed clusters are appended through a block counter (the list's
+        // order varies, its contents do not)
+        if (threadIdx.x == 0) s_n2 = 0;
+        __syncthreads();
+        for (int base = 64 * wv; base < nflat; base += 64 * kCullWaves) {
           const int f = base + lane;
           int cid = f < nflat ? flat_cluster(f) : -1;
           float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = blo;
@@ -324,20 +343,25 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
           }
           const unsigned long long cand = __ballot(cid >= 0);
           if (cand == 0ull) continue;
-          __syncthreads();
+          wave_lds_sync();
           s_box[lane] = blo;
           s_box[64 + lane] = bhi;
-          __syncthreads();
+          wave_lds_sync();
           unsigned long long need = 0ull;
           for (unsigned long long m = cand; m; m &= m - 1ull) {
             const int j = __builtin_ctzll(m);
             const float lb2 = box_lb2(ptx, pty, ptz, s_box[j], s_box[64 + j]);
             if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr)) need |= 1ull << j;
           }
-          const int pos = n2 + __popcll(need & ((1ull << lane) - 1ull));
+          if (need == 0ull) continue;
+          int at = 0;
+          if (lane == 0) at = atomicAdd(&s_n2, __popcll(need));
+          at = __shfl(at, 0, 64);
+          const int pos = at + __popcll(need & ((1ull << lane) - 1ull));
           if (((need >> lane) & 1ull) && pos < kListCap) D.clist[(size_t)tile * kListCap + pos] = cid;
-          n2 += __popcll(need);
         }
+        __syncthreads();
+        const int n2 = s_n2;
         if (n2 > kListCap || n2 == 0) {
           // more needed clusters than a list holds (or none, which valid lanes
           // exclude): slices over all clusters, tested per lane
@@ -408,13 +432,15 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const SlotDesc* __restrict_
       len = max(kSliceMin, (n + kMaxSlices - 1) / kMaxSlices);
       nsl = max(1, (n + len - 1) / len);
     }
-    int base = 0;
-    if (lane == 0) {
-      D.tinfo[tile] = make_int4(flags, n, len, first);
-      base = atomicAdd(D.scount, nsl);
+    if (wv == 0) {
+      int base = 0;
+      if (lane == 0) {
+        D.tinfo[tile] = make_int4(flags, n, len, first);
+        base = atomicAdd(D.scount, nsl);
+      }
+      base = __shfl(base, 0, 64);
+      for (int k = lane; k < nsl; k += 64) D.squeue[base + k] = make_int2(tile, k);
     }
-    base = __shfl(base, 0, 64);
-    for (int k = lane; k < nsl; k += 64) D.squeue[base + k] = make_int2(tile, k);
   }
 }
 
@@ -620,7 +646,8 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
 
 void launch_nn(const SlotDesc* descs, const SlotState* states, WorkList* wl, int grid,
                bool single, hipStream_t st) {
-  hipLaunchKernelGGL(nn_cull_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
+  hipLaunchKernelGGL(nn_cull_kernel, dim3(grid / kCullWaves), dim3(64 * kCullWaves), 0, st, descs,
+                     states, wl);
   if (!single) hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl);
   hipLaunchKernelGGL(nn_slice_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
 }
