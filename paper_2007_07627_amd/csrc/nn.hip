@@ -504,7 +504,9 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     const int p0 = sl * len, p1 = min(n, p0 + len);
     const int* __restrict__ list = D.clist + (size_t)tile * kListCap;
     const bool from_list = (flags & TI_LIST) != 0;
-    const bool lane_test = (flags & TI_LANETEST) != 0;
+    // per-lane box test before a cluster is filtered: range tiles, and warm
+    // lists (built with the reuse margin, so this pass may need fewer)
+    const bool lane_test = (flags & (TI_LANETEST | TI_WARM)) != 0;
     // cluster sequence of this slice: entry 0 is the nearest cluster when the
     // tile has one, then positions p0 .. p1 - 1 (-1: skip)
     const int lead = first >= 0 ? 1 : 0;
