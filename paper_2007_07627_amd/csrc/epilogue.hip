@@ -1,8 +1,8 @@
 // Weight-and-reduce pass after the closest-point search: per source point the
 // FP64 residual at the evaluated transform, the Welsch weight and energy term,
 // and the moments of the alignment problem; one fixed-order FP64 partial per
-// 256-source tile (no floating-point atomics, so results do not depend on the
-// batch composition or on scheduling).
+// kEpiTile-source item (no floating-point atomics, so results do not depend on
+// the batch composition or on scheduling).
 //
 //  point-to-point (eq. WelschAlignment): w = exp(-r^2 / (2 nu^2)) (w = 1 for
 //    L2), energy psi_nu(r) = -expm1(-r^2 / (2 nu^2)) (eq. welsch) or r^2, and
@@ -38,6 +38,110 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* out)
   __syncthreads();
 }
 
+// Closest target of sorted source si from this pass's key (or the previous
+// pass's index when the transform is unchanged), with the FP64 residual at
+// the evaluated transform. Also hands the index on to the next pass.
+__device__ __forceinline__ bool source_residual(const SlotDesc& D, const SlotState& S,
+                                                const double* T, int si, int& idx, double& px,
+                                                double& py, double& pz, double& qxd, double& qyd,
+                                                double& qzd, double& dx, double& dy, double& dz) {
+  if (si >= D.M) return false;
+  if (!S.reuse) {
+    const unsigned long long key = D.keys[si];
+    idx = (int)(unsigned)(key & 0xffffffffull);
+    // every source receives a key from the search; stay in bounds regardless
+    if ((unsigned)idx >= (unsigned)D.N) idx = 0;
+    const float d2 = __uint_as_float((unsigned)(key >> 32));
+    D.nnidx[si] = idx;
+    D.nnd2[si] = d2;
+    D.keys[si] = ~0ull;  // ready for the next pass's atomic min
+    if (D.idx_out) {
+      const int o = D.perm[si];
+      D.idx_out[o] = idx;
+      D.d2_out[o] = d2;
+    }
+  } else {
+    idx = D.nnidx[si];
+  }
+  px = D.px[si];
+  py = D.py[si];
+  pz = D.pz[si];
+  // FP64 transform with the same fused order as the search, not rounded
+  const double x = __builtin_fma(T[2], pz, __builtin_fma(T[1], py, __builtin_fma(T[0], px, T[3])));
+  const double y = __builtin_fma(T[6], pz, __builtin_fma(T[5], py, __builtin_fma(T[4], px, T[7])));
+  const double z = __builtin_fma(T[10], pz, __builtin_fma(T[9], py, __builtin_fma(T[8], px, T[11])));
+  qxd = D.qx[idx];
+  qyd = D.qy[idx];
+  qzd = D.qz[idx];
+  dx = x - qxd;
+  dy = y - qyd;
+  dz = z - qzd;
+  return true;
+}
+
+__device__ __forceinline__ void accumulate_p2p(const SlotDesc& D, const SlotState& S,
+                                               const double* T, int si, double (&v)[kP2PVals]) {
+  int idx = 0;
+  double px, py, pz, qxd, qyd, qzd, dx, dy, dz;
+  if (!source_residual(D, S, T, si, idx, px, py, pz, qxd, qyd, qzd, dx, dy, dz)) return;
+  const double s = S.inv2nu2;
+  const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+  double w = 1.0;
+  if (D.mode == P2P_L2) {
+    v[0] += r2;
+  } else {
+    v[0] += -expm1(-r2 * s);
+    w = exp(-r2 * s);
+  }
+  if (S.want_median) D.medkey[si] = r2;
+  const double a0 = px - S.cP[0], a1 = py - S.cP[1], a2 = pz - S.cP[2];
+  const double b0 = qxd - S.cQ[0], b1 = qyd - S.cQ[1], b2 = qzd - S.cQ[2];
+  const double wa0 = w * a0, wa1 = w * a1, wa2 = w * a2;
+  v[1] += w;
+  v[2] += wa0; v[3] += wa1; v[4] += wa2;
+  v[5] += w * b0; v[6] += w * b1; v[7] += w * b2;
+  v[8] += wa0 * b0; v[9] += wa0 * b1; v[10] += wa0 * b2;
+  v[11] += wa1 * b0; v[12] += wa1 * b1; v[13] += wa1 * b2;
+  v[14] += wa2 * b0; v[15] += wa2 * b1; v[16] += wa2 * b2;
+}
+
+__device__ __forceinline__ void accumulate_p2pl(const SlotDesc& D, const SlotState& S,
+                                                const double* T, int si, double (&v)[kP2PLVals]) {
+  int idx = 0;
+  double px, py, pz, qxd, qyd, qzd, dx, dy, dz;
+  if (!source_residual(D, S, T, si, idx, px, py, pz, qxd, qyd, qzd, dx, dy, dz)) return;
+  const double s = S.inv2nu2;
+  const double n0 = D.nx[idx], n1 = D.ny[idx], n2 = D.nz[idx];
+  const double B = __builtin_fma(dz, n2, __builtin_fma(dy, n1, dx * n0));
+  const double B2s = B * B * s;
+  const double gam = exp(-B2s);
+  v[0] += -expm1(-B2s);
+  v[1] += gam;
+  if (S.want_median) D.medkey[si] = fabs(B);
+  // J: rotation part n . (dR_j p + dt/d delta_j), translation part (dt/du)^T n
+  const double* K = S.K;
+  double J[6];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double* R = K + 9 * j;
+    const double r0 = R[0] * px + R[1] * py + R[2] * pz + K[27 + 0 + j];
+    const double r1 = R[3] * px + R[4] * py + R[5] * pz + K[27 + 3 + j];
+    const double r2 = R[6] * px + R[7] * py + R[8] * pz + K[27 + 6 + j];
+    J[j] = n0 * r0 + n1 * r1 + n2 * r2;
+    J[3 + j] = K[36 + j] * n0 + K[36 + 3 + j] * n1 + K[36 + 6 + j] * n2;
+  }
+  int t = 2;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    const double ga = gam * J[a];
+#pragma unroll
+    for (int b = a; b < 6; ++b) v[t++] += ga * J[b];
+  }
+  const double gB = gam * B;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) v[23 + a] += gB * J[a];
+}
+
 __global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ descs,
                                                   const SlotState* __restrict__ states,
                                                   WorkList* __restrict__ wl) {
@@ -60,105 +164,23 @@ __global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ d
     const SlotDesc& D = descs[slot];
     const SlotState& S = states[slot];
     const int e = g - wl->epi_base[lo];
-    const int si = e * kEpiTile + threadIdx.x;
-    const bool valid = si < D.M;
     const double* T = S.Teval;
-
-    int idx = 0;
-    double px = 0, py = 0, pz = 0, dx = 0, dy = 0, dz = 0, qxd = 0, qyd = 0, qzd = 0;
-    if (valid) {
-      if (!S.reuse) {
-        const unsigned long long key = D.keys[si];
-        idx = (int)(unsigned)(key & 0xffffffffull);
-        // every source receives a key from the search; stay in bounds regardless
-        if ((unsigned)idx >= (unsigned)D.N) idx = 0;
-        const float d2 = __uint_as_float((unsigned)(key >> 32));
-        D.nnidx[si] = idx;
-        D.nnd2[si] = d2;
-        D.keys[si] = ~0ull;  // ready for the next pass's atomic min
-        if (D.idx_out) {
-          const int o = D.perm[si];
-          D.idx_out[o] = idx;
-          D.d2_out[o] = d2;
-        }
-      } else {
-        idx = D.nnidx[si];
-      }
-      px = D.px[si];
-      py = D.py[si];
-      pz = D.pz[si];
-      // FP64 transform with the same fused order as the search, not rounded
-      const double x = __builtin_fma(T[2], pz, __builtin_fma(T[1], py, __builtin_fma(T[0], px, T[3])));
-      const double y = __builtin_fma(T[6], pz, __builtin_fma(T[5], py, __builtin_fma(T[4], px, T[7])));
-      const double z = __builtin_fma(T[10], pz, __builtin_fma(T[9], py, __builtin_fma(T[8], px, T[11])));
-      qxd = D.qx[idx];
-      qyd = D.qy[idx];
-      qzd = D.qz[idx];
-      dx = x - qxd;
-      dy = y - qyd;
-      dz = z - qzd;
-    }
     double* out = D.part + (size_t)e * kPartStride;
-    const double s = S.inv2nu2;
+    // each thread accumulates kEpiRows sources (one per 256-source row of the
+    // item) in row order, then the block reduces in a fixed order
     if (D.mode != P2PL_WELSCH) {
       double v[kP2PVals];
 #pragma unroll
       for (int i = 0; i < kP2PVals; ++i) v[i] = 0.0;
-      if (valid) {
-        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        double w = 1.0;
-        if (D.mode == P2P_L2) {
-          v[0] = r2;
-        } else {
-          v[0] = -expm1(-r2 * s);
-          w = exp(-r2 * s);
-        }
-        if (S.want_median) D.medkey[si] = r2;
-        const double a0 = px - S.cP[0], a1 = py - S.cP[1], a2 = pz - S.cP[2];
-        const double b0 = qxd - S.cQ[0], b1 = qyd - S.cQ[1], b2 = qzd - S.cQ[2];
-        v[1] = w;
-        v[2] = w * a0; v[3] = w * a1; v[4] = w * a2;
-        v[5] = w * b0; v[6] = w * b1; v[7] = w * b2;
-        v[8] = v[2] * b0; v[9] = v[2] * b1; v[10] = v[2] * b2;
-        v[11] = v[3] * b0; v[12] = v[3] * b1; v[13] = v[3] * b2;
-        v[14] = v[4] * b0; v[15] = v[4] * b1; v[16] = v[4] * b2;
-      }
+#pragma unroll
+      for (int r = 0; r < kEpiRows; ++r) accumulate_p2p(D, S, T, e * kEpiTile + 256 * r + threadIdx.x, v);
       block_reduce_store<kP2PVals>(v, out);
     } else {
       double v[kP2PLVals];
 #pragma unroll
       for (int i = 0; i < kP2PLVals; ++i) v[i] = 0.0;
-      if (valid) {
-        const double n0 = D.nx[idx], n1 = D.ny[idx], n2 = D.nz[idx];
-        const double B = __builtin_fma(dz, n2, __builtin_fma(dy, n1, dx * n0));
-        const double B2s = B * B * s;
-        const double gam = exp(-B2s);
-        v[0] = -expm1(-B2s);
-        v[1] = gam;
-        if (S.want_median) D.medkey[si] = fabs(B);
-        // J: rotation part n . (dR_j p + dt/d delta_j), translation part (dt/du)^T n
-        const double* K = S.K;
-        double J[6];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const double* R = K + 9 * j;
-          const double r0 = R[0] * px + R[1] * py + R[2] * pz + K[27 + 0 + j];
-          const double r1 = R[3] * px + R[4] * py + R[5] * pz + K[27 + 3 + j];
-          const double r2 = R[6] * px + R[7] * py + R[8] * pz + K[27 + 6 + j];
-          J[j] = n0 * r0 + n1 * r1 + n2 * r2;
-          J[3 + j] = K[36 + j] * n0 + K[36 + 3 + j] * n1 + K[36 + 6 + j] * n2;
-        }
-        int t = 2;
-#pragma unroll
-        for (int a = 0; a < 6; ++a) {
-          const double ga = gam * J[a];
-#pragma unroll
-          for (int b = a; b < 6; ++b) v[t++] = ga * J[b];
-        }
-        const double gB = gam * B;
-#pragma unroll
-        for (int a = 0; a < 6; ++a) v[23 + a] = gB * J[a];
-      }
+      for (int r = 0; r < kEpiRows; ++r) accumulate_p2pl(D, S, T, e * kEpiTile + 256 * r + threadIdx.x, v);
       block_reduce_store<kP2PLVals>(v, out);
     }
   }

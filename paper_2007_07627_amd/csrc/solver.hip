@@ -274,7 +274,7 @@ __device__ bool top_eig_rqi(const double A[16], const double x0[4], double q[4],
   nA = sqrt(nA);
   if (!(nA > 0.0)) return false;
   double x[4] = {x0[0], x0[1], x0[2], x0[3]};
-  double mu = 0.0, rn = 0.0;
+  double mu = 0.0, rn = 0.0, rn_prev = __builtin_inf();
   bool settled = false;
   for (int it = 0; it < 6; ++it) {
     double Ax[4];
@@ -285,8 +285,9 @@ __device__ bool top_eig_rqi(const double A[16], const double x0[4], double q[4],
 #pragma unroll
     for (int i = 0; i < 4; ++i) r2 += (Ax[i] - mu * x[i]) * (Ax[i] - mu * x[i]);
     rn = sqrt(r2);
-    if (settled) break;               // one polishing step after the residual settled
-    if (rn <= 1e-13 * nA) settled = true;
+    // settled: at the rounding level, or no longer shrinking (the noise floor)
+    if (rn <= 1e-15 * nA || (rn <= 1e-12 * nA && rn > 0.25 * rn_prev)) { settled = true; break; }
+    rn_prev = rn;
     double M[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) M[i] = A[i] - ((i % 5 == 0) ? mu : 0.0);
