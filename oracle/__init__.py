@@ -79,6 +79,9 @@ def lib():
         L.orc_eval.argtypes = [f32p, C.c_int64, f32p, C.c_void_p, C.c_int64, C.c_int, f64p,
                                C.c_double, C.POINTER(C.c_double), f64p, C.POINTER(C.c_uint)]
         L.orc_eval.restype = C.c_int
+        L.orc_nu_min_auto.argtypes = [f32p, C.c_void_p, C.c_int64, C.c_int, C.POINTER(C.c_double),
+                                      C.c_void_p]
+        L.orc_nu_min_auto.restype = C.c_int
         _lib = L
     return _lib
 
@@ -167,6 +170,24 @@ def anderson_solve(dF, Fk, metric):
 def median(v):
     v = _f64(v)
     return lib().orc_median(v, v.shape[0])
+
+
+def nu_min_auto(Q, Qn, mode, per_point=False):
+    """Automatic nu_min (Sec. 4.3 / Sec. 5, App. C) of a target set; with
+    per_point, also the per-target medians (squared distances for
+    point-to-point, tangent-plane distances for point-to-plane)."""
+    Q = _f32(Q).reshape(-1, 3)
+    qn = None
+    if Qn is not None:
+        Qn = _f32(Qn).reshape(-1, 3)
+        qn = Qn.ctypes.data
+    out = C.c_double(0.0)
+    pp = np.zeros(Q.shape[0]) if per_point else None
+    rc = lib().orc_nu_min_auto(Q, qn, Q.shape[0], int(mode), C.byref(out),
+                               pp.ctypes.data if per_point else None)
+    if rc != 0:
+        raise ValueError("orc_nu_min_auto: invalid arguments")
+    return (out.value, pp) if per_point else out.value
 
 
 def eval_map(P, Q, Qn, mode, T, nu=0.0):

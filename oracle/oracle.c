@@ -567,6 +567,67 @@ double orc_median(const double *v, int64_t n) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Automatic nu_min (Sec. 4.3, Sec. 5, App. C)                                */
+/* ------------------------------------------------------------------------ */
+
+/* The six nearest other targets of q_i by exhaustive scan: candidates are
+ * ordered by (exact FP32 squared distance of q_i - q_j, index j). */
+static void six_nearest(const float *Q, int64_t N, int64_t i, int64_t nb[6]) {
+  float bd[6];
+  int cnt = 0;
+  const float qx = Q[3 * i], qy = Q[3 * i + 1], qz = Q[3 * i + 2];
+  for (int64_t j = 0; j < N; ++j) {
+    if (j == i) continue;
+    const float dx = qx - Q[3 * j], dy = qy - Q[3 * j + 1], dz = qz - Q[3 * j + 2];
+    const float d = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    /* scanning j upwards, a later equal distance never displaces an earlier one */
+    int pos = cnt < 6 ? cnt : 6;
+    while (pos > 0 && d < bd[pos - 1]) --pos;
+    if (pos >= 6) continue;
+    const int last = cnt < 6 ? cnt : 5;
+    for (int k = last; k > pos; --k) {
+      bd[k] = bd[k - 1];
+      nb[k] = nb[k - 1];
+    }
+    bd[pos] = d;
+    nb[pos] = j;
+    if (cnt < 6) ++cnt;
+  }
+}
+
+int orc_nu_min_auto(const float *Q, const float *Qn, int64_t N, int mode, double *nu_min,
+                    double *per_point) {
+  if (N < 7 || !nu_min || (mode == ORC_P2PL_WELSCH && !Qn)) return -1;
+  double *v = (double *)malloc(sizeof(double) * (size_t)N);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t nb[6];
+    six_nearest(Q, N, i, nb);
+    double e[6];
+    for (int k = 0; k < 6; ++k) {
+      const int64_t j = nb[k];
+      if (mode == ORC_P2PL_WELSCH) {
+        /* distance of q_j to the tangent plane at q_i (normal n_i as given) */
+        const double dx = (double)Q[3 * j] - (double)Q[3 * i];
+        const double dy = (double)Q[3 * j + 1] - (double)Q[3 * i + 1];
+        const double dz = (double)Q[3 * j + 2] - (double)Q[3 * i + 2];
+        e[k] = fabs(fma((double)Qn[3 * i + 2], dz, fma((double)Qn[3 * i + 1], dy, (double)Qn[3 * i] * dx)));
+      } else {
+        /* squared distance (the median is taken on squares, sqrt at the end) */
+        const float dx = Q[3 * i] - Q[3 * j], dy = Q[3 * i + 1] - Q[3 * j + 1], dz = Q[3 * i + 2] - Q[3 * j + 2];
+        e[k] = (double)fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      }
+    }
+    v[i] = orc_median(e, 6);
+  }
+  const double med = orc_median(v, N);
+  if (per_point) memcpy(per_point, v, sizeof(double) * (size_t)N);
+  free(v);
+  *nu_min = (mode == ORC_P2PL_WELSCH) ? med / 6.0 : sqrt(med) / (3.0 * sqrt(3.0));
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Registration (Algorithm 1 with L2 or Welsch metric; Algorithm 2)           */
 /* ------------------------------------------------------------------------ */
 

@@ -89,6 +89,18 @@ int orc_anderson_solve(const double *dF, const double *Fk, int m, int metric,
 /* Element of rank floor(n/2) in ascending order (copy is sorted). */
 double orc_median(const double *v, int64_t n);
 
+/* Automatic nu_min (Sec. 4.3 for point-to-point, Sec. 5 for point-to-plane,
+ * rationale in App. C). For every target q_i: its six nearest other targets
+ * (exact FP32 squared distances of q_i - q_j, ties to the lower index, j != i);
+ * point-to-point: the median of their distances, Ebar = median over i,
+ * nu_min = Ebar / (3 sqrt 3); point-to-plane: the median of their distances
+ * |n_i . (q_j - q_i)| to the tangent plane at q_i, Hbar = median over i,
+ * nu_min = Hbar / 6. Medians are elements of rank floor(n/2). Needs N >= 7
+ * (returns -1 otherwise, or for point-to-plane without normals). The
+ * per-point values (FP64) go to per_point when it is not NULL. */
+int orc_nu_min_auto(const float *Q, const float *Qn, int64_t N, int mode, double *nu_min,
+                    double *per_point);
+
 /* Full registration: Fast ICP (L2 + AA), Algorithm 1, Algorithm 2.
  * Qn may be NULL except for ORC_P2PL_WELSCH. trace (optional) receives one
  * row of 20 doubles per evaluation [E, nu, -1, reused, T(16)], up to

@@ -440,3 +440,72 @@ def test_register_rejects_bad_arguments():
     T[0, 0] = 2
     with pytest.raises(ValueError):
         oracle.register(P, P, mode=0, T0=T)
+
+
+# ------------------------------------------------------------------ automatic nu_min
+# Sec. 4.3 (point-to-point: Ebar / (3 sqrt 3)) and Sec. 5 (point-to-plane:
+# Hbar / 6), App. C; medians of even counts are the element of rank n/2.
+
+def _lattice(n=40, h=2.0 ** -6):
+    g = np.stack(np.meshgrid(np.arange(n) * h, np.arange(n) * h, indexing="ij"), -1).reshape(-1, 2)
+    return np.c_[g, np.zeros(len(g))].astype(np.float32), h
+
+
+def test_nu_min_auto_square_lattice_closed_form():
+    """Interior points of a square lattice (spacing h, exact in FP32): the six
+    nearest are 4 at h and 2 of the 4 diagonals at h sqrt 2, so the median of
+    six (rank 3) is h; boundary points are fewer than half."""
+    Q, h = _lattice()
+    assert oracle.nu_min_auto(Q, None, oracle.P2P_WELSCH) == h / (3.0 * math.sqrt(3.0))
+
+
+def test_nu_min_auto_duplicates_count_at_distance_zero():
+    """Every lattice point twice: the six nearest of a point are its duplicate
+    (distance 0) and five of the eight copies of its axis neighbours; rank 3
+    is still h."""
+    Q, h = _lattice()
+    Q2 = np.concatenate([Q, Q])
+    assert oracle.nu_min_auto(Q2, None, oracle.P2P_WELSCH) == h / (3.0 * math.sqrt(3.0))
+
+
+def test_nu_min_auto_point_to_plane_lifted_lattice():
+    """Square lattice with every other column lifted by a << h, normals +z:
+    the six nearest of an interior point are 2 in its column (plane distance
+    0), its 2 other axis neighbours and 2 diagonals (plane distance a), so
+    the median (rank 3) is a and nu_min = a / 6."""
+    Q, h = _lattice()
+    a = 2.0 ** -14
+    n = 40
+    lift = (np.arange(len(Q)) % n) % 2 == 1
+    Q[lift, 2] = a
+    Qn = np.tile(np.float32([0, 0, 1]), (len(Q), 1))
+    assert oracle.nu_min_auto(Q, Qn, oracle.P2PL_WELSCH) == a / 6.0
+
+
+def test_nu_min_auto_brute_force_small_random():
+    """Independent numpy brute force on a small random set (no near-ties):
+    per-point sixth-order statistics, medians of rank n/2, the two formulas."""
+    rng = np.random.default_rng(7)
+    Q = rng.standard_normal((61, 3)).astype(np.float32)
+    Qn = rng.standard_normal((61, 3))
+    Qn = (Qn / np.linalg.norm(Qn, axis=1, keepdims=True)).astype(np.float32)
+    Qd = Q.astype(np.float64)
+    d2 = ((Qd[:, None, :] - Qd[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2, np.inf)
+    nb = np.argsort(d2, axis=1, kind="stable")[:, :6]
+    e = np.sort(np.take_along_axis(d2, nb, 1), axis=1)[:, 3]
+    ebar = np.sort(e)[len(e) // 2]
+    got = oracle.nu_min_auto(Q, None, oracle.P2P_WELSCH)
+    assert abs(got - math.sqrt(ebar) / (3 * math.sqrt(3))) < 1e-6 * got
+    H = np.abs(np.einsum("ik,ijk->ij", Qn.astype(np.float64), Qd[nb] - Qd[:, None, :]))
+    hbar = np.sort(np.sort(H, axis=1)[:, 3])[len(Q) // 2]
+    got = oracle.nu_min_auto(Q, Qn, oracle.P2PL_WELSCH)
+    assert abs(got - hbar / 6) < 1e-6 * got
+
+
+def test_nu_min_auto_rejects_tiny_sets_and_missing_normals():
+    Q = np.zeros((6, 3), np.float32)
+    with pytest.raises(ValueError):
+        oracle.nu_min_auto(Q, None, oracle.P2P_WELSCH)
+    with pytest.raises(ValueError):
+        oracle.nu_min_auto(np.zeros((10, 3), np.float32), None, oracle.P2PL_WELSCH)
