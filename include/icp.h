@@ -68,7 +68,7 @@ typedef struct {
   icp_mode mode;
   int anderson_m;        /* Anderson depth m in [0, 6]; 0 disables mixing (plain MM); paper: 5 (Sec. 4.2) */
   double nu_max;         /* <= 0: 3 x median of the initial residuals (Sec. 4.3, Sec. 5) */
-  double nu_min;         /* > 0, required for the Welsch modes (the paper's kNN rule is not built) */
+  double nu_min;         /* > 0; <= 0: the paper's automatic rule (icp_nu_min_auto, N >= 7) */
   double eps;            /* stage threshold on ||T - T'||_F (p2p) / ||xi* - xi|| (p2pl); paper 1e-5 */
   int iter_first;        /* I_nu of the first stage; paper: 1000 (p2p), 6 (p2pl) */
   int iter_inc;          /* I_nu increment per stage; paper: 0 (p2p), 1 (p2pl) */
@@ -188,6 +188,19 @@ icp_status icp_nn_query(icp_ctx *ctx, const float *P, int64_t M, const float *Q,
 icp_status icp_nn_query_dev(icp_ctx *ctx, const float *P_dev, int64_t M, const float *Q_dev,
                             int64_t N, const double T[16], icp_nn_method method,
                             int32_t *idx_out_dev, float *d2_out_dev, void *stream);
+
+/* Automatic nu_min of a target set (Sec. 4.3 for point-to-point, Sec. 5 for
+ * point-to-plane; rationale in App. C), the value a registration uses when
+ * its params.nu_min <= 0: for every target its six nearest other targets
+ * (exact FP32 squared distances, ties to the lower index); point-to-point
+ * (mode ICP_P2P_WELSCH): the median over targets of the median of their
+ * distances, Ebar, and nu_min = Ebar / (3 sqrt 3); point-to-plane (mode
+ * ICP_P2PL_WELSCH, normals Qn required, used as given): the same with the
+ * distances |n_i . (q_j - q_i)| to the tangent plane, Hbar, and
+ * nu_min = Hbar / 6. Medians of n values are the element of rank n / 2.
+ * Q, Qn: host AoS N x 3 FP32, N >= 7 (else ICP_ERR_INVALID_ARG). Synchronous. */
+icp_status icp_nu_min_auto(icp_ctx *ctx, const float *Q, const float *Qn, int64_t N,
+                           icp_mode mode, double *nu_min_out);
 
 /* Batched / served registration. Each request is validated and its arrays are
  * copied to pinned staging before the call returns (the caller may free them

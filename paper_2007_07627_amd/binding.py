@@ -24,7 +24,7 @@ ICP_FLAG_DEGENERATE, ICP_FLAG_AA_SINGULAR = 8, 16
 EXPORTED = ["icp_create", "icp_destroy", "icp_params_default", "icp_register", "icp_register_trace",
             "icp_eval", "icp_trace_items",
             "icp_register_dev",
-            "icp_nn_query", "icp_nn_query_dev", "icp_batch_submit", "icp_poll",
+            "icp_nn_query", "icp_nn_query_dev", "icp_nu_min_auto", "icp_batch_submit", "icp_poll",
             "icp_batch_wait_all", "icp_batch_config", "icp_profile", "icp_profile_read",
             "icp_status_str"]
 
@@ -89,6 +89,7 @@ def lib():
         L.icp_nn_query_dev.argtypes = [vp, vp, i64, vp, i64, vp, i32, vp, vp, vp]
         L.icp_batch_submit.argtypes = [vp, C.POINTER(icp_request), i32, C.POINTER(C.c_uint64)]
         L.icp_poll.argtypes = [vp, C.c_uint64, C.POINTER(icp_result)]
+        L.icp_nu_min_auto.argtypes = [vp, vp, vp, C.c_int64, i32, C.POINTER(C.c_double)]
         L.icp_batch_wait_all.argtypes = [vp]
         L.icp_batch_config.argtypes = [vp, i32, i32]
         L.icp_profile.argtypes = [vp, i32]
@@ -211,6 +212,18 @@ def icp_register_dev(ctx, P_t, Q_t, Qn_t=None, params: icp_params | None = None,
                                 C.byref(params), C.byref(r), st)
     _check(rc, "icp_register_dev")
     return result_dict(r)
+
+
+def icp_nu_min_auto(ctx, Q, Qn=None, mode: int = ICP_P2P_WELSCH, raw=False):
+    """Automatic nu_min of a target set (the value params.nu_min <= 0 selects)."""
+    Q = _f32(Q)
+    Qn = None if Qn is None else _f32(Qn)
+    out = C.c_double(0.0)
+    rc = lib().icp_nu_min_auto(ctx, _ptr(Q), _ptr(Qn), Q.shape[0], int(mode), C.byref(out))
+    if raw:
+        return rc, out.value
+    _check(rc, "icp_nu_min_auto")
+    return out.value
 
 
 def icp_nn_query(ctx, P, Q, T=None, method: int = ICP_NN_AUTO, raw=False):

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libicp.so")
-SOURCES = ["nn.hip", "epilogue.hip", "solver.hip", "setup.hip", "engine.hip"]
+SOURCES = ["nn.hip", "knn.hip", "epilogue.hip", "solver.hip", "setup.hip", "engine.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

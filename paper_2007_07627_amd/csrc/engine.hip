@@ -30,6 +30,9 @@ void launch_epi(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
 void launch_solver(const SlotDesc*, SlotState*, int, int*, WorkList*, bool, hipStream_t);
 void launch_boot(const SlotDesc*, SlotState*, int, WorkList*, bool, hipStream_t);
 void launch_median(const SlotDesc*, SlotState*, int, hipStream_t);
+void launch_nu_min_auto(const float4*, const float4*, const float4*, const float4*, const float4*, int,
+                        int, const float*, const float*, const float*, const float*, const float*,
+                        const float*, int, bool, double*, double*, hipStream_t);
 void launch_plan(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
 void launch_aos_to_soa(const float*, int, float*, float*, float*, hipStream_t);
 void launch_bbox(const float*, const float*, const float*, int, float*, double*, hipStream_t);
@@ -187,6 +190,7 @@ struct OwnedRequest {
   icp_params prm{};
   bool query = false;
   bool eval = false;   // one application of the MM map (icp_eval)
+  bool numin_only = false;  // only the automatic nu_min of the targets (icp_nu_min_auto)
   double Tq[16];
   icp_nn_method qmethod = ICP_NN_AUTO;
   int32_t* idx_dev_out = nullptr;  // device outputs for a dev query
@@ -195,6 +199,9 @@ struct OwnedRequest {
   uint64_t ticket = 0;
   Clock::time_point t_submit;
 };
+
+// nu_min <= 0 selects the automatic rule for the Welsch modes.
+static bool auto_nu_min(const icp_params* p) { return p->mode != ICP_P2P_L2 && !(p->nu_min > 0.0); }
 
 static void fill_stats(const HostSlot& h, hipStream_t st, icp_result* r) {
   unsigned long long v[kQueues * kStatStride] = {};
@@ -445,6 +452,16 @@ struct Engine {
                           F4(L.o_qorg), F4(L.o_ccen), F4(L.o_clo), F4(L.o_chi), ss);
     launch_build_super(F4(L.o_clo), F4(L.o_chi), F4(L.o_ccen), L.ncl, L.nsup, F4(L.o_slo),
                        F4(L.o_shi), rho, ss);
+    // automatic nu_min from the targets' six nearest neighbours, into the
+    // state (scratch holds the per-target values until the source sort)
+    if (r.numin_only || (!r.query && !r.eval && auto_nu_min(&r.prm))) {
+      const bool plane = r.prm.mode == ICP_P2PL_WELSCH;
+      launch_nu_min_auto(F4(L.o_qorg), F4(L.o_clo), F4(L.o_chi), F4(L.o_slo), F4(L.o_shi), L.ncl,
+                         L.nsup, F(L.o_qx), F(L.o_qy), F(L.o_qz), plane ? F(L.o_nx) : nullptr,
+                         plane ? F(L.o_ny) : nullptr, plane ? F(L.o_nz) : nullptr, L.N, plane,
+                         reinterpret_cast<double*>(b + L.o_scratch),
+                         reinterpret_cast<double*>(st_base + offsetof(SlotState, nu_min)), ss);
+    }
     // source tiles
     launch_bbox(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, cP, ss);
     launch_morton_order(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, scratch, &order, ss);
@@ -584,7 +601,8 @@ static icp_status check_params(const icp_params* p) {
   if (!p) return ICP_ERR_INVALID_ARG;
   if (p->mode < ICP_P2P_L2 || p->mode > ICP_P2PL_WELSCH) return ICP_ERR_INVALID_ARG;
   if (p->anderson_m < 0 || p->anderson_m > 6) return ICP_ERR_INVALID_ARG;
-  if (p->mode != ICP_P2P_L2 && !(p->nu_min > 0.0 && std::isfinite(p->nu_min))) return ICP_ERR_INVALID_ARG;
+  // nu_min <= 0: the automatic rule (six nearest targets), which needs N >= 7
+  if (p->mode != ICP_P2P_L2 && !std::isfinite(p->nu_min)) return ICP_ERR_INVALID_ARG;
   if (!(p->eps > 0.0) || p->iter_first <= 0 || p->max_line_search < 0) return ICP_ERR_INVALID_ARG;
   if (p->nn < ICP_NN_AUTO || p->nn > ICP_NN_CLUSTER) return ICP_ERR_INVALID_ARG;
   if (p->engine != ICP_ENGINE_GRAPH && p->engine != ICP_ENGINE_PLAIN) return ICP_ERR_INVALID_ARG;
@@ -595,6 +613,13 @@ static icp_status check_params(const icp_params* p) {
 
 static icp_status check_sizes(int64_t M, int64_t N) {
   if (M <= 0 || N <= 0 || M > (1 << 28) || N > (1 << 28)) return ICP_ERR_INVALID_ARG;
+  return ICP_OK;
+}
+
+static icp_status check_params_sized(const icp_params* p, int64_t N) {
+  const icp_status s = check_params(p);
+  if (s != ICP_OK) return s;
+  if (auto_nu_min(p) && N < 7) return ICP_ERR_INVALID_ARG;  // six other targets needed
   return ICP_OK;
 }
 
@@ -900,7 +925,7 @@ static icp_status validate_host(const float* P, int64_t M, const float* Q, const
   if (!P || !Q) return ICP_ERR_INVALID_ARG;
   icp_status s = check_sizes(M, N);
   if (s != ICP_OK) return s;
-  s = check_params(prm);
+  s = check_params_sized(prm, N);
   if (s != ICP_OK) return s;
   if (prm->mode == ICP_P2PL_WELSCH && !Qn) return ICP_ERR_NO_NORMALS;
   if (!finite_coords(P, M) || !finite_coords(Q, N)) return ICP_ERR_NONFINITE;
@@ -991,7 +1016,7 @@ icp_status icp_register_dev(icp_ctx* ctx, const float* P_dev, int64_t M, const f
   if (!ctx || !out || !P_dev || !Q_dev) return ICP_ERR_INVALID_ARG;
   icp_status s = check_sizes(M, N);
   if (s != ICP_OK) return s;
-  s = check_params(params);
+  s = check_params_sized(params, N);
   if (s != ICP_OK) return s;
   if (params->mode == ICP_P2PL_WELSCH && !Qn_dev) return ICP_ERR_NO_NORMALS;
   OwnedRequest r;
@@ -1020,6 +1045,37 @@ icp_status icp_nn_query(icp_ctx* ctx, const float* P, int64_t M, const float* Q,
   std::lock_guard<std::mutex> g(ctx->sync_mu);
   icp_result res;
   return run_sync(ctx, r, &res, nullptr, idx_out, d2_out);
+}
+
+icp_status icp_nu_min_auto(icp_ctx* ctx, const float* Q, const float* Qn, int64_t N, icp_mode mode,
+                           double* nu_min_out) {
+  if (!ctx || !Q || !nu_min_out) return ICP_ERR_INVALID_ARG;
+  if (mode != ICP_P2P_WELSCH && mode != ICP_P2PL_WELSCH) return ICP_ERR_INVALID_ARG;
+  if (N < 7 || N > (1 << 28)) return ICP_ERR_INVALID_ARG;
+  icp_params prm;
+  icp_params_default(mode, &prm);
+  prm.nu_min = 0.0;
+  // the targets stand in for the sources: the setup needs both sets
+  const icp_status v = validate_host(Q, N, Q, Qn, N, &prm);
+  if (v != ICP_OK) return v;
+  OwnedRequest r;
+  r.P.assign(Q, Q + 3 * N);
+  r.Q.assign(Q, Q + 3 * N);
+  if (mode == ICP_P2PL_WELSCH) r.Qn.assign(Qn, Qn + 3 * N);
+  r.M = N; r.N = N; r.prm = prm;
+  r.numin_only = true;
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  Engine& E = ctx->sync_eng;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ICP_ERR_DEVICE;
+  bool oom = false;
+  if (!E.admit(0, r, &oom)) { E.release(0); return ICP_ERR_DEVICE; }
+  if (oom) return ICP_ERR_OOM;
+  SlotState S;
+  const bool ok = E.read_state(0, &S);
+  E.release(0);
+  if (!ok) return ICP_ERR_DEVICE;
+  *nu_min_out = S.nu_min;
+  return ICP_OK;
 }
 
 icp_status icp_nn_query_dev(icp_ctx* ctx, const float* P_dev, int64_t M, const float* Q_dev,

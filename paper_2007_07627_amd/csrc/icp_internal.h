@@ -148,6 +148,22 @@ constexpr int kQueues = 8;
 constexpr int kQueueStride = 64;  // ints between sub-queue counters
 constexpr int kStatStride = 32;  // u64 between per-die statistics lines
 
+// Closest-point key: the FP32 squared distance's bits above the target
+// index, so that the integer minimum is the lexicographic (d2, index) minimum.
+__device__ __forceinline__ unsigned long long make_key(float d2, int idx) {
+  return ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)idx;
+}
+
+// Squared distance from a point to an axis-aligned box (0 inside); every
+// member of the box is at exact squared distance at least this (up to the
+// rounding of this expression, which callers allow for).
+__device__ __forceinline__ float box_lb2(float px, float py, float pz, float4 lo, float4 hi) {
+  const float dx = fmaxf(fmaxf(lo.x - px, px - hi.x), 0.0f);
+  const float dy = fmaxf(fmaxf(lo.y - py, py - hi.y), 0.0f);
+  const float dz = fmaxf(fmaxf(lo.z - pz, pz - hi.z), 0.0f);
+  return dx * dx + dy * dy + dz * dz;
+}
+
 // Active-slot work lists rebuilt before every phase.
 struct WorkList {
   int n_active;

@@ -61,9 +61,6 @@ __device__ __forceinline__ float winner_threshold(float H) {
   return H + 2.2e-6f * fabsf(H) + 1e-37f;
 }
 
-__device__ __forceinline__ unsigned long long make_key(float d2, int idx) {
-  return ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)idx;
-}
 
 // Exact FP32 scan of n targets of the original-coordinate array.
 // Pointers read from a slot descriptor are generic; loading through a global
@@ -95,12 +92,6 @@ __device__ __forceinline__ unsigned long long exact_scan(const float4* qorg, int
   return key;
 }
 
-__device__ __forceinline__ float box_lb2(float px, float py, float pz, float4 lo, float4 hi) {
-  const float dx = fmaxf(fmaxf(lo.x - px, px - hi.x), 0.0f);
-  const float dy = fmaxf(fmaxf(lo.y - py, py - hi.y), 0.0f);
-  const float dz = fmaxf(fmaxf(lo.z - pz, pz - hi.z), 0.0f);
-  return dx * dx + dy * dy + dz * dz;
-}
 
 __device__ __forceinline__ float box_ub2(float px, float py, float pz, float4 lo, float4 hi) {
   const float dx = fmaxf(fabsf(px - lo.x), fabsf(px - hi.x));

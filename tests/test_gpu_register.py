@@ -137,7 +137,11 @@ def test_plain_and_graph_engines_bit_identical(ctx):
 
 def test_register_invalid_arguments(ctx):
     P = np.zeros((10, 3), np.float32)
-    prm = B.icp_params_default(B.ICP_P2P_WELSCH)  # nu_min unset
+    # nu_min unset selects the automatic rule, which needs 7 targets
+    prm = B.icp_params_default(B.ICP_P2P_WELSCH)
+    rc, _ = B.icp_register(ctx, P, P[:6], None, prm, raw=True)
+    assert rc == B.ICP_ERR_INVALID_ARG
+    prm = B.icp_params_default(B.ICP_P2P_WELSCH, nu_min=float("nan"))
     rc, _ = B.icp_register(ctx, P, P, None, prm, raw=True)
     assert rc == B.ICP_ERR_INVALID_ARG
     prm = B.icp_params_default(B.ICP_P2PL_WELSCH, nu_min=1e-3)
