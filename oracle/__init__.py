@@ -82,6 +82,8 @@ def lib():
         L.orc_nu_min_auto.argtypes = [f32p, C.c_void_p, C.c_int64, C.c_int, C.POINTER(C.c_double),
                                       C.c_void_p]
         L.orc_nu_min_auto.restype = C.c_int
+        L.orc_estimate_normals.argtypes = [f32p, C.c_int64, f32p]
+        L.orc_estimate_normals.restype = C.c_int
         _lib = L
     return _lib
 
@@ -188,6 +190,15 @@ def nu_min_auto(Q, Qn, mode, per_point=False):
     if rc != 0:
         raise ValueError("orc_nu_min_auto: invalid arguments")
     return (out.value, pp) if per_point else out.value
+
+
+def estimate_normals(Q):
+    """Normals from the 30 nearest points (the point included) by FP64 PCA."""
+    Q = _f32(Q).reshape(-1, 3)
+    out = np.zeros_like(Q)
+    if lib().orc_estimate_normals(Q, Q.shape[0], out) != 0:
+        raise ValueError("orc_estimate_normals: needs at least 30 points")
+    return out
 
 
 def eval_map(P, Q, Qn, mode, T, nu=0.0):

@@ -628,6 +628,60 @@ int orc_nu_min_auto(const float *Q, const float *Qn, int64_t N, int mode, double
 }
 
 /* ------------------------------------------------------------------------ */
+/* Normal estimation from 30 nearest neighbours                               */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_NORMAL_K 30
+
+int orc_estimate_normals(const float *Q, int64_t N, float *normals) {
+  if (N < ORC_NORMAL_K || !normals) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i) {
+    const float qx = Q[3 * i], qy = Q[3 * i + 1], qz = Q[3 * i + 2];
+    float bd[ORC_NORMAL_K];
+    int64_t nb[ORC_NORMAL_K];
+    int cnt = 0;
+    for (int64_t j = 0; j < N; ++j) {
+      const float dx = qx - Q[3 * j], dy = qy - Q[3 * j + 1], dz = qz - Q[3 * j + 2];
+      const float d = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      int pos = cnt;
+      while (pos > 0 && d < bd[pos - 1]) --pos;  /* later equal distances stay behind */
+      if (pos >= ORC_NORMAL_K) continue;
+      const int last = cnt < ORC_NORMAL_K ? cnt : ORC_NORMAL_K - 1;
+      for (int k = last; k > pos; --k) {
+        bd[k] = bd[k - 1];
+        nb[k] = nb[k - 1];
+      }
+      bd[pos] = d;
+      nb[pos] = j;
+      if (cnt < ORC_NORMAL_K) ++cnt;
+    }
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < ORC_NORMAL_K; ++k)
+      for (int a = 0; a < 3; ++a) m[a] += (double)Q[3 * nb[k] + a];
+    for (int a = 0; a < 3; ++a) m[a] /= ORC_NORMAL_K;
+    double C[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < ORC_NORMAL_K; ++k) {
+      double e[3];
+      for (int a = 0; a < 3; ++a) e[a] = (double)Q[3 * nb[k] + a] - m[a];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) C[3 * a + b] += e[a] * e[b];
+    }
+    for (int a = 0; a < 9; ++a) C[a] /= ORC_NORMAL_K;
+    /* symmetric PSD: the SVD is the eigen-decomposition, singular values descending */
+    double U[9], S[3], V[9];
+    orc_svd3(C, U, S, V);
+    double n[3] = {V[2], V[5], V[8]};
+    const double l = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int a = 0; a < 3; ++a) n[a] /= l;
+    if (n[0] * qx + n[1] * qy + n[2] * qz > 0.0)
+      for (int a = 0; a < 3; ++a) n[a] = -n[a];
+    for (int a = 0; a < 3; ++a) normals[3 * i + a] = (float)n[a];
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Registration (Algorithm 1 with L2 or Welsch metric; Algorithm 2)           */
 /* ------------------------------------------------------------------------ */
 

@@ -101,6 +101,15 @@ double orc_median(const double *v, int64_t n);
 int orc_nu_min_auto(const float *Q, const float *Qn, int64_t N, int mode, double *nu_min,
                     double *per_point);
 
+/* Normals of a point set for point-to-plane registration without given
+ * normals (the paper estimates them from 30 nearest neighbours): for every
+ * point q_i its k = 30 nearest points of the set, q_i itself included (exact
+ * FP32 squared distances of q_i - q_j, ties to the lower index); their mean
+ * and covariance in FP64 (sums in that order); the unit eigenvector of the
+ * smallest eigenvalue, oriented so that n . q_i <= 0 (towards a viewpoint at
+ * the origin). Needs N >= 30; returns -1 otherwise. */
+int orc_estimate_normals(const float *Q, int64_t N, float *normals);
+
 /* Full registration: Fast ICP (L2 + AA), Algorithm 1, Algorithm 2.
  * Qn may be NULL except for ORC_P2PL_WELSCH. trace (optional) receives one
  * row of 20 doubles per evaluation [E, nu, -1, reused, T(16)], up to

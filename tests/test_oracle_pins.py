@@ -509,3 +509,52 @@ def test_nu_min_auto_rejects_tiny_sets_and_missing_normals():
         oracle.nu_min_auto(Q, None, oracle.P2P_WELSCH)
     with pytest.raises(ValueError):
         oracle.nu_min_auto(np.zeros((10, 3), np.float32), None, oracle.P2PL_WELSCH)
+
+
+# ------------------------------------------------------------------ normal estimation
+# 30 nearest points (the point included), FP64 PCA, smallest eigenvector,
+# oriented towards a viewpoint at the origin.
+
+def test_normals_of_a_tilted_plane_are_exact():
+    g = np.stack(np.meshgrid(np.arange(20), np.arange(20), indexing="ij"), -1).reshape(-1, 2) * 0.05
+    n0 = np.array([0.3, -0.2, 1.0])
+    n0 /= np.linalg.norm(n0)
+    a = np.cross(n0, [1.0, 0, 0]); a /= np.linalg.norm(a)
+    b = np.cross(n0, a)
+    Q = (np.array([0.2, -0.1, 2.0]) + g[:, :1] * a + g[:, 1:] * b).astype(np.float32)
+    n = oracle.estimate_normals(Q).astype(np.float64)
+    # the plane lies on the far side of the origin along n0: normals face the origin
+    assert np.abs(n + n0).max() < 1e-5
+
+
+def test_normals_of_a_sphere_point_to_the_centre():
+    k = np.arange(4000) + 0.5
+    phi = np.arccos(1 - 2 * k / 4000)
+    th = np.pi * (1 + 5 ** 0.5) * k
+    u = np.c_[np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)]
+    n = oracle.estimate_normals((2.0 * u).astype(np.float32)).astype(np.float64)
+    ang = np.arccos(np.clip((n * -u).sum(1), -1, 1))
+    # a PCA normal is the normal near the neighbourhood's centroid, which sits
+    # a fraction of the spacing (~0.11 here) off the point: a few 1e-3 rad on
+    # radius 2; a tangent eigenvector or a wrong orientation would be ~pi/2 or pi
+    assert np.median(ang) < 1e-2 and ang.max() < 3e-2
+
+
+def test_normals_match_numpy_pca_small_random():
+    rng = np.random.default_rng(11)
+    xy = rng.uniform(-1, 1, (200, 2))
+    Q = np.c_[xy, 0.3 * xy[:, 0] ** 2 - 0.2 * xy[:, 1] + 3.0].astype(np.float32)
+    n = oracle.estimate_normals(Q).astype(np.float64)
+    Qd = Q.astype(np.float64)
+    d2 = ((Qd[:, None, :] - Qd[None, :, :]) ** 2).sum(-1)
+    nb = np.argsort(d2, axis=1, kind="stable")[:, :30]
+    for i in range(len(Q)):
+        X = Qd[nb[i]]
+        w, V = np.linalg.eigh(np.cov(X.T, bias=True))
+        e = V[:, 0] * (-1.0 if V[:, 0] @ Qd[i] > 0 else 1.0)
+        assert np.abs(n[i] - e).max() < 1e-6
+
+
+def test_normals_reject_fewer_than_thirty_points():
+    with pytest.raises(ValueError):
+        oracle.estimate_normals(np.zeros((29, 3), np.float32))
