@@ -202,6 +202,16 @@ icp_status icp_nn_query_dev(icp_ctx *ctx, const float *P_dev, int64_t M, const f
 icp_status icp_nu_min_auto(icp_ctx *ctx, const float *Q, const float *Qn, int64_t N,
                            icp_mode mode, double *nu_min_out);
 
+/* Normals of a point set for point-to-plane registration of targets given
+ * without normals (the paper estimates them from 30 nearest neighbours): for
+ * every point its 30 nearest points of the set, the point itself included
+ * (exact FP32 squared distances, ties to the lower index); the FP64 mean and
+ * covariance of the 30 (summed in that order); the unit eigenvector of the
+ * smallest eigenvalue, oriented so that n . q <= 0 (towards a viewpoint at
+ * the origin; the registration does not depend on the orientation).
+ * Q: host AoS N x 3 FP32, N >= 30; normals_out: host N x 3 FP32. Synchronous. */
+icp_status icp_estimate_normals(icp_ctx *ctx, const float *Q, int64_t N, float *normals_out);
+
 /* Batched / served registration. Each request is validated and its arrays are
  * copied to pinned staging before the call returns (the caller may free them
  * at once); tickets_out[i] receives a unique ticket. A background scheduler

@@ -24,7 +24,7 @@ ICP_FLAG_DEGENERATE, ICP_FLAG_AA_SINGULAR = 8, 16
 EXPORTED = ["icp_create", "icp_destroy", "icp_params_default", "icp_register", "icp_register_trace",
             "icp_eval", "icp_trace_items",
             "icp_register_dev",
-            "icp_nn_query", "icp_nn_query_dev", "icp_nu_min_auto", "icp_batch_submit", "icp_poll",
+            "icp_nn_query", "icp_nn_query_dev", "icp_nu_min_auto", "icp_estimate_normals", "icp_batch_submit", "icp_poll",
             "icp_batch_wait_all", "icp_batch_config", "icp_profile", "icp_profile_read",
             "icp_status_str"]
 
@@ -90,6 +90,7 @@ def lib():
         L.icp_batch_submit.argtypes = [vp, C.POINTER(icp_request), i32, C.POINTER(C.c_uint64)]
         L.icp_poll.argtypes = [vp, C.c_uint64, C.POINTER(icp_result)]
         L.icp_nu_min_auto.argtypes = [vp, vp, vp, C.c_int64, i32, C.POINTER(C.c_double)]
+        L.icp_estimate_normals.argtypes = [vp, vp, C.c_int64, vp]
         L.icp_batch_wait_all.argtypes = [vp]
         L.icp_batch_config.argtypes = [vp, i32, i32]
         L.icp_profile.argtypes = [vp, i32]
@@ -212,6 +213,17 @@ def icp_register_dev(ctx, P_t, Q_t, Qn_t=None, params: icp_params | None = None,
                                 C.byref(params), C.byref(r), st)
     _check(rc, "icp_register_dev")
     return result_dict(r)
+
+
+def icp_estimate_normals(ctx, Q, raw=False):
+    """Normals from the 30 nearest points (the point included), FP64 PCA."""
+    Q = _f32(Q)
+    out = np.zeros_like(Q)
+    rc = lib().icp_estimate_normals(ctx, _ptr(Q), Q.shape[0], _ptr(out))
+    if raw:
+        return rc, out
+    _check(rc, "icp_estimate_normals")
+    return out
 
 
 def icp_nu_min_auto(ctx, Q, Qn=None, mode: int = ICP_P2P_WELSCH, raw=False):

@@ -30,6 +30,8 @@ void launch_epi(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
 void launch_solver(const SlotDesc*, SlotState*, int, int*, WorkList*, bool, hipStream_t);
 void launch_boot(const SlotDesc*, SlotState*, int, WorkList*, bool, hipStream_t);
 void launch_median(const SlotDesc*, SlotState*, int, hipStream_t);
+void launch_estimate_normals(const float4*, const float4*, const float4*, const float4*, const float4*,
+                             int, int, const float*, const float*, const float*, float*, hipStream_t);
 void launch_nu_min_auto(const float4*, const float4*, const float4*, const float4*, const float4*, int,
                         int, const float*, const float*, const float*, const float*, const float*,
                         const float*, int, bool, double*, double*, hipStream_t);
@@ -1076,6 +1078,36 @@ icp_status icp_nu_min_auto(icp_ctx* ctx, const float* Q, const float* Qn, int64_
   if (!ok) return ICP_ERR_DEVICE;
   *nu_min_out = S.nu_min;
   return ICP_OK;
+}
+
+icp_status icp_estimate_normals(icp_ctx* ctx, const float* Q, int64_t N, float* normals_out) {
+  if (!ctx || !Q || !normals_out) return ICP_ERR_INVALID_ARG;
+  if (N < 30 || N > (1 << 28)) return ICP_ERR_INVALID_ARG;
+  if (!finite_coords(Q, N)) return ICP_ERR_NONFINITE;
+  OwnedRequest r;
+  // the points stand in for both sets: the setup builds the cluster index
+  r.P.assign(Q, Q + 3 * N);
+  r.Q.assign(Q, Q + 3 * N);
+  r.M = N; r.N = N;
+  icp_params_default(ICP_P2P_L2, &r.prm);
+  std::lock_guard<std::mutex> g(ctx->sync_mu);
+  Engine& E = ctx->sync_eng;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ICP_ERR_DEVICE;
+  bool oom = false;
+  if (!E.admit(0, r, &oom)) { E.release(0); return ICP_ERR_DEVICE; }
+  if (oom) return ICP_ERR_OOM;
+  const Layout& L = E.hs[0].L;
+  char* b = E.hs[0].mem;
+  auto F4 = [&](size_t o) { return reinterpret_cast<const float4*>(b + o); };
+  auto F = [&](size_t o) { return reinterpret_cast<float*>(b + o); };
+  float* out = F(L.o_scratch);  // 12 N bytes, free once the setup is done
+  launch_estimate_normals(F4(L.o_qorg), F4(L.o_clo), F4(L.o_chi), F4(L.o_slo), F4(L.o_shi), L.ncl,
+                          L.nsup, F(L.o_qx), F(L.o_qy), F(L.o_qz), out, E.side);
+  const bool ok = hipGetLastError() == hipSuccess &&
+                  hipMemcpyAsync(normals_out, out, 12ull * N, hipMemcpyDeviceToHost, E.side) == hipSuccess &&
+                  hipStreamSynchronize(E.side) == hipSuccess;
+  E.release(0);
+  return ok ? ICP_OK : ICP_ERR_DEVICE;
 }
 
 icp_status icp_nn_query_dev(icp_ctx* ctx, const float* P_dev, int64_t M, const float* Q_dev,
