@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
-P2P_L2, P2P_WELSCH, P2PL_WELSCH = 0, 1, 2
+P2P_L2, P2P_WELSCH, P2PL_WELSCH, P2PL_L2 = 0, 1, 2, 3
 FLAG_CONVERGED, FLAG_MAX_ITER, FLAG_ZERO_WEIGHT, FLAG_DEGENERATE, FLAG_AA_SINGULAR = 1, 2, 4, 8, 16
 
 
@@ -76,6 +76,8 @@ def lib():
                                    C.POINTER(C.c_int)]
         L.orc_register.restype = C.c_int
         L.orc_params_default.argtypes = [C.c_int, C.POINTER(Params)]
+        L.orc_params_classical.argtypes = [C.c_int, C.POINTER(Params)]
+        L.orc_params_classical.restype = C.c_int
         L.orc_eval.argtypes = [f32p, C.c_int64, f32p, C.c_void_p, C.c_int64, C.c_int, f64p,
                                C.c_double, C.POINTER(C.c_double), f64p, C.POINTER(C.c_uint)]
         L.orc_eval.restype = C.c_int
@@ -222,6 +224,15 @@ def eval_map(P, Q, Qn, mode, T, nu=0.0):
 def default_params(mode):
     p = Params()
     lib().orc_params_default(mode, C.byref(p))
+    return p
+
+
+def classical_params(mode):
+    """ICP (P2P_L2) or ICP-l (P2PL_L2) with the comparison methods' settings:
+    no mixing, no line search, 1000 iterations, ||dT||_F^2 < 1e-5."""
+    p = Params()
+    if lib().orc_params_classical(mode, C.byref(p)) != 0:
+        raise ValueError("oracle: classical settings exist for P2P_L2 and P2PL_L2 only")
     return p
 
 

@@ -597,7 +597,8 @@ static void six_nearest(const float *Q, int64_t N, int64_t i, int64_t nb[6]) {
 
 int orc_nu_min_auto(const float *Q, const float *Qn, int64_t N, int mode, double *nu_min,
                     double *per_point) {
-  if (N < 7 || !nu_min || (mode == ORC_P2PL_WELSCH && !Qn)) return -1;
+  if (N < 7 || !nu_min || (mode != ORC_P2P_WELSCH && mode != ORC_P2PL_WELSCH)) return -1;
+  if (mode == ORC_P2PL_WELSCH && !Qn) return -1;
   double *v = (double *)malloc(sizeof(double) * (size_t)N);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) {
@@ -750,13 +751,16 @@ static int ctx_corr(orc_ctx *c, const double T[16], const double *key, int keyle
   return 0;
 }
 
+static int mode_plane(int mode) { return mode == ORC_P2PL_WELSCH || mode == ORC_P2PL_L2; }
+static int mode_l2(int mode) { return mode == ORC_P2P_L2 || mode == ORC_P2PL_L2; }
+
 static void ctx_residuals(orc_ctx *c, const double T[16]) {
   for (int64_t i = 0; i < c->M; ++i) {
     double x[3];
     xform_f64(T, c->P + 3 * i, x);
     const double dx = x[0] - (double)c->Qh[3 * i], dy = x[1] - (double)c->Qh[3 * i + 1],
                  dz = x[2] - (double)c->Qh[3 * i + 2];
-    if (c->mode == ORC_P2PL_WELSCH) {
+    if (mode_plane(c->mode)) {
       const float *n = c->Qn + 3 * (int64_t)c->idx[i];
       c->res[i] = fma(dz, (double)n[2], fma(dy, (double)n[1], dx * (double)n[0]));
     } else {
@@ -818,7 +822,9 @@ static int chol6_solve(const double A[36], const double b[6], double x[6]) {
 }
 
 /* Point-to-plane evaluation at xi: E~_nu(xi) and xi* = G_ppl(xi) (eq. GNMapping):
- * A = sum g J J^T, c = sum g B J, xi* = xi - A^{-1} c (reading R6). */
+ * A = sum g J J^T, c = sum g B J, xi* = xi - A^{-1} c (reading R6). Classical
+ * point-to-plane ICP takes g = 1 and the energy sum B^2 (the limit of the
+ * Welsch weights as nu grows). */
 static orc_evalres eval_p2pl(orc_ctx *c, const double xi[6], double nu) {
   orc_evalres ev;
   memset(&ev, 0, sizeof ev);
@@ -830,10 +836,11 @@ static orc_evalres eval_p2pl(orc_ctx *c, const double xi[6], double nu) {
   se3_derivs(xi, dR, Dt, Du);
   const double s = 1.0 / (2.0 * nu * nu);
   double A[36] = {0}, cv[6] = {0}, E = 0, W = 0;
+  const int L2 = mode_l2(c->mode);
   for (int64_t i = 0; i < c->M; ++i) {
     const double B = c->res[i];
-    E += -expm1(-B * B * s);
-    const double g = exp(-B * B * s);
+    E += L2 ? B * B : -expm1(-B * B * s);
+    const double g = L2 ? 1.0 : exp(-B * B * s);
     W += g;
     double J[6];
     plane_gradient_from(dR, Dt, Du, c->P + 3 * i, c->Qn + 3 * (int64_t)c->idx[i], J);
@@ -843,7 +850,7 @@ static orc_evalres eval_p2pl(orc_ctx *c, const double xi[6], double nu) {
     }
   }
   ev.E = E;
-  ctx_record(c, E, nu, reused, T);
+  ctx_record(c, E, L2 ? 0.0 : nu, reused, T);
   for (int a = 0; a < 6; ++a) ev.prop[a] = xi[a];
   if (!(W > 1e-300)) {
     ev.flags = ORC_FLAG_ZERO_WEIGHT;
@@ -878,6 +885,26 @@ void orc_params_default(int mode, orc_params *out) {
     out->iter_cap = 1000;
   }
   for (int i = 0; i < 16; ++i) out->T0[i] = (i % 5 == 0) ? 1.0 : 0.0;
+  if (mode == ORC_P2PL_L2) orc_params_classical(mode, out);
+}
+
+/* App. E: the comparison methods stop after 1000 iterations or when the
+ * squared Frobenius norm of the change of transform falls below 1e-5. */
+int orc_params_classical(int mode, orc_params *out) {
+  if (mode != ORC_P2P_L2 && mode != ORC_P2PL_L2) return -1;
+  memset(out, 0, sizeof *out);
+  out->mode = mode;
+  out->anderson_m = 0;
+  out->nu_max = -1.0;
+  out->nu_min = -1.0;
+  out->eps = sqrt(1e-5);
+  out->iter_first = 1000;
+  out->iter_inc = 0;
+  out->iter_cap = 1000;
+  out->max_total_iter = 0;
+  out->max_line_search = 0;
+  for (int i = 0; i < 16; ++i) out->T0[i] = (i % 5 == 0) ? 1.0 : 0.0;
+  return 0;
 }
 
 #define HIST 8 /* ring capacity (m <= 6, needs m + 1 entries) */
@@ -1015,9 +1042,12 @@ static void register_p2p(orc_ctx *c, const orc_params *prm, double nu0, orc_resu
   res->nu_final = L2 ? 0.0 : nu;
 }
 
-/* Algorithm 2: robust point-to-plane with line search and Anderson mixing. */
+/* Algorithm 2: robust point-to-plane with line search and Anderson mixing.
+ * Classical point-to-plane ICP runs the same loop with unit weights, a single
+ * stage, and the convergence test on the change of transform (App. E). */
 static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_result *res) {
   const int m = prm->anderson_m;
+  const int L2 = mode_l2(c->mode);
   double nu = nu0;
   double xkm1[6], xk[6], xstar[6];
   orc_se3_log(prm->T0, xkm1);
@@ -1081,8 +1111,16 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
       double xs_next[6];
       memcpy(xs_next, best.prop, sizeof xs_next);
       double dn = 0;
-      for (int a = 0; a < 6; ++a) dn += (xs_next[a] - xk[a]) * (xs_next[a] - xk[a]);
-      if (sqrt(dn) < prm->eps) { converged = 1; break; }
+      if (L2) {
+        double Tn[16], Tc[16];
+        orc_se3_exp(xs_next, Tn);
+        orc_se3_exp(xk, Tc);
+        dn = frob_diff(Tn, Tc);
+      } else {
+        for (int a = 0; a < 6; ++a) dn += (xs_next[a] - xk[a]) * (xs_next[a] - xk[a]);
+        dn = sqrt(dn);
+      }
+      if (dn < prm->eps) { converged = 1; break; }
       double xn[6];
       for (int a = 0; a < 6; ++a) {
         G[k % HIST][a] = xs_next[a];
@@ -1109,7 +1147,7 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
     }
     if (converged) res->flags = (res->flags & ~(unsigned)ORC_FLAG_MAX_ITER) | ORC_FLAG_CONVERGED;
     else res->flags = (res->flags & ~(unsigned)ORC_FLAG_CONVERGED) | ORC_FLAG_MAX_ITER;
-    if (nu == prm->nu_min) break;
+    if (L2 || nu == prm->nu_min) break;
     nu = fmax(nu / 2.0, prm->nu_min);
     k++;
     stage++;
@@ -1117,15 +1155,15 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
   }
   orc_se3_exp(xk, res->T);
   res->energy = Ecur;
-  res->nu_final = nu;
+  res->nu_final = L2 ? 0.0 : nu;
 }
 
 /* One un-accelerated map application at T (see the header). */
 int orc_eval(const float *P, int64_t M, const float *Q, const float *Qn, int64_t N, int mode,
              const double T[16], double nu, double *E, double Tout[16], unsigned *flags) {
-  if (!P || !Q || M <= 0 || N <= 0 || mode < 0 || mode > 2) return -1;
-  if (mode == ORC_P2PL_WELSCH && !Qn) return -1;
-  if (mode != ORC_P2P_L2 && !(nu > 0)) return -1;
+  if (!P || !Q || M <= 0 || N <= 0 || mode < 0 || mode > 3) return -1;
+  if (mode_plane(mode) && !Qn) return -1;
+  if (!mode_l2(mode) && !(nu > 0)) return -1;
   orc_ctx c;
   memset(&c, 0, sizeof c);
   c.P = P; c.Q = Q; c.Qn = Qn; c.M = M; c.N = N; c.mode = mode;
@@ -1136,7 +1174,7 @@ int orc_eval(const float *P, int64_t M, const float *Q, const float *Qn, int64_t
   c.res = (double *)malloc(sizeof(double) * (size_t)M);
   c.w = (double *)malloc(sizeof(double) * (size_t)M);
   orc_evalres ev;
-  if (mode == ORC_P2PL_WELSCH) {
+  if (mode_plane(mode)) {
     double xi[6];
     orc_se3_log(T, xi);
     ev = eval_p2pl(&c, xi, nu);
@@ -1156,10 +1194,10 @@ int orc_register(const float *P, int64_t M, const float *Q, const float *Qn, int
                  const orc_params *prm, orc_result *res, double *trace, int trace_cap,
                  int *trace_len, double *etrace, int etrace_cap, int *etrace_len) {
   if (!P || !Q || !prm || !res || M <= 0 || N <= 0) return -1;
-  if (prm->mode < 0 || prm->mode > 2) return -1;
-  if (prm->mode == ORC_P2PL_WELSCH && !Qn) return -1;
+  if (prm->mode < 0 || prm->mode > 3) return -1;
+  if (mode_plane(prm->mode) && !Qn) return -1;
   if (prm->anderson_m < 0 || prm->anderson_m > 6) return -1;
-  if (prm->mode != ORC_P2P_L2 && !(prm->nu_min > 0)) return -1;
+  if (!mode_l2(prm->mode) && !(prm->nu_min > 0)) return -1;
   if (!(prm->eps > 0) || prm->iter_first <= 0) return -1;
   if (!valid_rigid(prm->T0)) return -1;
   memset(res, 0, sizeof *res);
@@ -1177,7 +1215,7 @@ int orc_register(const float *P, int64_t M, const float *Q, const float *Qn, int
 
   /* nu_max = 3 x median of the initial residuals (Sec. 4.3; Sec. 5). */
   double nu0 = prm->nu_max;
-  if (prm->mode != ORC_P2P_L2 && !(nu0 > 0)) {
+  if (!mode_l2(prm->mode) && !(nu0 > 0)) {
     if (prm->mode == ORC_P2PL_WELSCH) {
       double x0[6];
       orc_se3_log(prm->T0, x0);
@@ -1193,7 +1231,7 @@ int orc_register(const float *P, int64_t M, const float *Q, const float *Qn, int
       nu0 = 3.0 * sqrt(orc_median(c.res, M));
     }
   }
-  if (prm->mode == ORC_P2PL_WELSCH) register_p2pl(&c, prm, nu0, res);
+  if (mode_plane(prm->mode)) register_p2pl(&c, prm, nu0, res);
   else register_p2p(&c, prm, nu0, res);
   res->nn_passes = c.nn_passes;
   res->evaluations = c.evaluations;

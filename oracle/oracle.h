@@ -20,7 +20,10 @@
 extern "C" {
 #endif
 
-enum { ORC_P2P_L2 = 0, ORC_P2P_WELSCH = 1, ORC_P2PL_WELSCH = 2 };
+/* ORC_P2PL_L2 is classical point-to-plane ICP (Chen and Medioni), the
+ * "ICP-l" comparison of Sec. 6: energy sum B_i^2, Gauss-Newton map of
+ * eq. GNMapping with unit weights, one stage. */
+enum { ORC_P2P_L2 = 0, ORC_P2P_WELSCH = 1, ORC_P2PL_WELSCH = 2, ORC_P2PL_L2 = 3 };
 
 enum {
   ORC_FLAG_CONVERGED = 1u,
@@ -31,7 +34,7 @@ enum {
 };
 
 typedef struct {
-  int mode;              /* ORC_P2P_L2 / ORC_P2P_WELSCH / ORC_P2PL_WELSCH */
+  int mode;              /* ORC_P2P_L2 / ORC_P2P_WELSCH / ORC_P2PL_WELSCH / ORC_P2PL_L2 */
   int anderson_m;        /* Anderson depth m; 0 = plain MM iteration */
   double nu_max;         /* <= 0: 3 x median rule at T0 */
   double nu_min;         /* must be > 0 for the Welsch modes */
@@ -110,8 +113,9 @@ int orc_nu_min_auto(const float *Q, const float *Qn, int64_t N, int mode, double
  * the origin). Needs N >= 30; returns -1 otherwise. */
 int orc_estimate_normals(const float *Q, int64_t N, float *normals);
 
-/* Full registration: Fast ICP (L2 + AA), Algorithm 1, Algorithm 2.
- * Qn may be NULL except for ORC_P2PL_WELSCH. trace (optional) receives one
+/* Full registration: Fast ICP (L2 + AA), Algorithm 1, Algorithm 2, and
+ * classical point-to-plane ICP. Qn may be NULL except for the point-to-plane
+ * modes. trace (optional) receives one
  * row of 20 doubles per evaluation [E, nu, -1, reused, T(16)], up to
  * trace_cap rows (the setup pass that only feeds the median is not a row);
  * etrace (optional) receives (stage, accepted energy)
@@ -129,6 +133,13 @@ int orc_eval(const float *P, int64_t M, const float *Q, const float *Qn, int64_t
              const double T[16], double nu, double *E, double Tout[16], unsigned *flags);
 
 void orc_params_default(int mode, orc_params *out);
+
+/* The comparison methods of Sec. 6 with the termination the paper gives them
+ * (App. on the experiment settings): ICP (mode ORC_P2P_L2) and ICP-l (mode
+ * ORC_P2PL_L2), no Anderson mixing, no line search, one stage of at most
+ * 1000 iterations, stop when ||T_{k+1} - T_k||_F^2 < 1e-5 (eps = sqrt(1e-5)
+ * on the Frobenius norm). Returns -1 for the other modes. */
+int orc_params_classical(int mode, orc_params *out);
 
 #ifdef __cplusplus
 }

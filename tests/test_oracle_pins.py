@@ -558,3 +558,133 @@ def test_normals_match_numpy_pca_small_random():
 def test_normals_reject_fewer_than_thirty_points():
     with pytest.raises(ValueError):
         oracle.estimate_normals(np.zeros((29, 3), np.float32))
+
+
+# ------------------------------------------------------------------ classical baselines
+# ICP and ICP-l as the comparison methods of Sec. 6 run (App. E): no mixing,
+# no line search, 1000 iterations or ||T_{k+1} - T_k||_F^2 < 1e-5.
+
+def _expm_twist(xi):
+    return scipy.linalg.expm(_twist_matrix(np.asarray(xi, np.float64)))
+
+
+def test_classical_settings_follow_appendix_e():
+    for mode in (oracle.P2P_L2, oracle.P2PL_L2):
+        p = oracle.classical_params(mode)
+        assert p.anderson_m == 0 and p.max_line_search == 0
+        assert (p.iter_first, p.iter_inc, p.iter_cap) == (1000, 0, 1000)
+        assert abs(p.eps ** 2 - 1e-5) <= 1e-20
+    with pytest.raises(ValueError):
+        oracle.classical_params(oracle.P2P_WELSCH)
+
+
+@pytest.mark.parametrize("seed", [31, 32])
+def test_icp_l_step_is_linear_least_squares(seed):
+    """One ICP-l update at T is the Gauss-Newton step of sum_i B_i(xi)^2,
+    B_i = n_j . (exp(xi^) p_i - q_j), on the correspondences at T (eq. GNSystem
+    with unit weights). Computed here another way: numpy closest points, scipy
+    expm, a central-difference Jacobian and numpy lstsq on J instead of
+    Cholesky on the normal equations."""
+    rng = np.random.default_rng(seed)
+    Q = rng.normal(size=(400, 3)).astype(np.float32)
+    Qn = rng.normal(size=(400, 3))
+    Qn = (Qn / np.linalg.norm(Qn, axis=1, keepdims=True)).astype(np.float32)
+    P = (rng.normal(size=(150, 3)) * 0.9).astype(np.float32)
+    xi = rng.normal(scale=0.05, size=6)
+    T = _expm_twist(xi)
+    E, Tn, fl = oracle.eval_map(P, Q, Qn, oracle.P2PL_L2, T)
+    assert fl == 0
+    Pt = (P.astype(np.float64) @ T[:3, :3].T + T[:3, 3]).astype(np.float32).astype(np.float64)
+    d2 = ((Pt[:, None, :] - Q[None, :, :].astype(np.float64)) ** 2).sum(-1)
+    j = d2.argmin(1)
+    srt = np.sort(d2, 1)
+    assert (srt[:, 1] - srt[:, 0] > 1e-6 * srt[:, 1]).all()  # no near-ties
+    q, n, p = Q[j].astype(np.float64), Qn[j].astype(np.float64), P.astype(np.float64)
+
+    def B(x):
+        Tx = _expm_twist(x)
+        return ((p @ Tx[:3, :3].T + Tx[:3, 3] - q) * n).sum(1)
+
+    b0 = B(xi)
+    assert abs(E - (b0 ** 2).sum()) <= 1e-12 * (b0 ** 2).sum()
+    h = 1e-6
+    J = np.stack([(B(xi + h * e) - B(xi - h * e)) / (2 * h) for e in np.eye(6)], 1)
+    step = np.linalg.lstsq(J, b0, rcond=None)[0]
+    Tref = _expm_twist(xi - step)
+    assert np.abs(Tn - Tref).max() < 1e-8
+
+
+def test_icp_l_exact_recovery_noise_free():
+    """Noise-free point-to-plane data with exact correspondences at the ground
+    truth: ICP-l run to a tight threshold lands on it."""
+    d = synth.height_field_pair(synth.rng_for(3, 97), m=3000, n=3000, outliers=0.0, noise=0.0,
+                                max_angle=3.0, trans_frac=0.01)
+    Q, Qn = d["Q"], d["Qn"]
+    R, t = synth.random_motion(synth.rng_for(3, 96), 3.0, 0.02)
+    P = (Q.astype(np.float64) @ R.T + t).astype(np.float32)
+    Tgt = np.eye(4)
+    Tgt[:3, :3] = R.T
+    Tgt[:3, 3] = -R.T @ t
+    r = oracle.register(P, Q, Qn, params=oracle.classical_params(oracle.P2PL_L2), eps=1e-10)
+    assert r["flags"] & oracle.FLAG_CONVERGED
+    assert metrics.rotation_error_rad(r["T"], Tgt) < 1e-6
+    assert metrics.translation_error(r["T"], Tgt) < 1e-6
+
+
+@pytest.mark.parametrize("mode", [oracle.P2P_L2, oracle.P2PL_L2])
+def test_classical_stop_rule_on_consecutive_transforms(mode):
+    """Every step before the last changes T by ||dT||_F^2 >= 1e-5; the map
+    applied at the returned T moves it by less."""
+    d = synth.height_field_pair(synth.rng_for(3, 61), m=1500, n=3000)
+    Qn = d["Qn"] if mode == oracle.P2PL_L2 else None
+    r = oracle.register(d["P"], d["Q"], Qn, params=oracle.classical_params(mode), trace_cap=2000)
+    Ts = r["trace"][:, 4:].reshape(-1, 4, 4)
+    assert r["flags"] & oracle.FLAG_CONVERGED
+    assert np.array_equal(Ts[-1], r["T"]) and r["iterations"] == len(Ts) - 1 >= 2
+    assert r["stages"] == 1 and r["nu_final"] == 0.0 and r["aa_accepted"] == 0
+    for i in range(1, len(Ts) - 1):
+        assert np.sum((Ts[i + 1] - Ts[i]) ** 2) >= 1e-5, i
+    _, Tn, _ = oracle.eval_map(d["P"], d["Q"], Qn, mode, r["T"])
+    assert np.sum((Tn - r["T"]) ** 2) < 1e-5
+
+
+def test_classical_iteration_cap_counts_map_applications():
+    """The cap counts inner iterations: the stage opens with one map
+    application at T0 (Algorithm 1 before its loop), then each of the cap
+    iterations applies the map once more, so a run stopped by the cap
+    evaluated cap + 2 distinct transforms."""
+    d = synth.partial_sphere_pair(synth.rng_for(2, 62), m=300, n=300)
+    for mode, Qn in ((oracle.P2P_L2, None), (oracle.P2PL_L2, d["Qn"])):
+        r = oracle.register(d["P"], d["Q"], Qn, params=oracle.classical_params(mode), eps=1e-300,
+                            iter_first=8, iter_cap=8)
+        assert r["iterations"] == 8 and r["flags"] & oracle.FLAG_MAX_ITER
+        assert r["nn_passes"] == 10 == r["evaluations"]
+
+
+def test_icp_l_is_welsch_point_to_plane_in_the_large_nu_limit():
+    """nu -> infinity makes every Welsch weight 1: Algorithm 2 without line
+    search and mixing then takes exactly the ICP-l steps."""
+    d = synth.height_field_pair(synth.rng_for(3, 63), m=1000, n=3000)
+    kw = dict(eps=1e-12, iter_first=5, iter_cap=5)
+    a = oracle.register(d["P"], d["Q"], d["Qn"], params=oracle.classical_params(oracle.P2PL_L2), **kw)
+    b = oracle.register(d["P"], d["Q"], d["Qn"], mode=oracle.P2PL_WELSCH, anderson_m=0, max_line_search=0,
+                        nu_max=1e8, nu_min=1e8, **kw)
+    assert a["iterations"] == b["iterations"] == 5
+    assert np.abs(a["T"] - b["T"]).max() < 1e-12
+
+
+def test_robust_point_to_plane_beats_icp_l_with_outliers():
+    """The qualitative claim of Tables 1-4 for the point-to-plane family: with
+    outliers and partial overlap the Welsch metric lands closer to the ground
+    truth than the L2 metric."""
+    worse = 0
+    for s in range(3):
+        d = synth.height_field_pair(synth.rng_for(3, 64 + s), m=2000, n=5000, outliers=0.2)
+        a = oracle.register(d["P"], d["Q"], d["Qn"], params=oracle.classical_params(oracle.P2PL_L2))
+        b = oracle.register(d["P"], d["Q"], d["Qn"], mode=oracle.P2PL_WELSCH, anderson_m=6,
+                            nu_min=d["nu_min"])
+        ea = metrics.rmse(d["T_gt"], a["T"], d["P"])
+        eb = metrics.rmse(d["T_gt"], b["T"], d["P"])
+        print(f"seed {s}: ICP-l {ea:.3e} robust {eb:.3e}")
+        worse += eb >= ea
+    assert worse == 0
