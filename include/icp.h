@@ -47,7 +47,9 @@ typedef enum {
 typedef enum {
   ICP_P2P_L2 = 0,        /* Fast ICP: L2 point-to-point + Anderson (Sec. 4.2) */
   ICP_P2P_WELSCH = 1,    /* Algorithm 1: Welsch point-to-point + Anderson (Sec. 4.3) */
-  ICP_P2PL_WELSCH = 2    /* Algorithm 2: Welsch point-to-plane + Anderson (Sec. 5) */
+  ICP_P2PL_WELSCH = 2,   /* Algorithm 2: Welsch point-to-plane + Anderson (Sec. 5) */
+  ICP_P2PL_L2 = 3        /* classical point-to-plane ICP ("ICP-l", Sec. 6): energy sum B_i^2,
+                            the Gauss-Newton map of Algorithm 2 with unit weights, one stage */
 } icp_mode;
 
 /* Closest-point search (eq. CorresponcePoint). All methods return the same
@@ -69,7 +71,8 @@ typedef struct {
   int anderson_m;        /* Anderson depth m in [0, 6]; 0 disables mixing (plain MM); paper: 5 (Sec. 4.2) */
   double nu_max;         /* <= 0: 3 x median of the initial residuals (Sec. 4.3, Sec. 5) */
   double nu_min;         /* > 0; <= 0: the paper's automatic rule (icp_nu_min_auto, N >= 7) */
-  double eps;            /* stage threshold on ||T - T'||_F (p2p) / ||xi* - xi|| (p2pl); paper 1e-5 */
+  double eps;            /* stage threshold on ||T - T'||_F (point-to-point and ICP_P2PL_L2) /
+                            ||xi* - xi|| (ICP_P2PL_WELSCH); paper 1e-5 */
   int iter_first;        /* I_nu of the first stage; paper: 1000 (p2p), 6 (p2pl) */
   int iter_inc;          /* I_nu increment per stage; paper: 0 (p2p), 1 (p2pl) */
   int iter_cap;          /* I_nu upper bound; paper: 1000 (p2p), 10 (p2pl); <= 0 none */
@@ -128,8 +131,16 @@ typedef struct {
 icp_status icp_create(int device, size_t hbm_budget_bytes, icp_ctx **out);
 icp_status icp_destroy(icp_ctx *ctx);
 
-/* The paper's defaults for a mode (Sec. 4.2, Sec. 4.3, Sec. 5). */
+/* The paper's defaults for a mode (Sec. 4.2, Sec. 4.3, Sec. 5); for
+ * ICP_P2PL_L2 the classical settings below. */
 icp_status icp_params_default(icp_mode mode, icp_params *out);
+
+/* Settings of the comparison methods ICP (mode ICP_P2P_L2) and ICP-l (mode
+ * ICP_P2PL_L2) as App. E runs them: no Anderson mixing (anderson_m = 0), no
+ * line search (max_line_search = 0), one stage of at most 1000 iterations,
+ * stop once ||T_{k+1} - T_k||_F^2 < 1e-5 (eps = sqrt(1e-5)). Other modes:
+ * ICP_ERR_INVALID_ARG. */
+icp_status icp_params_classical(icp_mode mode, icp_params *out);
 
 /* Synchronous registration (Algorithm 1 / Algorithm 2 / Fast ICP). Inputs are
  * copied before the call returns; `out` is written by the call. */

@@ -15,13 +15,13 @@ LIB_PATH = os.path.join(_PKG, "libicp.so")
 
 ICP_OK, ICP_ERR_INVALID_ARG, ICP_ERR_NONFINITE, ICP_ERR_NO_NORMALS, ICP_ERR_OOM = 0, 1, 2, 3, 4
 ICP_ERR_DEVICE, ICP_ERR_NOT_READY, ICP_ERR_UNKNOWN_TICKET, ICP_ERR_QUEUE_FULL = 5, 6, 7, 8
-ICP_P2P_L2, ICP_P2P_WELSCH, ICP_P2PL_WELSCH = 0, 1, 2
+ICP_P2P_L2, ICP_P2P_WELSCH, ICP_P2PL_WELSCH, ICP_P2PL_L2 = 0, 1, 2, 3
 ICP_NN_AUTO, ICP_NN_BRUTE, ICP_NN_CLUSTER = 0, 1, 2
 ICP_ENGINE_GRAPH, ICP_ENGINE_PLAIN = 0, 1
 ICP_FLAG_CONVERGED, ICP_FLAG_MAX_ITER, ICP_FLAG_ZERO_WEIGHT = 1, 2, 4
 ICP_FLAG_DEGENERATE, ICP_FLAG_AA_SINGULAR = 8, 16
 
-EXPORTED = ["icp_create", "icp_destroy", "icp_params_default", "icp_register", "icp_register_trace",
+EXPORTED = ["icp_create", "icp_destroy", "icp_params_default", "icp_params_classical", "icp_register", "icp_register_trace",
             "icp_eval", "icp_trace_items",
             "icp_register_dev",
             "icp_nn_query", "icp_nn_query_dev", "icp_nu_min_auto", "icp_estimate_normals", "icp_batch_submit", "icp_poll",
@@ -77,6 +77,7 @@ def lib():
         L.icp_create.argtypes = [i32, C.c_size_t, C.POINTER(vp)]
         L.icp_destroy.argtypes = [vp]
         L.icp_params_default.argtypes = [i32, C.POINTER(icp_params)]
+        L.icp_params_classical.argtypes = [i32, C.POINTER(icp_params)]
         L.icp_register.argtypes = [vp, vp, i64, vp, vp, i64, C.POINTER(icp_params), C.POINTER(icp_result)]
         L.icp_register_trace.argtypes = [vp, vp, i64, vp, vp, i64, C.POINTER(icp_params),
                                          C.POINTER(icp_result), vp, i32, C.POINTER(C.c_int)]
@@ -142,6 +143,19 @@ def icp_destroy(ctx):
 def icp_params_default(mode: int = ICP_P2P_WELSCH, **overrides) -> icp_params:
     p = icp_params()
     _check(lib().icp_params_default(mode, C.byref(p)), "icp_params_default")
+    for k, v in overrides.items():
+        if k == "T0":
+            p.T0[:] = list(np.asarray(v, dtype=np.float64).reshape(16))
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def icp_params_classical(mode: int = ICP_P2P_L2, **overrides) -> icp_params:
+    """ICP (ICP_P2P_L2) or ICP-l (ICP_P2PL_L2) with the comparison methods'
+    settings: no mixing, no line search, 1000 iterations, ||dT||_F^2 < 1e-5."""
+    p = icp_params()
+    _check(lib().icp_params_classical(mode, C.byref(p)), "icp_params_classical")
     for k, v in overrides.items():
         if k == "T0":
             p.T0[:] = list(np.asarray(v, dtype=np.float64).reshape(16))

@@ -203,7 +203,7 @@ struct OwnedRequest {
 };
 
 // nu_min <= 0 selects the automatic rule for the Welsch modes.
-static bool auto_nu_min(const icp_params* p) { return p->mode != ICP_P2P_L2 && !(p->nu_min > 0.0); }
+static bool auto_nu_min(const icp_params* p) { return !mode_l2(p->mode) && !(p->nu_min > 0.0); }
 
 static void fill_stats(const HostSlot& h, hipStream_t st, icp_result* r) {
   unsigned long long v[kQueues * kStatStride] = {};
@@ -381,7 +381,7 @@ struct Engine {
 
   static size_t footprint(const OwnedRequest& r) {
     Layout L;
-    L.plan(r.M, r.N, r.prm.mode == ICP_P2PL_WELSCH, r.query && !r.idx_dev_out);
+    L.plan(r.M, r.N, mode_plane(r.prm.mode), r.query && !r.idx_dev_out);
     return L.total;
   }
 
@@ -391,7 +391,7 @@ struct Engine {
     *oom = false;
     (void)hipGetLastError();  // launch errors below are checked against a clean slate
     HostSlot& h = hs[s];
-    const bool p2pl = !r.query && r.prm.mode == ICP_P2PL_WELSCH;
+    const bool p2pl = !r.query && mode_plane(r.prm.mode);
     h.L.plan(r.M, r.N, p2pl, r.query && !r.idx_dev_out, r.trace_cap);
     h.mem = arena->alloc(h.L.total);
     if (!h.mem) { *oom = true; return true; }
@@ -426,7 +426,7 @@ struct Engine {
     S.eps = r.prm.eps;
     S.nu_min = r.prm.nu_min;
     S.nu_max = r.prm.nu_max;
-    S.nu_auto = (!r.query && !r.eval && r.prm.mode != ICP_P2P_L2 && !(r.prm.nu_max > 0)) ? 1 : 0;
+    S.nu_auto = (!r.query && !r.eval && !mode_l2(r.prm.mode) && !(r.prm.nu_max > 0)) ? 1 : 0;
     S.want_median = S.nu_auto;
     hs[s].want_median = S.want_median != 0;
     S.k = 1;
@@ -457,7 +457,7 @@ struct Engine {
     // automatic nu_min from the targets' six nearest neighbours, into the
     // state (scratch holds the per-target values until the source sort)
     if (r.numin_only || (!r.query && !r.eval && auto_nu_min(&r.prm))) {
-      const bool plane = r.prm.mode == ICP_P2PL_WELSCH;
+      const bool plane = mode_plane(r.prm.mode);
       launch_nu_min_auto(F4(L.o_qorg), F4(L.o_clo), F4(L.o_chi), F4(L.o_slo), F4(L.o_shi), L.ncl,
                          L.nsup, F(L.o_qx), F(L.o_qy), F(L.o_qz), plane ? F(L.o_nx) : nullptr,
                          plane ? F(L.o_ny) : nullptr, plane ? F(L.o_nz) : nullptr, L.N, plane,
@@ -601,10 +601,10 @@ static bool rigid_ok(const double* T) {
 
 static icp_status check_params(const icp_params* p) {
   if (!p) return ICP_ERR_INVALID_ARG;
-  if (p->mode < ICP_P2P_L2 || p->mode > ICP_P2PL_WELSCH) return ICP_ERR_INVALID_ARG;
+  if (p->mode < ICP_P2P_L2 || p->mode > ICP_P2PL_L2) return ICP_ERR_INVALID_ARG;
   if (p->anderson_m < 0 || p->anderson_m > 6) return ICP_ERR_INVALID_ARG;
   // nu_min <= 0: the automatic rule (six nearest targets), which needs N >= 7
-  if (p->mode != ICP_P2P_L2 && !std::isfinite(p->nu_min)) return ICP_ERR_INVALID_ARG;
+  if (!mode_l2(p->mode) && !std::isfinite(p->nu_min)) return ICP_ERR_INVALID_ARG;
   if (!(p->eps > 0.0) || p->iter_first <= 0 || p->max_line_search < 0) return ICP_ERR_INVALID_ARG;
   if (p->nn < ICP_NN_AUTO || p->nn > ICP_NN_CLUSTER) return ICP_ERR_INVALID_ARG;
   if (p->engine != ICP_ENGINE_GRAPH && p->engine != ICP_ENGINE_PLAIN) return ICP_ERR_INVALID_ARG;
@@ -860,7 +860,8 @@ const char* icp_status_str(icp_status s) {
 }
 
 icp_status icp_params_default(icp_mode mode, icp_params* out) {
-  if (!out || mode < ICP_P2P_L2 || mode > ICP_P2PL_WELSCH) return ICP_ERR_INVALID_ARG;
+  if (!out || mode < ICP_P2P_L2 || mode > ICP_P2PL_L2) return ICP_ERR_INVALID_ARG;
+  if (mode == ICP_P2PL_L2) return icp_params_classical(mode, out);
   std::memset(out, 0, sizeof *out);
   out->mode = mode;
   out->anderson_m = 5;
@@ -874,6 +875,27 @@ icp_status icp_params_default(icp_mode mode, icp_params* out) {
   } else {
     out->iter_first = 1000; out->iter_inc = 0; out->iter_cap = 1000;
   }
+  out->nn = ICP_NN_AUTO;
+  out->engine = ICP_ENGINE_GRAPH;
+  for (int i = 0; i < 16; ++i) out->T0[i] = (i % 5 == 0) ? 1.0 : 0.0;
+  return ICP_OK;
+}
+
+// App. E: the comparison methods run to 1000 iterations or until the squared
+// Frobenius norm of the change of transform is below 1e-5.
+icp_status icp_params_classical(icp_mode mode, icp_params* out) {
+  if (!out || (mode != ICP_P2P_L2 && mode != ICP_P2PL_L2)) return ICP_ERR_INVALID_ARG;
+  std::memset(out, 0, sizeof *out);
+  out->mode = mode;
+  out->anderson_m = 0;
+  out->nu_max = -1.0;
+  out->nu_min = -1.0;
+  out->eps = std::sqrt(1e-5);
+  out->iter_first = 1000;
+  out->iter_inc = 0;
+  out->iter_cap = 1000;
+  out->max_total_iter = 0;
+  out->max_line_search = 0;
   out->nn = ICP_NN_AUTO;
   out->engine = ICP_ENGINE_GRAPH;
   for (int i = 0; i < 16; ++i) out->T0[i] = (i % 5 == 0) ? 1.0 : 0.0;
@@ -929,9 +951,9 @@ static icp_status validate_host(const float* P, int64_t M, const float* Q, const
   if (s != ICP_OK) return s;
   s = check_params_sized(prm, N);
   if (s != ICP_OK) return s;
-  if (prm->mode == ICP_P2PL_WELSCH && !Qn) return ICP_ERR_NO_NORMALS;
+  if (mode_plane(prm->mode) && !Qn) return ICP_ERR_NO_NORMALS;
   if (!finite_coords(P, M) || !finite_coords(Q, N)) return ICP_ERR_NONFINITE;
-  if (prm->mode == ICP_P2PL_WELSCH) {
+  if (mode_plane(prm->mode)) {
     if (!finite_coords(Qn, N)) return ICP_ERR_NONFINITE;
     for (int64_t i = 0; i < N; ++i) {
       const double l = (double)Qn[3 * i] * Qn[3 * i] + (double)Qn[3 * i + 1] * Qn[3 * i + 1] +
@@ -950,7 +972,7 @@ icp_status icp_register(icp_ctx* ctx, const float* P, int64_t M, const float* Q,
   OwnedRequest r;
   r.P.assign(P, P + 3 * M);
   r.Q.assign(Q, Q + 3 * N);
-  if (params->mode == ICP_P2PL_WELSCH) r.Qn.assign(Qn, Qn + 3 * N);
+  if (mode_plane(params->mode)) r.Qn.assign(Qn, Qn + 3 * N);
   r.M = M; r.N = N; r.prm = *params;
   std::lock_guard<std::mutex> g(ctx->sync_mu);
   return run_sync(ctx, r, out, nullptr, nullptr, nullptr);
@@ -962,16 +984,16 @@ icp_status icp_eval(icp_ctx* ctx, const float* P, int64_t M, const float* Q, con
   if (!ctx || !T || !energy_out || !T_out || !flags_out) return ICP_ERR_INVALID_ARG;
   icp_params prm;
   if (icp_params_default(mode, &prm) != ICP_OK) return ICP_ERR_INVALID_ARG;
-  if (mode != ICP_P2P_L2 && !(nu > 0.0 && std::isfinite(nu))) return ICP_ERR_INVALID_ARG;
-  prm.nu_min = mode == ICP_P2P_L2 ? 0.0 : nu;
-  prm.nu_max = mode == ICP_P2P_L2 ? 1.0 : nu;
+  if (!mode_l2(mode) && !(nu > 0.0 && std::isfinite(nu))) return ICP_ERR_INVALID_ARG;
+  prm.nu_min = mode_l2(mode) ? 0.0 : nu;
+  prm.nu_max = mode_l2(mode) ? 1.0 : nu;
   std::memcpy(prm.T0, T, sizeof prm.T0);
   const icp_status v = validate_host(P, M, Q, Qn, N, &prm);
   if (v != ICP_OK) return v;
   OwnedRequest r;
   r.P.assign(P, P + 3 * M);
   r.Q.assign(Q, Q + 3 * N);
-  if (mode == ICP_P2PL_WELSCH) r.Qn.assign(Qn, Qn + 3 * N);
+  if (mode_plane(mode)) r.Qn.assign(Qn, Qn + 3 * N);
   r.M = M; r.N = N; r.prm = prm;
   r.eval = true;
   std::memcpy(r.Tq, T, sizeof r.Tq);
@@ -996,7 +1018,7 @@ icp_status icp_register_trace(icp_ctx* ctx, const float* P, int64_t M, const flo
   OwnedRequest r;
   r.P.assign(P, P + 3 * M);
   r.Q.assign(Q, Q + 3 * N);
-  if (params->mode == ICP_P2PL_WELSCH) r.Qn.assign(Qn, Qn + 3 * N);
+  if (mode_plane(params->mode)) r.Qn.assign(Qn, Qn + 3 * N);
   r.M = M; r.N = N; r.prm = *params;
   r.trace_cap = trace_cap;
   std::lock_guard<std::mutex> g(ctx->sync_mu);
@@ -1020,7 +1042,7 @@ icp_status icp_register_dev(icp_ctx* ctx, const float* P_dev, int64_t M, const f
   if (s != ICP_OK) return s;
   s = check_params_sized(params, N);
   if (s != ICP_OK) return s;
-  if (params->mode == ICP_P2PL_WELSCH && !Qn_dev) return ICP_ERR_NO_NORMALS;
+  if (mode_plane(params->mode) && !Qn_dev) return ICP_ERR_NO_NORMALS;
   OwnedRequest r;
   r.P_dev = P_dev; r.Q_dev = Q_dev; r.Qn_dev = Qn_dev;
   r.M = M; r.N = N; r.prm = *params;
@@ -1160,7 +1182,7 @@ icp_status icp_batch_submit(icp_ctx* ctx, const icp_request* reqs, int n, uint64
     auto r = std::make_unique<OwnedRequest>();
     r->P.assign(q.P, q.P + 3 * q.M);
     r->Q.assign(q.Q, q.Q + 3 * q.N);
-    if (q.params.mode == ICP_P2PL_WELSCH) r->Qn.assign(q.Qn, q.Qn + 3 * q.N);
+    if (mode_plane(q.params.mode)) r->Qn.assign(q.Qn, q.Qn + 3 * q.N);
     r->M = q.M; r->N = q.N; r->prm = q.params;
     r->t_submit = now;
     owned.push_back(std::move(r));

@@ -10,7 +10,8 @@
 //    per-pair bounding-box centres.
 //  point-to-plane (eq. ProxyPointToPlaneAlignment, eq. GNSystem): B = (x - q) . n,
 //    g = exp(-B^2 / (2 nu^2)), J from the per-pass derivative matrices
-//    (App. D), sum g J J^T (upper triangle), sum g B J, sum g, sum psi_nu(B).
+//    (App. D), sum g J J^T (upper triangle), sum g B J, sum g, sum psi_nu(B);
+//    classical point-to-plane ICP takes g = 1 and the energy term B^2.
 #include "icp_internal.h"
 
 namespace icp {
@@ -113,9 +114,15 @@ __device__ __forceinline__ void accumulate_p2pl(const SlotDesc& D, const SlotSta
   const double s = S.inv2nu2;
   const double n0 = D.nx[idx], n1 = D.ny[idx], n2 = D.nz[idx];
   const double B = __builtin_fma(dz, n2, __builtin_fma(dy, n1, dx * n0));
-  const double B2s = B * B * s;
-  const double gam = exp(-B2s);
-  v[0] += -expm1(-B2s);
+  // classical point-to-plane ICP: unit weights and energy B^2
+  double gam = 1.0;
+  if (D.mode == P2PL_L2) {
+    v[0] += B * B;
+  } else {
+    const double B2s = B * B * s;
+    gam = exp(-B2s);
+    v[0] += -expm1(-B2s);
+  }
   v[1] += gam;
   if (S.want_median) D.medkey[si] = fabs(B);
   // J: rotation part n . (dR_j p + dt/d delta_j), translation part (dt/du)^T n
@@ -168,7 +175,7 @@ __global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ d
     double* out = D.part + (size_t)e * kPartStride;
     // each thread accumulates kEpiRows sources (one per 256-source row of the
     // item) in row order, then the block reduces in a fixed order
-    if (D.mode != P2PL_WELSCH) {
+    if (!mode_plane(D.mode)) {
       double v[kP2PVals];
 #pragma unroll
       for (int i = 0; i < kP2PVals; ++i) v[i] = 0.0;

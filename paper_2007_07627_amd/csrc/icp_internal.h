@@ -28,7 +28,10 @@ constexpr float kVerletFrac = 0.08f;  // candidate-list margin / median cluster 
 // tile record flags (cull kernel -> slice kernel)
 enum TileFlags { TI_WARM = 1, TI_LIST = 2, TI_RANGE = 4, TI_LANETEST = 8 };
 
-enum Mode { P2P_L2 = 0, P2P_WELSCH = 1, P2PL_WELSCH = 2 };
+enum Mode { P2P_L2 = 0, P2P_WELSCH = 1, P2PL_WELSCH = 2, P2PL_L2 = 3 };
+// point-to-plane residuals (normals needed) / unit weights (no nu)
+__host__ __device__ constexpr bool mode_plane(int m) { return m == P2PL_WELSCH || m == P2PL_L2; }
+__host__ __device__ constexpr bool mode_l2(int m) { return m == P2P_L2 || m == P2PL_L2; }
 enum NNMethod { NN_AUTO = 0, NN_BRUTE = 1, NN_CLUSTER = 2 };
 enum SlotStatus { ST_FREE = 0, ST_SETUP = 1, ST_RUNNING = 2, ST_DONE = 3 };
 

@@ -582,8 +582,8 @@ __device__ inline bool same_bits(const double* a, const double* b, int n) {
 }
 
 __device__ inline void set_nu(SlotState& S, double nu) {
-  S.inv2nu2 = S.mode == P2P_L2 ? 0.0 : 1.0 / (2.0 * nu * nu);
-  S.nu_eval = S.mode == P2P_L2 ? 0.0 : nu;
+  S.inv2nu2 = mode_l2(S.mode) ? 0.0 : 1.0 / (2.0 * nu * nu);
+  S.nu_eval = mode_l2(S.mode) ? 0.0 : nu;
 }
 
 // Candidate lists are rebuilt on the first two passes (the first has no warm
@@ -651,7 +651,7 @@ __device__ void request_xi(SlotState& S, const double xi[6], double nu) {
 __device__ void finish(SlotState& S, const double T[16], double E) {
   for (int i = 0; i < 16; ++i) S.Tres[i] = T[i];
   S.energy = E;
-  S.nu_final = S.mode == P2P_L2 ? 0.0 : S.nu;
+  S.nu_final = mode_l2(S.mode) ? 0.0 : S.nu;
   S.status = ST_DONE;
 }
 
@@ -812,7 +812,7 @@ __device__ void step_p2pl(SlotState& S, const double* mom) {
       S.sm = SM_STAGE_EVAL;
       return;
     }
-    S.nu = S.nu_max;
+    S.nu = mode_l2(S.mode) ? 0.0 : S.nu_max;
     S.want_median = 0;
     sm = SM_STAGE_EVAL;
   }
@@ -903,9 +903,19 @@ __device__ void step_p2pl(SlotState& S, const double* mom) {
       finish(S, T, S.Eit);
       return;
     }
+    // Algorithm 2 tests the parameter change; classical point-to-plane ICP
+    // the change of transform, as the comparison methods do (App. E)
     double dn = 0.0;
-    for (int a = 0; a < 6; ++a) dn += (S.best_prop[a] - S.xk[a]) * (S.best_prop[a] - S.xk[a]);
-    if (sqrt(dn) < S.eps) {
+    if (mode_l2(S.mode)) {
+      double Tn[16], Tc[16];
+      twist_exp(S.best_prop, Tn);
+      twist_exp(S.xk, Tc);
+      dn = frob16(Tn, Tc);
+    } else {
+      for (int a = 0; a < 6; ++a) dn += (S.best_prop[a] - S.xk[a]) * (S.best_prop[a] - S.xk[a]);
+      dn = sqrt(dn);
+    }
+    if (dn < S.eps) {
       S.flags = (S.flags & ~F_MAX_ITER) | F_CONVERGED;
       goto stage_end;
     }
@@ -932,7 +942,7 @@ __device__ void step_p2pl(SlotState& S, const double* mom) {
   }
   return;
 stage_end:
-  if (S.nu == S.nu_min) {
+  if (mode_l2(S.mode) || S.nu == S.nu_min) {
     double T[16];
     twist_exp(S.xk, T);
     finish(S, T, S.Eit);
@@ -1071,7 +1081,7 @@ __global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__
   const SlotDesc& D = descs[slot];
   const int lane = threadIdx.x;
   double acc[kP2PLVals];
-  if (D.mode == P2PL_WELSCH) merge_partials<kP2PLVals>(D, acc);
+  if (mode_plane(D.mode)) merge_partials<kP2PLVals>(D, acc);
   else merge_partials<kP2PVals>(D, acc);
   if (lane == 0) solver_step(D, S, acc);
   __syncthreads();
@@ -1101,7 +1111,7 @@ __device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc) 
     // energy at the requested transform and the MM update from it
     double T[16];
     unsigned f;
-    if (D.mode == P2PL_WELSCH) {
+    if (mode_plane(D.mode)) {
       double xp[6];
       f = gn_p2pl(acc, S.last_key, xp);
       twist_exp(xp, T);
@@ -1111,7 +1121,7 @@ __device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc) 
     S.flags = f;
     S.nu = S.nu_eval;
     finish(S, T, acc[0]);
-  } else if (D.mode == P2PL_WELSCH) {
+  } else if (mode_plane(D.mode)) {
     step_p2pl(S, acc);
   } else {
     step_p2p(S, acc);
@@ -1131,13 +1141,13 @@ __global__ void boot_kernel(const SlotDesc* __restrict__ descs, SlotState* __res
   if (S.sm == SM_QUERY) {
     request_T(S, S.Tkm1, 1.0);
   } else if (S.sm == SM_EVAL) {
-    if (S.mode == P2PL_WELSCH) {
+    if (mode_plane(S.mode)) {
       twist_log(S.Tkm1, S.xkm1);
       request_xi(S, S.xkm1, S.nu_max);
     } else {
       request_T(S, S.Tkm1, S.nu_max);
     }
-  } else if (S.mode == P2PL_WELSCH) {
+  } else if (mode_plane(S.mode)) {
     twist_log(S.Tkm1, S.xkm1);
     request_xi(S, S.xkm1, S.nu_auto ? 1.0 : S.nu_max);
   } else {

@@ -36,6 +36,20 @@ def test_params_default_matches_paper():
     assert B.lib().icp_params_default(7, C.byref(B.icp_params())) == B.ICP_ERR_INVALID_ARG
 
 
+def test_params_classical_match_appendix_e():
+    """The comparison methods (App. E): no mixing, no line search, one stage
+    of at most 1000 iterations, ||dT||_F^2 < 1e-5."""
+    for mode in (B.ICP_P2P_L2, B.ICP_P2PL_L2):
+        p = B.icp_params_classical(mode)
+        assert p.mode == mode and p.anderson_m == 0 and p.max_line_search == 0
+        assert (p.iter_first, p.iter_inc, p.iter_cap) == (1000, 0, 1000)
+        assert abs(p.eps * p.eps - 1e-5) <= 1e-20
+    q = B.icp_params_default(B.ICP_P2PL_L2)
+    assert q.anderson_m == 0 and q.max_line_search == 0 and q.iter_first == 1000
+    for mode in (B.ICP_P2P_WELSCH, B.ICP_P2PL_WELSCH, 9):
+        assert B.lib().icp_params_classical(mode, C.byref(B.icp_params())) == B.ICP_ERR_INVALID_ARG
+
+
 def test_struct_sizes():
     assert C.sizeof(B.icp_params) == 192
     assert C.sizeof(B.icp_result) == 200
