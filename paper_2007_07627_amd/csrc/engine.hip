@@ -42,7 +42,7 @@ size_t sort_scratch_words(int);
 void launch_morton_order(const float*, const float*, const float*, int, const float*, unsigned*,
                          unsigned**, hipStream_t);
 void launch_build_clusters(const float*, const float*, const float*, const unsigned*, int, int,
-                           float4*, float4*, float4*, float4*, float4*, hipStream_t);
+                           float4*, float4*, float4*, float4*, float4*, float4*, hipStream_t);
 void launch_build_super(const float4*, const float4*, const float4*, int, int, float4*, float4*,
                         float*, hipStream_t);
 void launch_build_tiles(const float*, const float*, const float*, const unsigned*, int, int, float*,
@@ -123,8 +123,8 @@ struct Layout {
   // byte offsets
   size_t o_px, o_py, o_pz, o_perm, o_tsph, o_pox, o_poy, o_poz;
   size_t o_qx, o_qy, o_qz, o_nx, o_ny, o_nz;
-  size_t o_qloc, o_qorg, o_ccen, o_clo, o_chi, o_slo, o_shi;
-  size_t o_clist, o_tinfo, o_squeue, o_scount;
+  size_t o_qloc, o_qorg, o_ccen, o_clo, o_chi, o_kbox, o_slo, o_shi;
+  size_t o_clist, o_squeue, o_scount;
   size_t o_keys, o_nnidx, o_nnd2, o_part, o_med, o_idx, o_d2, o_scratch, o_trace, o_stats, o_items;
   int trace_cap = 0;
   size_t add(size_t bytes) {
@@ -150,11 +150,11 @@ struct Layout {
     o_qloc = add(16ull * ncl * kCluster);
     o_qorg = add(16ull * ncl * kCluster);
     o_ccen = add(16ull * ncl); o_clo = add(16ull * ncl); o_chi = add(16ull * ncl);
+    o_kbox = add(32ull * ncl * kChunksPerCluster);
     o_slo = add(16ull * nsup); o_shi = add(16ull * nsup);
     o_keys = add(8ull * M);
     o_clist = add(4ull * kListCap * ntile);
-    o_tinfo = add(16ull * ntile);
-    o_squeue = add(8ull * kMaxSlices * ntile);
+    o_squeue = add(16ull * kMaxSlices * ntile);
     o_scount = add(16);
     o_nnidx = add(4ull * M);
     o_nnd2 = add(4ull * M);
@@ -451,7 +451,7 @@ struct Engine {
     unsigned* order = nullptr;
     launch_morton_order(F(L.o_qx), F(L.o_qy), F(L.o_qz), L.N, bbQ, scratch, &order, ss);
     launch_build_clusters(F(L.o_qx), F(L.o_qy), F(L.o_qz), order, L.N, L.ncl, F4(L.o_qloc),
-                          F4(L.o_qorg), F4(L.o_ccen), F4(L.o_clo), F4(L.o_chi), ss);
+                          F4(L.o_qorg), F4(L.o_ccen), F4(L.o_clo), F4(L.o_chi), F4(L.o_kbox), ss);
     launch_build_super(F4(L.o_clo), F4(L.o_chi), F4(L.o_ccen), L.ncl, L.nsup, F4(L.o_slo),
                        F4(L.o_shi), rho, ss);
     // automatic nu_min from the targets' six nearest neighbours, into the
@@ -486,10 +486,10 @@ struct Engine {
     D.nz = p2pl ? F(L.o_nz) : nullptr;
     D.qloc = F4(L.o_qloc); D.qorg = F4(L.o_qorg); D.ccen = F4(L.o_ccen);
     D.clo = F4(L.o_clo); D.chi = F4(L.o_chi); D.slo = F4(L.o_slo); D.shi = F4(L.o_shi);
+    D.kbox = F4(L.o_kbox);
     D.keys = reinterpret_cast<unsigned long long*>(b + L.o_keys);
     D.clist = reinterpret_cast<int*>(b + L.o_clist);
-    D.tinfo = reinterpret_cast<int4*>(b + L.o_tinfo);
-    D.squeue = reinterpret_cast<int2*>(b + L.o_squeue);
+    D.squeue = reinterpret_cast<int4*>(b + L.o_squeue);
     D.scount = reinterpret_cast<int*>(b + L.o_scount);
     D.nnidx = reinterpret_cast<int32_t*>(b + L.o_nnidx);
     D.nnd2 = F(L.o_nnd2);

@@ -77,12 +77,13 @@ struct SlotDesc {
   const float4* ccen;         // cluster centre (x, y, z) and radius
   const float4* clo;          // cluster AABB min
   const float4* chi;          // cluster AABB max
+  const float4* kbox;         // per chunk of kChunk targets: AABB min, AABB max (2 entries)
   const float4* slo;          // super-cluster AABB min
   const float4* shi;          // super-cluster AABB max
   unsigned long long* keys;   // per sorted source: (bits(d2) << 32) | index, merged by atomic min
   int* clist;                 // per tile: kListCap candidate cluster ids
-  int4* tinfo;                // per tile: (flags, count, slice length, nearest cluster or -1)
-  int2* squeue;               // slices queued by the cull kernel: (tile, slice)
+  int4* squeue;               // slices queued by the cull kernel: (tile, first list
+                              // position, end position, flags | (nearest cluster + 1) << 4)
   int* scount;                // number of queued slices (reset by the planner)
   int32_t* nnidx;             // per sorted source: closest original target index
   float* nnd2;                // per sorted source: its FP32 squared distance

@@ -118,54 +118,85 @@ __device__ __forceinline__ float lane_f(float v, int j) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
 }
 
-// Process one cluster with the filter (all kCluster targets, in chunks of
-// kChunk) from its copy staged in LDS; every lane reads the same target, so
-// each read is a broadcast. The filter value of a target is
+// Process one cluster with the filter (in chunks of kChunk targets) from its
+// copy staged in LDS; every lane reads the same target, so each read is a
+// broadcast. With kPrune, chunks that no lane can need are skipped: every
+// target of a chunk is at exact squared distance >= lb2 from the lane's point
+// (the chunk's box bound, lowered by 2^-20 for its own rounding), and the lane
+// needs only targets within winner_threshold(min(H, W)) (W: warm bound), so a
+// chunk above that for every lane holds only targets strictly farther than
+// each lane's winner (no tie can be lost). The boxes of all chunks are tested
+// together before the first chunk is filtered. The exhaustive method filters
+// every chunk. The filter value of a target is
 // v = 2 (h - pl . ql) + |pl|^2 with pl = p' - cc, h = |ql|^2 / 2, evaluated as
 // three FMAs and a final FMA; its distance to the exact squared distance is at
 // most u (7 (|pl| + rho)^2 + |v|) (rounding of the centred coordinates, of h,
 // of the three FMAs and of the last FMA); 4u is used, so for the chunk
 // minimum v: lo = v - 2^-22 |v| - delta, hi = v + 2^-22 |v| + delta,
 // delta = 2^-22 7 (|pl| + rho)^2.
-__device__ __forceinline__ void filter_cluster(const float4* __restrict__ tg, int c, float plx,
-                                               float ply, float plz, float rho_c, LaneBest& L) {
+__device__ __forceinline__ void filter_chunk(const float4* __restrict__ qc, int id, float npx,
+                                             float npy, float npz, float pp, float delta,
+                                             LaneBest& L) {
+  static_assert(kChunk == 16, "the min tree below covers 16 targets");
+  float sv[kChunk];
+#pragma unroll
+  for (int j = 0; j < kChunk; ++j) {
+    const float4 a = qc[j];
+    sv[j] = __builtin_fmaf(npx, a.x, __builtin_fmaf(npy, a.y, __builtin_fmaf(npz, a.z, a.w)));
+  }
+  // balanced tree of three-way minima (8 instructions for 16 values)
+  const float t0 = fminf(fminf(sv[0], sv[1]), sv[2]);
+  const float t1 = fminf(fminf(sv[3], sv[4]), sv[5]);
+  const float t2 = fminf(fminf(sv[6], sv[7]), sv[8]);
+  const float t3 = fminf(fminf(sv[9], sv[10]), sv[11]);
+  const float t4 = fminf(fminf(sv[12], sv[13]), sv[14]);
+  const float m0 = fminf(fminf(t0, t1), t2);
+  const float m1 = fminf(fminf(t3, t4), sv[15]);
+  const float v = __builtin_fmaf(2.0f, fminf(m0, m1), pp);
+  // an all-padding chunk has v = +inf: keep lo = hi = +inf (no inf - inf)
+  const float e = fminf(0x1.0p-22f * fabsf(v) + delta, 1e38f);
+  const float lo = v - e, hi = v + e;
+  const bool better = hi < L.H;
+  const float olo = better ? L.loA : lo;  // the chunk that is not (or no longer) A
+  const int oid = better ? L.A : id;
+  const bool nb = olo < L.S;
+  L.S2 = fminf(L.S2, nb ? L.S : olo);
+  L.B = nb ? oid : L.B;
+  L.S = nb ? olo : L.S;
+  L.loA = better ? lo : L.loA;
+  L.A = better ? id : L.A;
+  L.H = fminf(L.H, hi);
+}
+
+template <bool kPrune>
+__device__ __forceinline__ int filter_cluster(const float4* __restrict__ tg,
+                                               const float4* __restrict__ bx, int c, float plx,
+                                               float ply, float plz, float rho_c, float px,
+                                               float py, float pz, bool valid, float W,
+                                               LaneBest& L) {
   const float npx = -plx, npy = -ply, npz = -plz;
   const float pp = __builtin_fmaf(plz, plz, __builtin_fmaf(ply, ply, plx * plx));
   const float t = sqrtf(pp) + rho_c;
   const float delta = 0x1.0p-22f * 7.0f * 1.0001f * t * t;
-#pragma unroll 1
-  for (int ch = 0; ch < kChunksPerCluster; ++ch) {
-    const float4* qc = tg + ch * kChunk;
-    static_assert(kChunk == 16, "the min tree below covers 16 targets");
-    float sv[kChunk];
+  if (kPrune) {
+    const float thr = winner_threshold(fminf(L.H, W));
+    unsigned mask = 0;
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      const float4 a = qc[j];
-      sv[j] = __builtin_fmaf(npx, a.x, __builtin_fmaf(npy, a.y, __builtin_fmaf(npz, a.z, a.w)));
+    for (int ch = 0; ch < kChunksPerCluster; ++ch) {
+      const float lb2 = box_lb2(px, py, pz, bx[2 * ch], bx[2 * ch + 1]);
+      if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr)) mask |= 1u << ch;
     }
-    // balanced tree of three-way minima (8 instructions for 16 values)
-    const float t0 = fminf(fminf(sv[0], sv[1]), sv[2]);
-    const float t1 = fminf(fminf(sv[3], sv[4]), sv[5]);
-    const float t2 = fminf(fminf(sv[6], sv[7]), sv[8]);
-    const float t3 = fminf(fminf(sv[9], sv[10]), sv[11]);
-    const float t4 = fminf(fminf(sv[12], sv[13]), sv[14]);
-    const float m0 = fminf(fminf(t0, t1), t2);
-    const float m1 = fminf(fminf(t3, t4), sv[15]);
-    const float v = __builtin_fmaf(2.0f, fminf(m0, m1), pp);
-    // an all-padding chunk has v = +inf: keep lo = hi = +inf (no inf - inf)
-    const float e = fminf(0x1.0p-22f * fabsf(v) + delta, 1e38f);
-    const float lo = v - e, hi = v + e;
-    const int id = c * kChunksPerCluster + ch;
-    const bool better = hi < L.H;
-    const float olo = better ? L.loA : lo;  // the chunk that is not (or no longer) A
-    const int oid = better ? L.A : id;
-    const bool nb = olo < L.S;
-    L.S2 = fminf(L.S2, nb ? L.S : olo);
-    L.B = nb ? oid : L.B;
-    L.S = nb ? olo : L.S;
-    L.loA = better ? lo : L.loA;
-    L.A = better ? id : L.A;
-    L.H = fminf(L.H, hi);
+    const int n = __builtin_popcount(mask);
+    for (; mask; mask &= mask - 1u) {
+      const int ch = __builtin_ctz(mask);
+      filter_chunk(tg + ch * kChunk, c * kChunksPerCluster + ch, npx, npy, npz, pp, delta, L);
+    }
+    return n;
+  } else {
+#pragma unroll 1
+    for (int ch = 0; ch < kChunksPerCluster; ++ch)
+      filter_chunk(tg + ch * kChunk, c * kChunksPerCluster + ch, npx, npy, npz, pp, delta, L);
+    return kChunksPerCluster;
   }
 }
 
@@ -196,6 +227,22 @@ __device__ __forceinline__ void lane_point(const SlotDesc& D, const double* T, i
       const float d = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
       W = d * (1.0f + 4e-6f) + 1e-37f;
     }
+  }
+}
+
+// The same from coordinates and previous index already loaded (prev < 0: no
+// warm bound), so that a caller can issue these loads early.
+__device__ __forceinline__ void lane_point_from(const SlotDesc& D, const double* T, bool valid,
+                                                float x, float y, float z, int prev, float& ptx,
+                                                float& pty, float& ptz, float& W) {
+  ptx = pty = ptz = 0.f;
+  W = __builtin_inff();
+  if (!valid) return;
+  xform_f32(T, x, y, z, ptx, pty, ptz);
+  if (prev >= 0 && prev < D.N) {
+    const float dx = ptx - D.qx[prev], dy = pty - D.qy[prev], dz = ptz - D.qz[prev];
+    const float d = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    W = d * (1.0f + 4e-6f) + 1e-37f;
   }
 }
 
@@ -423,14 +470,14 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
       len = max(kSliceMin, (n + kMaxSlices - 1) / kMaxSlices);
       nsl = max(1, (n + len - 1) / len);
     }
+    // each slice record carries everything the slice kernel needs, so that
+    // its first loads do not wait on a tile record
     if (wv == 0) {
       int base = 0;
-      if (lane == 0) {
-        D.tinfo[tile] = make_int4(flags, n, len, first);
-        base = atomicAdd(D.scount, nsl);
-      }
+      if (lane == 0) base = atomicAdd(D.scount, nsl);
       base = __shfl(base, 0, 64);
-      for (int k = lane; k < nsl; k += 64) D.squeue[base + k] = make_int2(tile, k);
+      for (int k = lane; k < nsl; k += 64)
+        D.squeue[base + k] = make_int4(tile, k * len, min(n, (k + 1) * len), flags | ((first + 1) << 4));
     }
   }
 }
@@ -467,6 +514,8 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
                                                       const SlotState* __restrict__ states,
                                                       WorkList* __restrict__ wl) {
   __shared__ float4 s_tgt[kCluster];
+  __shared__ float4 s_box[2 * kChunksPerCluster];
+  static_assert(2 * kChunksPerCluster <= 64, "one box entry per lane");
   const int lane = threadIdx.x;
   // one-slot engine: the slice total is the slot's count (from this pass's
   // cull or, with reused lists, from the last one)
@@ -483,16 +532,13 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     const SlotState& S = states[slot];
     const int local = g - wl->s_base[a];
     const long long t_begin = D.item_stats ? (long long)__builtin_readcyclecounter() : 0ll;
-    const int2 q = D.squeue[local];
-    const int tile = __builtin_amdgcn_readfirstlane(q.x), sl = __builtin_amdgcn_readfirstlane(q.y);
-    const int4 ti = D.tinfo[tile];
-    const int flags = __builtin_amdgcn_readfirstlane(ti.x), n = __builtin_amdgcn_readfirstlane(ti.y);
-    const int len = __builtin_amdgcn_readfirstlane(ti.z), first = __builtin_amdgcn_readfirstlane(ti.w);
+    const int4 q = D.squeue[local];
+    const int tile = __builtin_amdgcn_readfirstlane(q.x);
+    const int p0 = __builtin_amdgcn_readfirstlane(q.y), p1 = __builtin_amdgcn_readfirstlane(q.z);
+    const int meta = __builtin_amdgcn_readfirstlane(q.w);
+    const int flags = meta & 15, first = (meta >> 4) - 1;
     const int si = tile * kTile + lane;
     const bool valid = si < D.M;
-    float ptx, pty, ptz, W;
-    lane_point(D, S.Teval, si, valid, (flags & TI_WARM) != 0, ptx, pty, ptz, W);
-    const int p0 = sl * len, p1 = min(n, p0 + len);
     const int* __restrict__ list = D.clist + (size_t)tile * kListCap;
     const bool from_list = (flags & TI_LIST) != 0;
     // per-lane box test before a cluster is filtered: range tiles, and warm
@@ -510,44 +556,66 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     };
 
     LaneBest L{__builtin_inff(), __builtin_inff(), __builtin_inff(), __builtin_inff(), -1, -1};
-    int nproc = 0;
+    int nproc = 0;  // chunks run through the filter
     // Up to 64 entries at a time: lane j fetches entry j's cluster id, centre
-    // and box in one round trip; the loop reads them across lanes. The next
-    // cluster's targets are loaded into registers while the current one,
-    // staged in LDS, is filtered.
-    for (int gb = 0; gb < nent; gb += 64) {
+    // and box; the loop reads them across lanes. The first batch's loads are
+    // issued together with the source point's (coordinates, previous closest
+    // target), so that the slice starts after two round trips.
+    auto batch = [&](int gb, int& myc, float4& mcc, float4& mlo, float4& mhi) {
       const int e = gb + lane;
-      int myc = -1;
-      float4 mcc = make_float4(0.f, 0.f, 0.f, 0.f), mlo = mcc, mhi = mcc;
-      if (e < nent) {
-        myc = cluster_at(e);
-        if (myc >= 0) {
-          mcc = D.ccen[myc];
-          if (lane_test) {
-            mlo = D.clo[myc];
-            mhi = D.chi[myc];
-          }
+      myc = e < nent ? cluster_at(e) : -1;
+      mcc = mlo = mhi = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (myc >= 0) {
+        mcc = D.ccen[myc];
+        if (lane_test) {
+          mlo = D.clo[myc];
+          mhi = D.chi[myc];
         }
       }
+    };
+    float spx = 0.f, spy = 0.f, spz = 0.f;
+    int prev = -1;
+    if (valid) {
+      spx = D.px[si];
+      spy = D.py[si];
+      spz = D.pz[si];
+      if (flags & TI_WARM) prev = D.nnidx[si];
+    }
+    int myc;
+    float4 mcc, mlo, mhi;
+    batch(0, myc, mcc, mlo, mhi);
+    float ptx, pty, ptz, W;
+    lane_point_from(D, S.Teval, valid, spx, spy, spz, prev, ptx, pty, ptz, W);
+    // The next cluster's targets are loaded into registers while the current
+    // one, staged in LDS, is filtered.
+    for (int gb = 0; gb < nent; gb += 64) {
+      if (gb > 0) batch(gb, myc, mcc, mlo, mhi);
       const int gn = min(64, nent - gb);
       const unsigned long long live = __ballot(lane < gn && myc >= 0);
       if (live == 0ull) continue;
       int j = __builtin_ctzll(live);
       int c = __builtin_amdgcn_readlane(myc, j);
       constexpr int kRows = kCluster / 64;
-      float4 r[kRows];
+      constexpr int kBoxes = 2 * kChunksPerCluster;
+      float4 r[kRows], rb = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int t = 0; t < kRows; ++t) r[t] = load_global(D.qloc, (size_t)c * kCluster + 64 * t + lane);
+      if (lane < kBoxes) rb = load_global(D.kbox, (size_t)c * kBoxes + lane);
       for (unsigned long long rest = live & (live - 1ull);; rest &= rest - 1ull) {
-        __syncthreads();
+        // the block is one wavefront: its LDS accesses complete in order, so
+        // a wavefront fence orders the staging against the filter's reads (a
+        // block barrier would also wait for the loads still in flight)
+        wave_lds_sync();
 #pragma unroll
         for (int t = 0; t < kRows; ++t) s_tgt[64 * t + lane] = r[t];
-        __syncthreads();
+        if (lane < kBoxes) s_box[lane] = rb;
+        wave_lds_sync();
         const int jn = rest ? __builtin_ctzll(rest) : -1;
         const int cn = rest ? __builtin_amdgcn_readlane(myc, jn) : -1;
         if (cn >= 0) {
 #pragma unroll
           for (int t = 0; t < kRows; ++t) r[t] = load_global(D.qloc, (size_t)cn * kCluster + 64 * t + lane);
+          if (lane < kBoxes) rb = load_global(D.kbox, (size_t)cn * kBoxes + lane);
         }
         bool run = true;
         if (lane_test && gb + j >= lead) {
@@ -560,8 +628,12 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
         if (run) {
           const float plx = ptx - lane_f(mcc.x, j), ply = pty - lane_f(mcc.y, j),
                       plz = ptz - lane_f(mcc.z, j);
-          filter_cluster(s_tgt, c, plx, ply, plz, lane_f(mcc.w, j), L);
-          ++nproc;
+          if (lane_test)
+            nproc += filter_cluster<true>(s_tgt, s_box, c, plx, ply, plz, lane_f(mcc.w, j), ptx,
+                                          pty, ptz, valid, W, L);
+          else
+            nproc += filter_cluster<false>(s_tgt, s_box, c, plx, ply, plz, lane_f(mcc.w, j), ptx,
+                                           pty, ptz, valid, W, L);
         }
         if (cn < 0) break;
         j = jn;
@@ -618,17 +690,17 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
       if (lane == 0 && D.stats) {
         // one statistics line per die keeps these atomics off a single address
         unsigned long long* st = D.stats + (blockIdx.x % kQueues) * kStatStride;
-        atomicAdd(&st[0], (unsigned long long)nproc * kCluster * (unsigned long long)nv);
+        atomicAdd(&st[0], (unsigned long long)nproc * kChunk * (unsigned long long)nv);
         atomicAdd(&st[1], (unsigned long long)ne);
       }
       if (lane == 0 && D.item_stats && local < D.ntile * kMaxSlices) {
         int* row = D.item_stats + 8 * (size_t)local;
         row[0] = (int)((long long)__builtin_readcyclecounter() - t_begin);
         row[1] = nproc;
-        row[2] = n;
+        row[2] = p1 - p0;
         row[3] = flags | (__any(amb) ? 64 : 0);
-        row[4] = sl;
-        row[5] = len;
+        row[4] = p0;
+        row[5] = p1;
         row[6] = (int)(t_filter - t_begin);
         row[7] = S.phases;
       }

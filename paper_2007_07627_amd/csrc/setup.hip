@@ -204,7 +204,7 @@ __global__ __launch_bounds__(64) void build_clusters_kernel(
     const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
     const unsigned* __restrict__ order, int n, int ncl, float4* __restrict__ qloc,
     float4* __restrict__ qorg, float4* __restrict__ ccen, float4* __restrict__ clo,
-    float4* __restrict__ chi) {
+    float4* __restrict__ chi, float4* __restrict__ kbox) {
   const int c = blockIdx.x;
   if (c >= ncl) return;
   const int lane = threadIdx.x;
@@ -224,6 +224,25 @@ __global__ __launch_bounds__(64) void build_clusters_kernel(
       for (int a = 0; a < 3; ++a) { mn[a] = fminf(mn[a], p[r][a]); mx[a] = fmaxf(mx[a], p[r][a]); }
     } else {
       p[r][0] = p[r][1] = p[r][2] = 0.0f;
+    }
+  }
+  // chunk boxes: the kChunk consecutive targets of a chunk sit in kChunk
+  // consecutive lanes of one row
+  static_assert(64 % kChunk == 0 && (kChunk & (kChunk - 1)) == 0, "chunks tile a row");
+  for (int r = 0; r < kRows; ++r) {
+    float kmn[3], kmx[3];
+    for (int a = 0; a < 3; ++a) {
+      kmn[a] = id[r] >= 0 ? p[r][a] : __builtin_inff();
+      kmx[a] = id[r] >= 0 ? p[r][a] : -__builtin_inff();
+      for (int o = 1; o < kChunk; o <<= 1) {
+        kmn[a] = fminf(kmn[a], __shfl_xor(kmn[a], o, 64));
+        kmx[a] = fmaxf(kmx[a], __shfl_xor(kmx[a], o, 64));
+      }
+    }
+    if ((lane & (kChunk - 1)) == 0) {
+      const size_t k = (size_t)c * kChunksPerCluster + (r * 64 + lane) / kChunk;
+      kbox[2 * k] = make_float4(kmn[0], kmn[1], kmn[2], 0.0f);
+      kbox[2 * k + 1] = make_float4(kmx[0], kmx[1], kmx[2], 0.0f);
     }
   }
   for (int a = 0; a < 3; ++a)
@@ -432,9 +451,9 @@ void launch_morton_order(const float* x, const float* y, const float* z, int n, 
 
 void launch_build_clusters(const float* x, const float* y, const float* z, const unsigned* order,
                            int n, int ncl, float4* qloc, float4* qorg, float4* ccen, float4* clo,
-                           float4* chi, hipStream_t st) {
+                           float4* chi, float4* kbox, hipStream_t st) {
   hipLaunchKernelGGL(build_clusters_kernel, dim3(ncl), dim3(64), 0, st, x, y, z, order, n, ncl, qloc,
-                     qorg, ccen, clo, chi);
+                     qorg, ccen, clo, chi, kbox);
 }
 
 void launch_build_super(const float4* clo, const float4* chi, const float4* ccen, int ncl, int nsup,
