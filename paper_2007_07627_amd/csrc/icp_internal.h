@@ -135,6 +135,7 @@ struct SlotState {
   double cP[3], cQ[3];        // fixed centring of the moments (bbox centres)
   double Tref[16];            // transform of the last candidate-list build
   double Vq[16];              // eigenbasis of the last quaternion alignment (warm start)
+  double lk[6];               // point-to-point with mixing: log of the current iterate Tk
   double verlet;              // list margin (copied from the descriptor at boot)
   int cull;                   // 1: this pass rebuilds the candidate lists
   int cull_pad;

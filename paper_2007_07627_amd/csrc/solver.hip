@@ -220,6 +220,7 @@ __device__ __forceinline__ void jacobi_rot(double A[16], double V[16], int p, in
 // zero pivot is replaced by a tiny one (M is then an exactly singular shifted
 // matrix and any large solution along its null space is what is wanted).
 __device__ __forceinline__ void solve4(double M[16], double b[4], double tiny) {
+  double inv[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     int p = k;
@@ -241,10 +242,10 @@ __device__ __forceinline__ void solve4(double M[16], double b[4], double tiny) {
       b[i] = sw ? a : c;
     }
     if (M[5 * k] == 0.0) M[5 * k] = tiny;
-    const double inv = 1.0 / M[5 * k];
+    inv[k] = 1.0 / M[5 * k];
 #pragma unroll
     for (int i = k + 1; i < 4; ++i) {
-      const double f = M[4 * i + k] * inv;
+      const double f = M[4 * i + k] * inv[k];
 #pragma unroll
       for (int j = k + 1; j < 4; ++j) M[4 * i + j] -= f * M[4 * k + j];
       b[i] -= f * b[k];
@@ -255,7 +256,7 @@ __device__ __forceinline__ void solve4(double M[16], double b[4], double tiny) {
     double v = b[k];
 #pragma unroll
     for (int j = k + 1; j < 4; ++j) v -= M[4 * k + j] * b[j];
-    b[k] = v / M[5 * k];
+    b[k] = v * inv[k];
   }
 }
 
@@ -295,8 +296,9 @@ __device__ bool top_eig_rqi(const double A[16], const double x0[4], double q[4],
     solve4(M, y, 1e-300 * nA);
     const double ny = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
     if (!(ny > 0.0) || !(ny < __builtin_inf())) return false;
+    const double iny = 1.0 / ny;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) x[i] = y[i] / ny;
+    for (int i = 0; i < 4; ++i) x[i] = y[i] * iny;
   }
   if (!settled || !(rn <= 1e-12 * nA)) return false;
   // Householder reflection H = I - 2 v v^T / (v^T v), v = x + sign(x_m) e_m
@@ -312,11 +314,12 @@ __device__ bool top_eig_rqi(const double A[16], const double x0[4], double q[4],
 #pragma unroll
   for (int i = 0; i < 4; ++i) v[i] += (i == m) ? sg : 0.0;
   const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
+  const double s2 = 2.0 / vv;
   double H[16];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) H[4 * i + j] = ((i == j) ? 1.0 : 0.0) - 2.0 * v[i] * v[j] / vv;
+    for (int j = 0; j < 4; ++j) H[4 * i + j] = ((i == j) ? 1.0 : 0.0) - s2 * v[i] * v[j];
   // H A H; column m of H is -sg x, the other columns span its complement
   double AH[16], C[16];
 #pragma unroll
@@ -350,8 +353,8 @@ __device__ bool top_eig_rqi(const double A[16], const double x0[4], double q[4],
   const double c11 = b - B[0], c21 = -0.5 * (B[3] + B[1]), c31 = -0.5 * (B[6] + B[2]);
   const double c22 = b - B[4], c32 = -0.5 * (B[7] + B[5]), c33 = b - B[8];
   if (!(c11 > 0.0)) return false;
-  const double l11 = sqrt(c11);
-  const double l21 = c21 / l11, l31 = c31 / l11;
+  const double l11 = sqrt(c11), il11 = 1.0 / l11;
+  const double l21 = c21 * il11, l31 = c31 * il11;
   const double d22 = c22 - l21 * l21;
   if (!(d22 > 0.0)) return false;
   const double l22 = sqrt(d22);
@@ -411,11 +414,12 @@ __device__ unsigned align_p2p(const double* mom, const double cP[3], const doubl
                               double V[16], double T[16]) {
   const double W = mom[1];
   if (!(W > 1e-300)) return F_ZERO_WEIGHT;
-  const double pb[3] = {mom[2] / W, mom[3] / W, mom[4] / W};
-  const double qb[3] = {mom[5] / W, mom[6] / W, mom[7] / W};
+  const double iW = 1.0 / W;
+  const double pb[3] = {mom[2] * iW, mom[3] * iW, mom[4] * iW};
+  const double qb[3] = {mom[5] * iW, mom[6] * iW, mom[7] * iW};
   double S[9];
   for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) S[3 * a + b] = mom[8 + 3 * a + b] - mom[2 + a] * mom[5 + b] / W;
+    for (int b = 0; b < 3; ++b) S[3 * a + b] = mom[8 + 3 * a + b] - pb[a] * mom[5 + b];
   const double Sxx = S[0], Sxy = S[1], Sxz = S[2], Syx = S[3], Syy = S[4], Syz = S[5],
                Szx = S[6], Szy = S[7], Szz = S[8];
   double N[16] = {Sxx + Syy + Szz, Syz - Szy,        Szx - Sxz,        Sxy - Syx,
@@ -512,7 +516,7 @@ __device__ bool anderson_mk(const SlotState& S, int k, int metric, double out[6]
                      dF[i][3] * dF[j][3] + dF[i][4] * dF[j][4] + dF[i][5] * dF[j][5];
     dmax = fmax(dmax, N[7 * i]);
   }
-  double L[36], th[6];
+  double L[36], iL[6], th[6];
 #pragma unroll
   for (int i = 0; i < 36; ++i) L[i] = 0.0;
   bool sing = !(dmax > 0.0);
@@ -523,12 +527,13 @@ __device__ bool anderson_mk(const SlotState& S, int k, int metric, double out[6]
     for (int kk = 0; kk < j; ++kk) s -= L[6 * j + kk] * L[6 * j + kk];
     if (!(s > 1e-10 * dmax)) sing = true;
     L[7 * j] = sing ? 1.0 : sqrt(s);
+    iL[j] = 1.0 / L[7 * j];
 #pragma unroll
     for (int i = j + 1; i < mk; ++i) {
       double v = N[6 * i + j];
 #pragma unroll
       for (int kk = 0; kk < j; ++kk) v -= L[6 * i + kk] * L[6 * j + kk];
-      L[6 * i + j] = v / L[7 * j];
+      L[6 * i + j] = v * iL[j];
     }
   }
   if (sing) {
@@ -541,14 +546,14 @@ __device__ bool anderson_mk(const SlotState& S, int k, int metric, double out[6]
       double v = r[i];
 #pragma unroll
       for (int kk = 0; kk < i; ++kk) v -= L[6 * i + kk] * y[kk];
-      y[i] = v / L[7 * i];
+      y[i] = v * iL[i];
     }
 #pragma unroll
     for (int i = mk - 1; i >= 0; --i) {
       double v = y[i];
 #pragma unroll
       for (int kk = i + 1; kk < mk; ++kk) v -= L[6 * kk + i] * th[kk];
-      th[i] = v / L[7 * i];
+      th[i] = v * iL[i];
     }
   }
 #pragma unroll
@@ -712,6 +717,7 @@ __device__ void step_p2p(SlotState& S, const double* mom) {
     for (int a = 0; a < 6; ++a) {
       S.G[(S.k - 1) % kHist][a] = lp[a];
       S.F[(S.k - 1) % kHist][a] = lp[a] - lq[a];
+      S.lk[a] = lp[a];
     }
     S.is_aa = 0;
     request_T(S, S.Tk, S.nu);
@@ -733,8 +739,10 @@ __device__ void step_p2p(SlotState& S, const double* mom) {
     S.iterations++;
     S.total++;
     if (m > 0 && E >= S.Eprev) {
-      // safeguard: revert to the un-accelerated iterate
+      // safeguard: revert to the un-accelerated iterate (whose log is the
+      // newest G entry)
       cpy(S.Tk, S.Tp, 16);
+      cpy(S.lk, S.G[(S.k - 1) % kHist], 6);
       S.aa_rejected++;
       request_T(S, S.Tk, S.nu);
       S.sm = SM_REVERT_EVAL;
@@ -764,16 +772,20 @@ __device__ void step_p2p(SlotState& S, const double* mom) {
       cpy(Tn, S.Tp, 16);
       S.is_aa = 0;
     } else {
-      double lp[6], lk[6], xa[6];
+      // log Tk is kept from when Tk was set: the G entry of an un-accelerated
+      // iterate, or the mixed parameters themselves (exp then log returns
+      // them up to rounding while the angle stays below pi)
+      double lp[6], xa[6];
       twist_log(S.Tp, lp);
-      twist_log(S.Tk, lk);
       for (int a = 0; a < 6; ++a) {
         S.G[S.k % kHist][a] = lp[a];
-        S.F[S.k % kHist][a] = lp[a] - lk[a];
+        S.F[S.k % kHist][a] = lp[a] - S.lk[a];
       }
       const int mk = (S.k - S.kstart) < m ? (S.k - S.kstart) : m;
       if (anderson(S, S.k, mk, 0, xa)) S.flags |= F_AA_SINGULAR;
       twist_exp(xa, Tn);
+      if (xa[0] * xa[0] + xa[1] * xa[1] + xa[2] * xa[2] < 9.0) cpy(S.lk, xa, 6);
+      else twist_log(Tn, S.lk);
       S.is_aa = 1;
     }
     cpy(S.Tk, Tn, 16);
