@@ -1077,24 +1077,43 @@ __global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__
                                                     int single) {
   const int slot = blockIdx.x;
   if (slot >= capacity) return;
-  if (states[slot].status != ST_RUNNING) return;
   // The state machine runs on an LDS copy of the slot state: its many
   // dependent reads and writes then cost LDS latency instead of a memory
-  // round trip each. The wavefront copies it in and out cooperatively.
+  // round trip each. The wavefront copies it in and out cooperatively. The
+  // state words (status included) and, for the one-slot engine, whose slot
+  // stays admitted for the whole replay, the partial moments are loaded in
+  // the same round trip.
   static_assert(sizeof(SlotState) % 8 == 0, "slot state is copied in 8-byte words");
   constexpr int kWords = (int)(sizeof(SlotState) / 8);
+  constexpr int kPer = (kWords + 63) / 64;
   __shared__ unsigned long long s_state[kWords];
-  {
-    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(states + slot);
-    for (int i = threadIdx.x; i < kWords; i += 64) s_state[i] = src[i];
+  const int lane = threadIdx.x;
+  const unsigned long long* src = reinterpret_cast<const unsigned long long*>(states + slot);
+  unsigned long long w[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int i = lane + 64 * t;
+    w[t] = i < kWords ? src[i] : 0ull;
+  }
+  const SlotDesc& D = descs[slot];
+  const bool plane = mode_plane(D.mode);
+  double acc[kP2PLVals];
+  if (single) {
+    if (plane) merge_partials<kP2PLVals>(D, acc);
+    else merge_partials<kP2PVals>(D, acc);
+  }
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int i = lane + 64 * t;
+    if (i < kWords) s_state[i] = w[t];
   }
   __syncthreads();
   SlotState& S = *reinterpret_cast<SlotState*>(s_state);
-  const SlotDesc& D = descs[slot];
-  const int lane = threadIdx.x;
-  double acc[kP2PLVals];
-  if (mode_plane(D.mode)) merge_partials<kP2PLVals>(D, acc);
-  else merge_partials<kP2PVals>(D, acc);
+  if (S.status != ST_RUNNING) return;
+  if (!single) {
+    if (plane) merge_partials<kP2PLVals>(D, acc);
+    else merge_partials<kP2PVals>(D, acc);
+  }
   if (lane == 0) solver_step(D, S, acc);
   __syncthreads();
   {
