@@ -26,7 +26,7 @@ namespace icp {
 
 // kernels launched from the other translation units
 void launch_nn(const SlotDesc*, const SlotState*, WorkList*, int, bool, hipStream_t);
-void launch_epi(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
+void launch_epi(const SlotDesc*, const SlotState*, WorkList*, int, bool, hipStream_t);
 void launch_solver(const SlotDesc*, SlotState*, int, int*, WorkList*, bool, hipStream_t);
 void launch_boot(const SlotDesc*, SlotState*, int, WorkList*, bool, hipStream_t);
 void launch_median(const SlotDesc*, SlotState*, int, hipStream_t);
@@ -333,7 +333,7 @@ struct Engine {
     mark(4 * i, s, capturing);
     launch_nn(d_desc, d_state, d_wl, nn_grid, single, s);
     mark(4 * i + 1, s, capturing);
-    launch_epi(d_desc, d_state, d_wl, epi_grid, s);
+    launch_epi(d_desc, d_state, d_wl, epi_grid, single, s);
     mark(4 * i + 2, s, capturing);
     if (!single || median) launch_median(d_desc, d_state, capacity, s);
     launch_solver(d_desc, d_state, capacity, d_done, d_wl, single, s);

@@ -39,119 +39,162 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* out)
   __syncthreads();
 }
 
-// Closest target of sorted source si from this pass's key (or the previous
-// pass's index when the transform is unchanged), with the FP64 residual at
-// the evaluated transform. Also hands the index on to the next pass.
-__device__ __forceinline__ bool source_residual(const SlotDesc& D, const SlotState& S,
-                                                const double* T, int si, int& idx, double& px,
-                                                double& py, double& pz, double& qxd, double& qyd,
-                                                double& qzd, double& dx, double& dy, double& dz) {
-  if (si >= D.M) return false;
-  if (!S.reuse) {
-    const unsigned long long key = D.keys[si];
-    idx = (int)(unsigned)(key & 0xffffffffull);
-    // every source receives a key from the search; stay in bounds regardless
-    if ((unsigned)idx >= (unsigned)D.N) idx = 0;
-    const float d2 = __uint_as_float((unsigned)(key >> 32));
-    D.nnidx[si] = idx;
-    D.nnd2[si] = d2;
-    D.keys[si] = ~0ull;  // ready for the next pass's atomic min
-    if (D.idx_out) {
-      const int o = D.perm[si];
-      D.idx_out[o] = idx;
-      D.d2_out[o] = d2;
+// One reduction item: kEpiRows rows of 256 sorted sources, one source per
+// thread and row. Every load of all rows is issued before any store or
+// arithmetic (the search keys, or the previous indices when the transform is
+// unchanged, and the source coordinates; then the closest targets and their
+// normals), so that an item costs two memory round trips. Then the closest
+// index is handed on to the next pass and the rows are accumulated in row
+// order; the block reduces in a fixed order.
+template <bool kPlane>
+__device__ __forceinline__ void epi_item(const SlotDesc& D, const SlotState& S, int e) {
+  constexpr int R = kEpiRows;
+  constexpr int NV = kPlane ? kP2PLVals : kP2PVals;
+  const bool reuse = S.reuse != 0;
+  int si[R], idx[R];
+  bool ok[R];
+  unsigned long long key[R];
+  float px[R], py[R], pz[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    si[r] = e * kEpiTile + 256 * r + (int)threadIdx.x;
+    ok[r] = si[r] < D.M;
+    idx[r] = 0;
+    key[r] = 0ull;
+    px[r] = py[r] = pz[r] = 0.0f;
+    if (ok[r]) {
+      if (!reuse) key[r] = D.keys[si[r]];
+      else idx[r] = D.nnidx[si[r]];
+      px[r] = D.px[si[r]];
+      py[r] = D.py[si[r]];
+      pz[r] = D.pz[si[r]];
     }
-  } else {
-    idx = D.nnidx[si];
   }
-  px = D.px[si];
-  py = D.py[si];
-  pz = D.pz[si];
-  // FP64 transform with the same fused order as the search, not rounded
-  const double x = __builtin_fma(T[2], pz, __builtin_fma(T[1], py, __builtin_fma(T[0], px, T[3])));
-  const double y = __builtin_fma(T[6], pz, __builtin_fma(T[5], py, __builtin_fma(T[4], px, T[7])));
-  const double z = __builtin_fma(T[10], pz, __builtin_fma(T[9], py, __builtin_fma(T[8], px, T[11])));
-  qxd = D.qx[idx];
-  qyd = D.qy[idx];
-  qzd = D.qz[idx];
-  dx = x - qxd;
-  dy = y - qyd;
-  dz = z - qzd;
-  return true;
-}
-
-__device__ __forceinline__ void accumulate_p2p(const SlotDesc& D, const SlotState& S,
-                                               const double* T, int si, double (&v)[kP2PVals]) {
-  int idx = 0;
-  double px, py, pz, qxd, qyd, qzd, dx, dy, dz;
-  if (!source_residual(D, S, T, si, idx, px, py, pz, qxd, qyd, qzd, dx, dy, dz)) return;
+  float qx[R], qy[R], qz[R], nx[R], ny[R], nz[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!reuse) idx[r] = (int)(unsigned)(key[r] & 0xffffffffull);
+    // every source receives a key from the search; stay in bounds regardless
+    if ((unsigned)idx[r] >= (unsigned)D.N) idx[r] = 0;
+    qx[r] = qy[r] = qz[r] = nx[r] = ny[r] = nz[r] = 0.0f;
+    if (ok[r]) {
+      qx[r] = D.qx[idx[r]];
+      qy[r] = D.qy[idx[r]];
+      qz[r] = D.qz[idx[r]];
+      if (kPlane) {
+        nx[r] = D.nx[idx[r]];
+        ny[r] = D.ny[idx[r]];
+        nz[r] = D.nz[idx[r]];
+      }
+    }
+  }
+  if (!reuse) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!ok[r]) continue;
+      const float d2 = __uint_as_float((unsigned)(key[r] >> 32));
+      D.nnidx[si[r]] = idx[r];
+      D.nnd2[si[r]] = d2;
+      D.keys[si[r]] = ~0ull;  // ready for the next pass's atomic min
+      if (D.idx_out) {
+        const int o = D.perm[si[r]];
+        D.idx_out[o] = idx[r];
+        D.d2_out[o] = d2;
+      }
+    }
+  }
+  const double* T = S.Teval;
   const double s = S.inv2nu2;
-  const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-  double w = 1.0;
-  if (D.mode == P2P_L2) {
-    v[0] += r2;
-  } else {
-    v[0] += -expm1(-r2 * s);
-    w = exp(-r2 * s);
+  double v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!ok[r]) continue;
+    // FP64 transform with the same fused order as the search, not rounded
+    const double p0 = px[r], p1 = py[r], p2 = pz[r];
+    const double x = __builtin_fma(T[2], p2, __builtin_fma(T[1], p1, __builtin_fma(T[0], p0, T[3])));
+    const double y = __builtin_fma(T[6], p2, __builtin_fma(T[5], p1, __builtin_fma(T[4], p0, T[7])));
+    const double z = __builtin_fma(T[10], p2, __builtin_fma(T[9], p1, __builtin_fma(T[8], p0, T[11])));
+    const double qxd = qx[r], qyd = qy[r], qzd = qz[r];
+    const double dx = x - qxd, dy = y - qyd, dz = z - qzd;
+    if (!kPlane) {
+      const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+      double w = 1.0;
+      if (D.mode == P2P_L2) {
+        v[0] += r2;
+      } else {
+        v[0] += -expm1(-r2 * s);
+        w = exp(-r2 * s);
+      }
+      if (S.want_median) D.medkey[si[r]] = r2;
+      const double a0 = p0 - S.cP[0], a1 = p1 - S.cP[1], a2 = p2 - S.cP[2];
+      const double b0 = qxd - S.cQ[0], b1 = qyd - S.cQ[1], b2 = qzd - S.cQ[2];
+      const double wa0 = w * a0, wa1 = w * a1, wa2 = w * a2;
+      v[1] += w;
+      v[2] += wa0; v[3] += wa1; v[4] += wa2;
+      v[5] += w * b0; v[6] += w * b1; v[7] += w * b2;
+      v[8] += wa0 * b0; v[9] += wa0 * b1; v[10] += wa0 * b2;
+      v[11] += wa1 * b0; v[12] += wa1 * b1; v[13] += wa1 * b2;
+      v[14] += wa2 * b0; v[15] += wa2 * b1; v[16] += wa2 * b2;
+    } else {
+      const double n0 = nx[r], n1 = ny[r], n2 = nz[r];
+      const double B = __builtin_fma(dz, n2, __builtin_fma(dy, n1, dx * n0));
+      // classical point-to-plane ICP: unit weights and energy B^2
+      double gam = 1.0;
+      if (D.mode == P2PL_L2) {
+        v[0] += B * B;
+      } else {
+        const double B2s = B * B * s;
+        gam = exp(-B2s);
+        v[0] += -expm1(-B2s);
+      }
+      v[1] += gam;
+      if (S.want_median) D.medkey[si[r]] = fabs(B);
+      // J: rotation part n . (dR_j p + dt/d delta_j), translation part (dt/du)^T n
+      const double* K = S.K;
+      double J[6];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double* Rj = K + 9 * j;
+        const double r0 = Rj[0] * p0 + Rj[1] * p1 + Rj[2] * p2 + K[27 + 0 + j];
+        const double r1 = Rj[3] * p0 + Rj[4] * p1 + Rj[5] * p2 + K[27 + 3 + j];
+        const double r2 = Rj[6] * p0 + Rj[7] * p1 + Rj[8] * p2 + K[27 + 6 + j];
+        J[j] = n0 * r0 + n1 * r1 + n2 * r2;
+        J[3 + j] = K[36 + j] * n0 + K[36 + 3 + j] * n1 + K[36 + 6 + j] * n2;
+      }
+      int t = 2;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const double ga = gam * J[a];
+#pragma unroll
+        for (int b = a; b < 6; ++b) v[t++] += ga * J[b];
+      }
+      const double gB = gam * B;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) v[23 + a] += gB * J[a];
+    }
   }
-  if (S.want_median) D.medkey[si] = r2;
-  const double a0 = px - S.cP[0], a1 = py - S.cP[1], a2 = pz - S.cP[2];
-  const double b0 = qxd - S.cQ[0], b1 = qyd - S.cQ[1], b2 = qzd - S.cQ[2];
-  const double wa0 = w * a0, wa1 = w * a1, wa2 = w * a2;
-  v[1] += w;
-  v[2] += wa0; v[3] += wa1; v[4] += wa2;
-  v[5] += w * b0; v[6] += w * b1; v[7] += w * b2;
-  v[8] += wa0 * b0; v[9] += wa0 * b1; v[10] += wa0 * b2;
-  v[11] += wa1 * b0; v[12] += wa1 * b1; v[13] += wa1 * b2;
-  v[14] += wa2 * b0; v[15] += wa2 * b1; v[16] += wa2 * b2;
+  block_reduce_store<NV>(v, D.part + (size_t)e * kPartStride);
 }
 
-__device__ __forceinline__ void accumulate_p2pl(const SlotDesc& D, const SlotState& S,
-                                                const double* T, int si, double (&v)[kP2PLVals]) {
-  int idx = 0;
-  double px, py, pz, qxd, qyd, qzd, dx, dy, dz;
-  if (!source_residual(D, S, T, si, idx, px, py, pz, qxd, qyd, qzd, dx, dy, dz)) return;
-  const double s = S.inv2nu2;
-  const double n0 = D.nx[idx], n1 = D.ny[idx], n2 = D.nz[idx];
-  const double B = __builtin_fma(dz, n2, __builtin_fma(dy, n1, dx * n0));
-  // classical point-to-plane ICP: unit weights and energy B^2
-  double gam = 1.0;
-  if (D.mode == P2PL_L2) {
-    v[0] += B * B;
-  } else {
-    const double B2s = B * B * s;
-    gam = exp(-B2s);
-    v[0] += -expm1(-B2s);
-  }
-  v[1] += gam;
-  if (S.want_median) D.medkey[si] = fabs(B);
-  // J: rotation part n . (dR_j p + dt/d delta_j), translation part (dt/du)^T n
-  const double* K = S.K;
-  double J[6];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const double* R = K + 9 * j;
-    const double r0 = R[0] * px + R[1] * py + R[2] * pz + K[27 + 0 + j];
-    const double r1 = R[3] * px + R[4] * py + R[5] * pz + K[27 + 3 + j];
-    const double r2 = R[6] * px + R[7] * py + R[8] * pz + K[27 + 6 + j];
-    J[j] = n0 * r0 + n1 * r1 + n2 * r2;
-    J[3 + j] = K[36 + j] * n0 + K[36 + 3 + j] * n1 + K[36 + 6 + j] * n2;
-  }
-  int t = 2;
-#pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    const double ga = gam * J[a];
-#pragma unroll
-    for (int b = a; b < 6; ++b) v[t++] += ga * J[b];
-  }
-  const double gB = gam * B;
-#pragma unroll
-  for (int a = 0; a < 6; ++a) v[23 + a] += gB * J[a];
-}
-
+// single: the one-slot engine (slot 0, admitted for the whole replay), whose
+// items are shared out statically by block index; otherwise items come from
+// the work list's queue and are mapped to their slots.
 __global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ descs,
                                                   const SlotState* __restrict__ states,
-                                                  WorkList* __restrict__ wl) {
+                                                  WorkList* __restrict__ wl, int single) {
+  if (single) {
+    const SlotDesc& D = descs[0];
+    const SlotState& S = states[0];
+    if (S.status != ST_RUNNING) return;
+    const bool plane = mode_plane(D.mode);
+    for (int e = blockIdx.x; e < D.nepi; e += gridDim.x) {
+      if (plane) epi_item<true>(D, S, e);
+      else epi_item<false>(D, S, e);
+    }
+    return;
+  }
   __shared__ int s_item;
   for (int round = 0;; ++round) {
     if (threadIdx.x == 0) s_item = queue_item(wl->q_epi, round);
@@ -171,31 +214,14 @@ __global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ d
     const SlotDesc& D = descs[slot];
     const SlotState& S = states[slot];
     const int e = g - wl->epi_base[lo];
-    const double* T = S.Teval;
-    double* out = D.part + (size_t)e * kPartStride;
-    // each thread accumulates kEpiRows sources (one per 256-source row of the
-    // item) in row order, then the block reduces in a fixed order
-    if (!mode_plane(D.mode)) {
-      double v[kP2PVals];
-#pragma unroll
-      for (int i = 0; i < kP2PVals; ++i) v[i] = 0.0;
-#pragma unroll
-      for (int r = 0; r < kEpiRows; ++r) accumulate_p2p(D, S, T, e * kEpiTile + 256 * r + threadIdx.x, v);
-      block_reduce_store<kP2PVals>(v, out);
-    } else {
-      double v[kP2PLVals];
-#pragma unroll
-      for (int i = 0; i < kP2PLVals; ++i) v[i] = 0.0;
-#pragma unroll
-      for (int r = 0; r < kEpiRows; ++r) accumulate_p2pl(D, S, T, e * kEpiTile + 256 * r + threadIdx.x, v);
-      block_reduce_store<kP2PLVals>(v, out);
-    }
+    if (mode_plane(D.mode)) epi_item<true>(D, S, e);
+    else epi_item<false>(D, S, e);
   }
 }
 
 void launch_epi(const SlotDesc* descs, const SlotState* states, WorkList* wl, int grid,
-                hipStream_t st) {
-  hipLaunchKernelGGL(epi_kernel, dim3(grid), dim3(256), 0, st, descs, states, wl);
+                bool single, hipStream_t st) {
+  hipLaunchKernelGGL(epi_kernel, dim3(grid), dim3(256), 0, st, descs, states, wl, single ? 1 : 0);
 }
 
 }  // namespace icp
