@@ -277,6 +277,7 @@ struct Engine {
     HIP_OK(hipMemset(d_desc, 0, sizeof(SlotDesc) * kMaxSlots));
     HIP_OK(hipMemset(d_state, 0, sizeof(SlotState) * kMaxSlots));
     HIP_OK(hipMemset(d_done, 0, sizeof(int) * kMaxSlots));
+    HIP_OK(hipMemset(d_wl, 0, sizeof(WorkList)));
     std::memset(h_done, 0, sizeof(int) * kMaxSlots);
     hs.assign(kMaxSlots, HostSlot());
     int cus = 256;

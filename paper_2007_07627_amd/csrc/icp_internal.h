@@ -187,6 +187,22 @@ struct WorkList {
   int q_s[kQueues * kQueueStride];
 };
 
+// Element i of a device array through a global-address-space pointer. The
+// descriptor's pointers are generic, and generic loads also hold the LDS
+// counter, so that waiting for LDS data would wait for them too; global loads
+// count only against the vector memory counter.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p, size_t i) {
+  return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+
+// LDS written by some lanes of a wavefront and read by others: a wavefront's
+// LDS operations complete in order, so a compiler fence is all it needs.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Work distribution of the persistent kernels. Workgroup b takes item b first
 // without an atomic; later items come from kQueues sub-queues, sub-queue
 // b mod kQueues serving the items gridDim + x + kQueues k. The hardware deals

@@ -72,6 +72,11 @@ __device__ __forceinline__ float4 load_global(const float4* p, size_t i) {
   const gv4f v = ((const __attribute__((address_space(1))) gv4f*)p)[i];
   return make_float4(v.x, v.y, v.z, v.w);
 }
+typedef int gv4i __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int4 load_global(const int4* p, size_t i) {
+  const gv4i v = ((const __attribute__((address_space(1))) gv4i*)p)[i];
+  return make_int4(v.x, v.y, v.z, v.w);
+}
 
 template <bool kGlobal>
 __device__ __forceinline__ unsigned long long exact_scan(const float4* qorg, int base,
@@ -219,11 +224,11 @@ __device__ __forceinline__ void lane_point(const SlotDesc& D, const double* T, i
   ptx = pty = ptz = 0.f;
   W = __builtin_inff();
   if (!valid) return;
-  xform_f32(T, D.px[si], D.py[si], D.pz[si], ptx, pty, ptz);
+  xform_f32(T, ldg(D.px, si), ldg(D.py, si), ldg(D.pz, si), ptx, pty, ptz);
   if (use_prev) {
-    const int prev = D.nnidx[si];
+    const int prev = ldg(D.nnidx, si);
     if (prev >= 0 && prev < D.N) {
-      const float dx = ptx - D.qx[prev], dy = pty - D.qy[prev], dz = ptz - D.qz[prev];
+      const float dx = ptx - ldg(D.qx, prev), dy = pty - ldg(D.qy, prev), dz = ptz - ldg(D.qz, prev);
       const float d = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
       W = d * (1.0f + 4e-6f) + 1e-37f;
     }
@@ -240,17 +245,10 @@ __device__ __forceinline__ void lane_point_from(const SlotDesc& D, const double*
   if (!valid) return;
   xform_f32(T, x, y, z, ptx, pty, ptz);
   if (prev >= 0 && prev < D.N) {
-    const float dx = ptx - D.qx[prev], dy = pty - D.qy[prev], dz = ptz - D.qz[prev];
+    const float dx = ptx - ldg(D.qx, prev), dy = pty - ldg(D.qy, prev), dz = ptz - ldg(D.qz, prev);
     const float d = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
     W = d * (1.0f + 4e-6f) + 1e-37f;
   }
-}
-
-// LDS written by some lanes of a wavefront and read by others: a wavefront's
-// LDS operations complete in order, so a compiler fence is all it needs.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
 }
 
 constexpr int kCullWaves = 4;
@@ -520,7 +518,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
   // one-slot engine: the slice total is the slot's count (from this pass's
   // cull or, with reused lists, from the last one)
   const int s_total = __builtin_amdgcn_readfirstlane(
-      wl->s_from_scount ? *descs[wl->slot[0]].scount : wl->s_total);
+      wl->s_from_scount ? ldg(descs[wl->slot[0]].scount, 0) : wl->s_total);
   for (int round = 0;; ++round) {
     int g = 0;
     if (lane == 0) g = queue_item(wl->q_s, round);
@@ -532,7 +530,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     const SlotState& S = states[slot];
     const int local = g - wl->s_base[a];
     const long long t_begin = D.item_stats ? (long long)__builtin_readcyclecounter() : 0ll;
-    const int4 q = D.squeue[local];
+    const int4 q = load_global(D.squeue, local);
     const int tile = __builtin_amdgcn_readfirstlane(q.x);
     const int p0 = __builtin_amdgcn_readfirstlane(q.y), p1 = __builtin_amdgcn_readfirstlane(q.z);
     const int meta = __builtin_amdgcn_readfirstlane(q.w);
@@ -551,7 +549,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     auto cluster_at = [&](int e) -> int {
       if (e < lead) return first;
       const int pos = p0 + e - lead;
-      const int c = from_list ? list[pos] : pos;
+      const int c = from_list ? ldg(list, pos) : pos;
       return (!from_list && c == first) ? -1 : c;
     };
 
@@ -566,20 +564,20 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
       myc = e < nent ? cluster_at(e) : -1;
       mcc = mlo = mhi = make_float4(0.f, 0.f, 0.f, 0.f);
       if (myc >= 0) {
-        mcc = D.ccen[myc];
+        mcc = load_global(D.ccen, myc);
         if (lane_test) {
-          mlo = D.clo[myc];
-          mhi = D.chi[myc];
+          mlo = load_global(D.clo, myc);
+          mhi = load_global(D.chi, myc);
         }
       }
     };
     float spx = 0.f, spy = 0.f, spz = 0.f;
     int prev = -1;
     if (valid) {
-      spx = D.px[si];
-      spy = D.py[si];
-      spz = D.pz[si];
-      if (flags & TI_WARM) prev = D.nnidx[si];
+      spx = ldg(D.px, si);
+      spy = ldg(D.py, si);
+      spz = ldg(D.pz, si);
+      if (flags & TI_WARM) prev = ldg(D.nnidx, si);
     }
     int myc;
     float4 mcc, mlo, mhi;
@@ -667,11 +665,12 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
       for (int e = 0; e < nent; ++e) {
         const int c = __builtin_amdgcn_readfirstlane(cluster_at(e));
         if (c < 0) continue;
-        const float lb2 = box_lb2(ptx, pty, ptz, D.clo[c], D.chi[c]);
+        const float lb2 = box_lb2(ptx, pty, ptz, load_global(D.clo, c), load_global(D.chi, c));
         const bool need = amb && lb2 * (1.0f - 0x1.0p-20f) <= thr;
         if (!__any(need)) continue;
         __syncthreads();
-        for (int t = 0; t < kCluster / 64; ++t) s_tgt[64 * t + lane] = D.qorg[c * kCluster + 64 * t + lane];
+        for (int t = 0; t < kCluster / 64; ++t)
+          s_tgt[64 * t + lane] = load_global(D.qorg, (size_t)c * kCluster + 64 * t + lane);
         __syncthreads();
         if (need) {
           key = exact_scan<false>(s_tgt, 0, kCluster, ptx, pty, ptz, key);

@@ -1057,7 +1057,7 @@ __device__ __forceinline__ void merge_partials(const SlotDesc& D, double* acc) {
   for (int e = lane; e < D.nepi; e += 64) {
     const double* p = D.part + (size_t)e * kPartStride;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) a[v] += p[v];
+    for (int v = 0; v < NV; ++v) a[v] += ldg(p, v);
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -1071,18 +1071,17 @@ __device__ __forceinline__ void merge_partials(const SlotDesc& D, double* acc) {
 
 __device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc);
 
-__global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__ descs,
-                                                    SlotState* __restrict__ states, int capacity,
-                                                    int* __restrict__ done, WorkList* __restrict__ wl,
-                                                    int single) {
-  const int slot = blockIdx.x;
-  if (slot >= capacity) return;
-  // The state machine runs on an LDS copy of the slot state: its many
-  // dependent reads and writes then cost LDS latency instead of a memory
-  // round trip each. The wavefront copies it in and out cooperatively. The
-  // state words (status included) and, for the one-slot engine, whose slot
-  // stays admitted for the whole replay, the partial moments are loaded in
-  // the same round trip.
+// One solver step of a slot, run by one wavefront (threads 0..63 of its
+// block). The state machine runs on an LDS copy of the slot state: its many
+// dependent reads and writes then cost LDS latency instead of a memory round
+// trip each. The wavefront copies it in and out cooperatively. The state
+// words (status included) and, for the one-slot engine, whose slot stays
+// admitted for the whole replay, the partial moments are loaded in the same
+// round trip.
+__device__ __forceinline__ void solver_run(const SlotDesc* __restrict__ descs,
+                                           SlotState* __restrict__ states,
+                           int* __restrict__ done, WorkList* __restrict__ wl, int slot,
+                           int single) {
   static_assert(sizeof(SlotState) % 8 == 0, "slot state is copied in 8-byte words");
   constexpr int kWords = (int)(sizeof(SlotState) / 8);
   constexpr int kPer = (kWords + 63) / 64;
@@ -1093,7 +1092,7 @@ __global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__
 #pragma unroll
   for (int t = 0; t < kPer; ++t) {
     const int i = lane + 64 * t;
-    w[t] = i < kWords ? src[i] : 0ull;
+    w[t] = ldg(src, i < kWords ? i : 0);
   }
   const SlotDesc& D = descs[slot];
   const bool plane = mode_plane(D.mode);
@@ -1107,7 +1106,7 @@ __global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__
     const int i = lane + 64 * t;
     if (i < kWords) s_state[i] = w[t];
   }
-  __syncthreads();
+  wave_lds_sync();
   SlotState& S = *reinterpret_cast<SlotState*>(s_state);
   if (S.status != ST_RUNNING) return;
   if (!single) {
@@ -1115,13 +1114,22 @@ __global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__
     else merge_partials<kP2PVals>(D, acc);
   }
   if (lane == 0) solver_step(D, S, acc);
-  __syncthreads();
+  wave_lds_sync();
   {
     unsigned long long* dst = reinterpret_cast<unsigned long long*>(states + slot);
-    for (int i = threadIdx.x; i < kWords; i += 64) dst[i] = s_state[i];
+    for (int i = lane; i < kWords; i += 64) dst[i] = s_state[i];
   }
   if (lane == 0 && S.status == ST_DONE) done[slot] = 1;
   if (lane == 0 && single) plan_single(D, S, wl, slot);
+}
+
+__global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__ descs,
+                                                    SlotState* __restrict__ states, int capacity,
+                                                    int* __restrict__ done, WorkList* __restrict__ wl,
+                                                    int single) {
+  const int slot = blockIdx.x;
+  if (slot >= capacity) return;
+  solver_run(descs, states, done, wl, slot, single);
 }
 
 // One pass of the state machine for a slot (lane 0 of the solver wavefront).
