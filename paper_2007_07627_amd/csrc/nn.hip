@@ -308,7 +308,7 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
       float U = warm ? sqrtf(wave_max(valid ? winner_threshold(W) : 0.0f)) * 1.000001f + 1e-30f
                      : __builtin_inff();
       for (int s2 = lane; s2 < D.nsup; s2 += 64)
-        U = fminf(U, sqrtf(box_ub2(cx, cy, cz, D.slo[s2], D.shi[s2])) * 1.000001f + r);
+        U = fminf(U, sqrtf(box_ub2(cx, cy, cz, load_global(D.slo, s2), load_global(D.shi, s2))) * 1.000001f + r);
       U = wave_min(U);
       // Warm lists are kept for later passes while every source stays within
       // the margin of its position now; a later pass's winner is then within
@@ -327,8 +327,8 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
         bool c = false;
         float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = blo;
         if (s2 < D.nsup) {
-          blo = D.slo[s2];
-          bhi = D.shi[s2];
+          blo = load_global(D.slo, s2);
+          bhi = load_global(D.shi, s2);
           c = sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r <= U * 1.00001f;
         }
         unsigned long long bal = __ballot(c);
@@ -373,8 +373,8 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
           int cid = f < nflat ? flat_cluster(f) : -1;
           float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = blo;
           if (cid >= 0) {
-            blo = D.clo[cid];
-            bhi = D.chi[cid];
+            blo = load_global(D.clo, cid);
+            bhi = load_global(D.chi, cid);
             if (!(sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r <= U * 1.00001f)) cid = -1;
           }
           const unsigned long long cand = __ballot(cid >= 0);
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
           bool c = false;
           const int cid = f < nflat ? flat_cluster(f) : -1;
           if (cid >= 0) {
-            const float4 blo = D.clo[cid], bhi = D.chi[cid];
+            const float4 blo = load_global(D.clo, cid), bhi = load_global(D.chi, cid);
             const float lb = sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r;
             const float ub = sqrtf(box_ub2(cx, cy, cz, blo, bhi)) * 1.000001f + r;
             if (ub < bestub || (ub == bestub && cid < bestc)) { bestub = ub; bestc = cid; }
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
             int cid = -1;
             if (f < ncand) {
               cid = s_cand[f];
-              const float lb = sqrtf(box_lb2(cx, cy, cz, D.clo[cid], D.chi[cid])) * 0.999999f - r;
+              const float lb = sqrtf(box_lb2(cx, cy, cz, load_global(D.clo, cid), load_global(D.chi, cid))) * 0.999999f - r;
               if (!(lb <= U * 1.00001f) || cid == first) cid = -1;
             }
             const unsigned long long keep = __ballot(cid >= 0);
