@@ -31,10 +31,54 @@ sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (packed FMA), published
 FLOPS_PER_PAIR = 8        # 3 sub, 1 mul, 2 FMA per (source, target) distance
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "nn_traffic_robust_p2p_100k.md")
+TRAFFIC_SOURCES = ["paper_2007_07627_amd/csrc/nn.hip", "paper_2007_07627_amd/csrc/icp_internal.h"]
+COPY_CALIBRATION_BYTES = 256 << 20
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def sources_digest():
+    """sha256 over the closest-point kernel sources (the counters in the
+    traffic summary hold only for the sources they were taken from)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per closest-point launch (cull + slice of one pass) from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when it is
+    missing or was taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            txt = f.read()
+    except OSError:
+        return None, "no counter summary"
+    tag = "<!-- traffic: "
+    if tag not in txt:
+        return None, "no counter summary"
+    rec = json.loads(txt.split(tag, 1)[1].split(" -->", 1)[0])
+    if rec.get("sources_sha256") != sources_digest():
+        return None, "counters predate the current kernel sources"
+    return float(rec["bytes_per_launch"]), "rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy"
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size, for scaling the HBM counters of a
+    rocprofv3 --pmc run (FETCH_SIZE / WRITE_SIZE in KiB per dispatch)."""
+    n = COPY_CALIBRATION_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 4 copies of {COPY_CALIBRATION_BYTES} bytes")
 
 
 def workload(name):
@@ -262,6 +306,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-brute", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain device copy of known size (for HBM counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the registration path runs on a single MI355X "
@@ -290,6 +336,8 @@ def main():
            for d, p in zip(ds, prms)]
     ctx = B.icp_create(0, 16 << 30)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        copy_calibration(torch)
 
     def run(engine, steps, profile=False):
         lat, res = [], []
@@ -345,11 +393,13 @@ def main():
     nn_ms = max(prof["nn_ms"], 1e-9)
     launches = max(1, prof["passes"])
     achieved = pairs * FLOPS_PER_PAIR / (nn_ms * 1e-3) / 1e12
+    traffic, traffic_note = measured_traffic() if args.workload == "robust-p2p-100k" else (None, "")
     roof = {"bound": "alu", "kernel": "nn_kernel", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+            "traffic_note": traffic_note,
             "ms_per_launch": nn_ms / launches, "launches": launches,
             "algorithmic_flops_per_launch": pairs * FLOPS_PER_PAIR / launches,
-            "work": "8 flops per (source, target) pair examined by the pruned search",
+            "work": "8 flops per (source, target) pair run through the filter (chunks some lane can need)",
             "share_of_pass_time": nn_ms / max(1e-9, nn_ms + prof["reduce_ms"] + prof["solve_ms"]),
             "reduce_ms_per_launch": prof["reduce_ms"] / launches,
             "solve_ms_per_launch": prof["solve_ms"] / launches}
