@@ -121,13 +121,19 @@ def cpu_baseline(d, prm, passes_per_reg, budget_s=12.0):
         t0 = time.perf_counter()
         oracle.eval_map(d["P"], d["Q"], d["Qn"] if mode == 2 else None, mode, np.eye(4), max(nu, 1e-3))
         times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start > budget_s or len(times) >= 5:
+        if time.perf_counter() - t_start > budget_s or len(times) >= 30:
             break
     t_pass = float(np.median(times))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     M, N = len(d["P"]), len(d["Q"])
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": 1.0 / (t_pass * passes_per_reg), "unit": "registrations/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": model,
             "sample": f"{len(times)} full-size map evaluations ({M} x {N} exhaustive FP32 closest point + "
                       f"FP64 alignment) at T0, median {t_pass:.3f} s each; registrations/s = "
                       f"1 / (t_eval x {passes_per_reg:.0f} closest-point passes per registration)",
