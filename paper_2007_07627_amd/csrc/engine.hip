@@ -154,7 +154,7 @@ struct Layout {
     o_slo = add(16ull * nsup); o_shi = add(16ull * nsup);
     o_keys = add(8ull * M);
     o_clist = add(4ull * kListCap * ntile);
-    o_squeue = add(16ull * kMaxSlices * ntile);
+    o_squeue = add(16ull * ((size_t)kMaxSlices * ntile + kExtraSlices));
     o_scount = add(16);
     o_nnidx = add(4ull * M);
     o_nnd2 = add(4ull * M);

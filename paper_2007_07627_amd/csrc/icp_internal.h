@@ -22,6 +22,11 @@ constexpr int kSupCap = 512;     // LDS candidate super-cluster capacity per NN 
 constexpr int kMaxSplit = 8;
 constexpr int kListCap = 512;    // candidate clusters stored per tile
 constexpr int kMaxSlices = 64;   // slices per tile in cluster mode
+// Candidate ranges over every cluster (tiles whose list would overflow) may be
+// cut into up to kMaxRangeSlices shorter slices, drawing the slices beyond
+// kMaxSlices from a per-pair budget of kExtraSlices.
+constexpr int kMaxRangeSlices = 256;
+constexpr int kExtraSlices = 1024;
 constexpr int kSliceMin = 6;     // clusters per slice at least (cluster mode)
 constexpr float kVerletFrac = 0.08f;  // candidate-list margin / median cluster radius
 
@@ -84,7 +89,7 @@ struct SlotDesc {
   int* clist;                 // per tile: kListCap candidate cluster ids
   int4* squeue;               // slices queued by the cull kernel: (tile, first list
                               // position, end position, flags | (nearest cluster + 1) << 4)
-  int* scount;                // number of queued slices (reset by the planner)
+  int* scount;                // [0] queued slices, [1] extra slices granted (reset by the planner)
   int32_t* nnidx;             // per sorted source: closest original target index
   float* nnd2;                // per sorted source: its FP32 squared distance
   double* part;               // nepi x kPartStride

@@ -472,8 +472,22 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
     // its first loads do not wait on a tile record
     if (wv == 0) {
       int base = 0;
-      if (lane == 0) base = atomicAdd(D.scount, nsl);
+      if (lane == 0) {
+        if (D.method != NN_BRUTE && (flags & TI_RANGE) && nsl >= kMaxSlices) {
+          // a long range (rare) is cut into shorter slices while the pair's
+          // budget of extra slices lasts: its slices would set the tail
+          const int l2 = max(kSliceMin, (n + kMaxRangeSlices - 1) / kMaxRangeSlices);
+          const int n2 = (n + l2 - 1) / l2;
+          if (n2 > nsl && atomicAdd(D.scount + 1, n2 - kMaxSlices) + (n2 - kMaxSlices) <= kExtraSlices) {
+            len = l2;
+            nsl = n2;
+          }
+        }
+        base = atomicAdd(D.scount, nsl);
+      }
       base = __shfl(base, 0, 64);
+      len = __shfl(len, 0, 64);
+      nsl = __shfl(nsl, 0, 64);
       for (int k = lane; k < nsl; k += 64)
         D.squeue[base + k] = make_int4(tile, k * len, min(n, (k + 1) * len), flags | ((first + 1) << 4));
     }

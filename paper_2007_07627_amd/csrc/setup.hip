@@ -374,7 +374,10 @@ __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__
   if (t < capacity && states[t].status == ST_RUNNING) {
     act = 1;
     nn = (states[t].reuse || !states[t].cull) ? 0 : descs[t].ntile;
-    if (nn) *descs[t].scount = 0;
+    if (nn) {
+      descs[t].scount[0] = 0;
+      descs[t].scount[1] = 0;
+    }
     ep = descs[t].nepi;
   }
   s_act[t] = act; s_nn[t] = nn; s_epi[t] = ep;

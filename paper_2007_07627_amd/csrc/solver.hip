@@ -1020,7 +1020,10 @@ __global__ __launch_bounds__(1024) void median_kernel(const SlotDesc* __restrict
 __device__ void plan_single(const SlotDesc& D, const SlotState& S, WorkList* wl, int slot) {
   const bool run = S.status == ST_RUNNING;
   const int nn = (run && !S.reuse && S.cull) ? D.ntile : 0;
-  if (nn) *D.scount = 0;
+  if (nn) {
+    D.scount[0] = 0;
+    D.scount[1] = 0;
+  }
   wl->single = 1;
   wl->n_active = run ? 1 : 0;
   wl->slot[0] = slot;
