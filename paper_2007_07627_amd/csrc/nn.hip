@@ -473,7 +473,7 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
     if (wv == 0) {
       int base = 0;
       if (lane == 0) {
-        if (D.method != NN_BRUTE && (flags & TI_RANGE) && nsl >= kMaxSlices) {
+        if (D.method != NN_BRUTE && (flags & TI_RANGE) && len > kSliceMin) {
           // a long range (rare) is cut into shorter slices while the pair's
           // budget of extra slices lasts: its slices would set the tail
           const int l2 = max(kSliceMin, (n + kMaxRangeSlices - 1) / kMaxRangeSlices);

@@ -98,3 +98,24 @@ def test_nn_full_size_sampled(ctx, method):
     sel = np.random.default_rng(0).choice(len(d["P"]), 3000, replace=False)
     oi, od = oracle.nn_query(d["P"][sel], d["Q"], d["T_gt"])
     assert np.array_equal(gi[sel], oi) and np.array_equal(gd[sel], od)
+
+
+@pytest.mark.parametrize("method", [B.ICP_NN_CLUSTER])
+def test_nn_scattered_tiles_long_ranges(ctx, method):
+    """Sources scattered over a box much larger than the target surface make
+    tiles whose candidate list overflows: they search every cluster in many
+    short slices (drawn from the per-pair budget of extra slices). Two
+    queries in a row and a registration check that the budget counter is
+    reset between passes."""
+    rng = np.random.default_rng(77)
+    Q = synth.bumpy_sphere(synth.rng_for(2, 77), 100_000)[0].astype(np.float32)
+    far = rng.uniform(-4.0, 4.0, (640, 3)).astype(np.float32)
+    near = Q[rng.choice(len(Q), 3000, replace=False)] + rng.normal(0, 0.01, (3000, 3)).astype(np.float32)
+    P = np.concatenate([far, near]).astype(np.float32)
+    for k in range(2):
+        _check(ctx, P, Q, _motion(90 + k, ang=5.0, tr=0.02), method, f"scattered {k}")
+    prm = B.icp_params_default(B.ICP_P2P_L2, anderson_m=0, iter_first=6, iter_cap=6, nn=method)
+    g = B.icp_register(ctx, P, Q, None, prm)
+    o = oracle.register(P, Q, mode=0, anderson_m=0, iter_first=6, iter_cap=6)
+    assert g["nn_passes"] == o["nn_passes"]
+    assert np.abs(g["T"] - o["T"]).max() < 1e-9
