@@ -22,11 +22,12 @@ constexpr int kSupCap = 512;     // LDS candidate super-cluster capacity per NN 
 constexpr int kMaxSplit = 8;
 constexpr int kListCap = 512;    // candidate clusters stored per tile
 constexpr int kMaxSlices = 64;   // slices per tile in cluster mode
-// Candidate ranges over every cluster (tiles whose list would overflow) may be
-// cut into up to kMaxRangeSlices shorter slices, drawing the slices beyond
-// kMaxSlices from a per-pair budget of kExtraSlices.
-constexpr int kMaxRangeSlices = 256;
-constexpr int kExtraSlices = 1024;
+// Long candidate sequences (lists whose length forced slices longer than
+// kSliceMin under the kMaxSlices cap, and ranges over every cluster for tiles
+// whose list would overflow) may be cut into up to kMaxLongSlices slices,
+// drawing the slices beyond kMaxSlices from a per-pair budget of kExtraSlices.
+constexpr int kMaxLongSlices = 1024;
+constexpr int kExtraSlices = 8192;
 constexpr int kSliceMin = 6;     // clusters per slice at least (cluster mode)
 constexpr float kVerletFrac = 0.08f;  // candidate-list margin / median cluster radius
 

@@ -473,10 +473,10 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
     if (wv == 0) {
       int base = 0;
       if (lane == 0) {
-        if (D.method != NN_BRUTE && (flags & TI_RANGE) && len > kSliceMin) {
-          // a long range (rare) is cut into shorter slices while the pair's
-          // budget of extra slices lasts: its slices would set the tail
-          const int l2 = max(kSliceMin, (n + kMaxRangeSlices - 1) / kMaxRangeSlices);
+        if (D.method != NN_BRUTE && len > kSliceMin) {
+          // a long candidate sequence (rare) is cut into shorter slices while
+          // the pair's budget of extra slices lasts: its slices would set the tail
+          const int l2 = max(kSliceMin, (n + kMaxLongSlices - 1) / kMaxLongSlices);
           const int n2 = (n + l2 - 1) / l2;
           if (n2 > nsl && atomicAdd(D.scount + 1, n2 - kMaxSlices) + (n2 - kMaxSlices) <= kExtraSlices) {
             len = l2;
