@@ -26,6 +26,7 @@ namespace icp {
 
 // kernels launched from the other translation units
 void launch_nn(const SlotDesc*, const SlotState*, WorkList*, int, bool, hipStream_t);
+void launch_brute(const SlotDesc*, const SlotState*, int, hipStream_t);
 void launch_epi(const SlotDesc*, const SlotState*, WorkList*, int, bool, hipStream_t);
 void launch_solver(const SlotDesc*, SlotState*, int, int*, WorkList*, bool, hipStream_t);
 void launch_boot(const SlotDesc*, SlotState*, int, WorkList*, bool, hipStream_t);
@@ -239,6 +240,7 @@ struct Engine {
   int dev = 0;
   int capacity = 1;
   bool single = false;       // one slot at a time, planned by its own solver
+  bool brute = false;        // one-slot engine: the resident pair uses the exhaustive method
   int target_items = 4096;   // NN work items aimed for when choosing splits
   hipStream_t st = nullptr;  // passes
   hipStream_t side = nullptr;  // admission / setup
@@ -253,6 +255,7 @@ struct Engine {
   int gphases = 0;
   int gcap = 0;
   bool gprof = false;
+  bool gbrute = false;
   int nn_grid = 4096, epi_grid = 1024;
   Arena* arena = nullptr;
   // profiling: timing events around the kernels of every pass
@@ -332,7 +335,9 @@ struct Engine {
   void enqueue_pass(hipStream_t s, int i = 0, bool capturing = false, bool median = false) {
     if (!single) launch_plan(d_desc, d_state, d_wl, capacity, s);
     mark(4 * i, s, capturing);
-    launch_nn(d_desc, d_state, d_wl, nn_grid, single, s);
+    // the one-slot engine's exhaustive method needs no cull pass
+    if (single && brute) launch_brute(d_desc, d_state, nn_grid, s);
+    else launch_nn(d_desc, d_state, d_wl, nn_grid, single, s);
     mark(4 * i + 1, s, capturing);
     launch_epi(d_desc, d_state, d_wl, epi_grid, single, s);
     mark(4 * i + 2, s, capturing);
@@ -360,7 +365,7 @@ struct Engine {
   }
 
   bool build_graph(int phases) {
-    if (gexec && gphases == phases && gcap == capacity && gprof == prof) return true;
+    if (gexec && gphases == phases && gcap == capacity && gprof == prof && gbrute == brute) return true;
     if (prof && !ensure_events(phases)) return false;
     if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
     if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
@@ -371,6 +376,7 @@ struct Engine {
     gphases = phases;
     gcap = capacity;
     gprof = prof;
+    gbrute = brute;
     return true;
   }
 
@@ -508,6 +514,7 @@ struct Engine {
     icp_nn_method meth = r.query ? r.qmethod : r.prm.nn;
     if (meth == ICP_NN_AUTO) meth = ((double)L.M * L.N <= 64.0e6) ? ICP_NN_BRUTE : ICP_NN_CLUSTER;
     D.method = meth == ICP_NN_BRUTE ? NN_BRUTE : NN_CLUSTER;
+    if (single) brute = D.method == NN_BRUTE;
     D.mode = S.mode;
     int split = std::max(1, cdiv(target_items, std::max(1, L.ntile)));
     split = std::min(split, std::min(kMaxSplit, L.ncl));

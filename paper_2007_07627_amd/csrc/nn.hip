@@ -722,6 +722,181 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
   }
 }
 
+// ------------------------------------------------------------------ exhaustive kernel
+// One-slot engine, exhaustive method: every target for every source, without
+// a cull pass. The wavefront holds two tiles (two sources per lane), so every
+// target read from LDS serves two pairs, which halves the LDS traffic per
+// pair. Items are (pair of tiles, cluster range) on a fixed grid of about
+// kBruteItems, shared out statically (they cost the same).
+constexpr int kBruteItems = 4096;
+
+// Folds one chunk into a lane's state (the bookkeeping of filter_chunk): m is
+// the chunk's minimum of h - pl . ql, v = 2 m + |pl|^2 with bounds lo, hi.
+__device__ __forceinline__ void lane_best_update(LaneBest& L, float m, float pp, float delta,
+                                                 int id) {
+  const float v = __builtin_fmaf(2.0f, m, pp);
+  // an all-padding chunk has v = +inf: keep lo = hi = +inf (no inf - inf)
+  const float e = fminf(0x1.0p-22f * fabsf(v) + delta, 1e38f);
+  const float lo = v - e, hi = v + e;
+  const bool better = hi < L.H;
+  const float olo = better ? L.loA : lo;
+  const int oid = better ? L.A : id;
+  const bool nb = olo < L.S;
+  L.S2 = fminf(L.S2, nb ? L.S : olo);
+  L.B = nb ? oid : L.B;
+  L.S = nb ? olo : L.S;
+  L.loA = better ? lo : L.loA;
+  L.A = better ? id : L.A;
+  L.H = fminf(L.H, hi);
+}
+
+// One cluster staged in LDS against two sources per lane; each chunk is read
+// in two halves of eight targets so that at most eight reads are in flight.
+__device__ __forceinline__ void filter_cluster_pair(const float4* __restrict__ tg, int c,
+                                                    const float (&pa)[3], const float (&pb)[3],
+                                                    float rho_c, LaneBest& La, LaneBest& Lb) {
+  const float ppa = __builtin_fmaf(pa[2], pa[2], __builtin_fmaf(pa[1], pa[1], pa[0] * pa[0]));
+  const float ppb = __builtin_fmaf(pb[2], pb[2], __builtin_fmaf(pb[1], pb[1], pb[0] * pb[0]));
+  const float ta = sqrtf(ppa) + rho_c, tb = sqrtf(ppb) + rho_c;
+  const float da = 0x1.0p-22f * 7.0f * 1.0001f * ta * ta;
+  const float db = 0x1.0p-22f * 7.0f * 1.0001f * tb * tb;
+#pragma unroll 1
+  for (int ch = 0; ch < kChunksPerCluster; ++ch) {
+    const float4* qc = tg + ch * kChunk;
+    float ma[2], mb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float a[kChunk / 2], b[kChunk / 2];
+#pragma unroll
+      for (int j = 0; j < kChunk / 2; ++j) {
+        const float4 q = qc[h * (kChunk / 2) + j];
+        a[j] = __builtin_fmaf(-pa[0], q.x, __builtin_fmaf(-pa[1], q.y, __builtin_fmaf(-pa[2], q.z, q.w)));
+        b[j] = __builtin_fmaf(-pb[0], q.x, __builtin_fmaf(-pb[1], q.y, __builtin_fmaf(-pb[2], q.z, q.w)));
+      }
+      static_assert(kChunk == 16, "the min trees below cover eight targets");
+      ma[h] = fminf(fminf(fminf(a[0], a[1]), a[2]), fminf(fminf(a[3], a[4]), a[5]));
+      ma[h] = fminf(fminf(ma[h], a[6]), a[7]);
+      mb[h] = fminf(fminf(fminf(b[0], b[1]), b[2]), fminf(fminf(b[3], b[4]), b[5]));
+      mb[h] = fminf(fminf(mb[h], b[6]), b[7]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const int id = c * kChunksPerCluster + ch;
+    lane_best_update(La, fminf(ma[0], ma[1]), ppa, da, id);
+    lane_best_update(Lb, fminf(mb[0], mb[1]), ppb, db, id);
+  }
+}
+
+__global__ __launch_bounds__(64) void nn_brute_kernel(const SlotDesc* __restrict__ descs,
+                                                      const SlotState* __restrict__ states) {
+  __shared__ float4 s_tgt[kCluster];
+  const int lane = threadIdx.x;
+  const SlotDesc& D = descs[0];
+  const SlotState& S = states[0];
+  if (S.status != ST_RUNNING || S.reuse) return;
+  const int ncl = D.ncl;
+  const int npair = (D.ntile + 1) / 2;
+  const int split = min(ncl, max(1, (kBruteItems + npair - 1) / npair));
+  const int len = (ncl + split - 1) / split;
+  const int nitems = npair * split;
+  constexpr int kRows = kCluster / 64;
+  for (int g = blockIdx.x; g < nitems; g += gridDim.x) {
+    const int pi = g / split, k = g - (g / split) * split;
+    const int c0 = k * len, c1 = min(ncl, c0 + len);
+    if (c0 >= c1) continue;
+    const int sa = 2 * pi * kTile + lane, sb = sa + kTile;
+    const bool va = sa < D.M, vb = sb < D.M;
+    const int ca = va ? sa : D.M - 1, cb = vb ? sb : D.M - 1;
+    const float xa = ldg(D.px, ca), ya = ldg(D.py, ca), za = ldg(D.pz, ca);
+    const float xb = ldg(D.px, cb), yb = ldg(D.py, cb), zb = ldg(D.pz, cb);
+    float4 r[kRows];
+#pragma unroll
+    for (int t = 0; t < kRows; ++t) r[t] = load_global(D.qloc, (size_t)c0 * kCluster + 64 * t + lane);
+    float4 cc = load_global(D.ccen, c0);
+    float ax, ay, az, Wa, bx, by, bz, Wb;
+    lane_point_from(D, S.Teval, va, xa, ya, za, -1, ax, ay, az, Wa);
+    lane_point_from(D, S.Teval, vb, xb, yb, zb, -1, bx, by, bz, Wb);
+    LaneBest La{__builtin_inff(), __builtin_inff(), __builtin_inff(), __builtin_inff(), -1, -1};
+    LaneBest Lb = La;
+    for (int c = c0; c < c1; ++c) {
+      wave_lds_sync();
+#pragma unroll
+      for (int t = 0; t < kRows; ++t) s_tgt[64 * t + lane] = r[t];
+      wave_lds_sync();
+      const float4 cur = cc;
+      if (c + 1 < c1) {
+#pragma unroll
+        for (int t = 0; t < kRows; ++t) r[t] = load_global(D.qloc, (size_t)(c + 1) * kCluster + 64 * t + lane);
+        cc = load_global(D.ccen, c + 1);
+      }
+      const float pa[3] = {ax - cur.x, ay - cur.y, az - cur.z};
+      const float pb[3] = {bx - cur.x, by - cur.y, bz - cur.z};
+      filter_cluster_pair(s_tgt, c, pa, pb, cur.w, La, Lb);
+    }
+    // resolution as in the slice kernel, for both sources of the lane
+    int nexact = 0;
+    auto resolve = [&](const LaneBest& Lx, float x, float y, float z, bool vx,
+                       unsigned long long& keyx, bool& ambx) -> bool {
+      const float thr_h = winner_threshold(Lx.H);
+      const bool has = vx && Lx.A >= 0;
+      const bool two = has && Lx.S <= thr_h;
+      ambx = two && Lx.S2 <= thr_h;
+      keyx = ~0ull;
+      if (has && !ambx) {
+        keyx = exact_scan<true>(D.qorg, Lx.A * kChunk, kChunk, x, y, z, keyx);
+        nexact += kChunk;
+        if (two) {
+          keyx = exact_scan<true>(D.qorg, Lx.B * kChunk, kChunk, x, y, z, keyx);
+          nexact += kChunk;
+        }
+      }
+      return has;
+    };
+    unsigned long long ka, kb;
+    bool amba, ambb;
+    const bool hasa = resolve(La, ax, ay, az, va, ka, amba);
+    const bool hasb = resolve(Lb, bx, by, bz, vb, kb, ambb);
+    if (__any(amba || ambb)) {
+      // near-ties: the slice's clusters again, exactly, for those lanes
+      const float tha = winner_threshold(La.H), thb = winner_threshold(Lb.H);
+      for (int c = c0; c < c1; ++c) {
+        const float4 blo = load_global(D.clo, c), bhi = load_global(D.chi, c);
+        const bool na = amba && box_lb2(ax, ay, az, blo, bhi) * (1.0f - 0x1.0p-20f) <= tha;
+        const bool nb = ambb && box_lb2(bx, by, bz, blo, bhi) * (1.0f - 0x1.0p-20f) <= thb;
+        if (!__any(na || nb)) continue;
+        wave_lds_sync();
+        for (int t = 0; t < kRows; ++t)
+          s_tgt[64 * t + lane] = load_global(D.qorg, (size_t)c * kCluster + 64 * t + lane);
+        wave_lds_sync();
+        if (na) {
+          ka = exact_scan<false>(s_tgt, 0, kCluster, ax, ay, az, ka);
+          nexact += kCluster;
+        }
+        if (nb) {
+          kb = exact_scan<false>(s_tgt, 0, kCluster, bx, by, bz, kb);
+          nexact += kCluster;
+        }
+      }
+    }
+    if (hasa) atomicMin(&D.keys[sa], ka);
+    if (hasb) atomicMin(&D.keys[sb], kb);
+    int nv = (va ? 1 : 0) + (vb ? 1 : 0);
+    int ne = nexact;
+    for (int o = 32; o > 0; o >>= 1) {
+      nv += __shfl_xor(nv, o, 64);
+      ne += __shfl_xor(ne, o, 64);
+    }
+    if (lane == 0 && D.stats) {
+      unsigned long long* st = D.stats + (blockIdx.x % kQueues) * kStatStride;
+      atomicAdd(&st[0], (unsigned long long)(c1 - c0) * kCluster * (unsigned long long)nv);
+      atomicAdd(&st[1], (unsigned long long)ne);
+    }
+  }
+}
+
+void launch_brute(const SlotDesc* descs, const SlotState* states, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(nn_brute_kernel, dim3(grid), dim3(64), 0, st, descs, states);
+}
+
 void launch_nn(const SlotDesc* descs, const SlotState* states, WorkList* wl, int grid,
                bool single, hipStream_t st) {
   hipLaunchKernelGGL(nn_cull_kernel, dim3(grid / kCullWaves), dim3(64 * kCullWaves), 0, st, descs,
