@@ -750,8 +750,12 @@ __device__ __forceinline__ void lane_best_update(LaneBest& L, float m, float pp,
   L.H = fminf(L.H, hi);
 }
 
-// One cluster staged in LDS against two sources per lane; each chunk is read
-// in two halves of eight targets so that at most eight reads are in flight.
+// One cluster staged in LDS against two sources per lane. The bookkeeping runs
+// per group of kBruteGroup targets (the rescan of a winning group covers all
+// of it), and the targets are read in runs of eight so that at most eight
+// reads are in flight.
+constexpr int kBruteGroup = 32;
+constexpr int kGroupsPerCluster = kCluster / kBruteGroup;
 __device__ __forceinline__ void filter_cluster_pair(const float4* __restrict__ tg, int c,
                                                     const float (&pa)[3], const float (&pb)[3],
                                                     float rho_c, LaneBest& La, LaneBest& Lb) {
@@ -761,28 +765,29 @@ __device__ __forceinline__ void filter_cluster_pair(const float4* __restrict__ t
   const float da = 0x1.0p-22f * 7.0f * 1.0001f * ta * ta;
   const float db = 0x1.0p-22f * 7.0f * 1.0001f * tb * tb;
 #pragma unroll 1
-  for (int ch = 0; ch < kChunksPerCluster; ++ch) {
-    const float4* qc = tg + ch * kChunk;
-    float ma[2], mb[2];
+  for (int ch = 0; ch < kGroupsPerCluster; ++ch) {
+    const float4* qc = tg + ch * kBruteGroup;
+    constexpr int kRuns = kBruteGroup / 8;
+    float ma[kRuns], mb[kRuns];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      float a[kChunk / 2], b[kChunk / 2];
+    for (int h = 0; h < kRuns; ++h) {
+      float a[8], b[8];
 #pragma unroll
-      for (int j = 0; j < kChunk / 2; ++j) {
-        const float4 q = qc[h * (kChunk / 2) + j];
+      for (int j = 0; j < 8; ++j) {
+        const float4 q = qc[h * 8 + j];
         a[j] = __builtin_fmaf(-pa[0], q.x, __builtin_fmaf(-pa[1], q.y, __builtin_fmaf(-pa[2], q.z, q.w)));
         b[j] = __builtin_fmaf(-pb[0], q.x, __builtin_fmaf(-pb[1], q.y, __builtin_fmaf(-pb[2], q.z, q.w)));
       }
-      static_assert(kChunk == 16, "the min trees below cover eight targets");
       ma[h] = fminf(fminf(fminf(a[0], a[1]), a[2]), fminf(fminf(a[3], a[4]), a[5]));
       ma[h] = fminf(fminf(ma[h], a[6]), a[7]);
       mb[h] = fminf(fminf(fminf(b[0], b[1]), b[2]), fminf(fminf(b[3], b[4]), b[5]));
       mb[h] = fminf(fminf(mb[h], b[6]), b[7]);
       __builtin_amdgcn_sched_barrier(0);
     }
-    const int id = c * kChunksPerCluster + ch;
-    lane_best_update(La, fminf(ma[0], ma[1]), ppa, da, id);
-    lane_best_update(Lb, fminf(mb[0], mb[1]), ppb, db, id);
+    static_assert(kBruteGroup == 32, "the group minimum below combines four runs");
+    const int id = c * kGroupsPerCluster + ch;
+    lane_best_update(La, fminf(fminf(ma[0], ma[1]), fminf(ma[2], ma[3])), ppa, da, id);
+    lane_best_update(Lb, fminf(fminf(mb[0], mb[1]), fminf(mb[2], mb[3])), ppb, db, id);
   }
 }
 
@@ -842,11 +847,11 @@ __global__ __launch_bounds__(64) void nn_brute_kernel(const SlotDesc* __restrict
       ambx = two && Lx.S2 <= thr_h;
       keyx = ~0ull;
       if (has && !ambx) {
-        keyx = exact_scan<true>(D.qorg, Lx.A * kChunk, kChunk, x, y, z, keyx);
-        nexact += kChunk;
+        keyx = exact_scan<true>(D.qorg, Lx.A * kBruteGroup, kBruteGroup, x, y, z, keyx);
+        nexact += kBruteGroup;
         if (two) {
-          keyx = exact_scan<true>(D.qorg, Lx.B * kChunk, kChunk, x, y, z, keyx);
-          nexact += kChunk;
+          keyx = exact_scan<true>(D.qorg, Lx.B * kBruteGroup, kBruteGroup, x, y, z, keyx);
+          nexact += kBruteGroup;
         }
       }
       return has;
