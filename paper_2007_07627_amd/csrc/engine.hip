@@ -40,8 +40,8 @@ void launch_plan(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t)
 void launch_aos_to_soa(const float*, int, float*, float*, float*, hipStream_t);
 void launch_bbox(const float*, const float*, const float*, int, float*, double*, hipStream_t);
 size_t sort_scratch_words(int);
-void launch_morton_order(const float*, const float*, const float*, int, const float*, unsigned*,
-                         unsigned**, hipStream_t);
+void launch_hilbert_order(const float*, const float*, const float*, int, const float*, unsigned*,
+                          unsigned**, hipStream_t);
 void launch_build_clusters(const float*, const float*, const float*, const unsigned*, int, int,
                            float4*, float4*, float4*, float4*, float4*, float4*, hipStream_t);
 void launch_build_super(const float4*, const float4*, const float4*, int, int, float4*, float4*,
@@ -180,6 +180,11 @@ struct HostSlot {
   Clock::time_point t_submit;
   int32_t* user_idx = nullptr;  // host outputs of a query (copied at harvest)
   float* user_d2 = nullptr;
+  // host sources of the admission's asynchronous uploads (they must outlive
+  // the copies, which may still be in flight when admit returns)
+  SlotState S0;
+  SlotDesc D0;
+  int zero = 0;
 };
 
 // ------------------------------------------------------------------ requests
@@ -393,8 +398,10 @@ struct Engine {
   }
 
   // Device-side setup of slot `s` for request r on the side stream. Returns
-  // false on a HIP error; OOM is reported through *oom.
-  bool admit(int s, const OwnedRequest& r, bool* oom) {
+  // false on a HIP error; OOM is reported through *oom. Without `sync` the
+  // setup may still be running on return: r's host arrays must then stay
+  // alive until the side stream (or a stream waiting on it) has drained.
+  bool admit(int s, const OwnedRequest& r, bool* oom, bool sync = true) {
     *oom = false;
     (void)hipGetLastError();  // launch errors below are checked against a clean slate
     HostSlot& h = hs[s];
@@ -419,7 +426,7 @@ struct Engine {
     double* cP = reinterpret_cast<double*>(st_base + offsetof(SlotState, cP));
     float* rho = reinterpret_cast<float*>(reinterpret_cast<char*>(d_desc + s) + offsetof(SlotDesc, rho_max));
     // state first (kernels below write some of its fields)
-    SlotState S;
+    SlotState& S = h.S0;
     std::memset(&S, 0, sizeof S);
     S.status = ST_SETUP;
     S.mode = r.query ? P2P_L2 : (int)r.prm.mode;
@@ -456,7 +463,7 @@ struct Engine {
     // target cluster index
     launch_bbox(F(L.o_qx), F(L.o_qy), F(L.o_qz), L.N, bbQ, cQ, ss);
     unsigned* order = nullptr;
-    launch_morton_order(F(L.o_qx), F(L.o_qy), F(L.o_qz), L.N, bbQ, scratch, &order, ss);
+    launch_hilbert_order(F(L.o_qx), F(L.o_qy), F(L.o_qz), L.N, bbQ, scratch, &order, ss);
     launch_build_clusters(F(L.o_qx), F(L.o_qy), F(L.o_qz), order, L.N, L.ncl, F4(L.o_qloc),
                           F4(L.o_qorg), F4(L.o_ccen), F4(L.o_clo), F4(L.o_chi), F4(L.o_kbox), ss);
     launch_build_super(F4(L.o_clo), F4(L.o_chi), F4(L.o_ccen), L.ncl, L.nsup, F4(L.o_slo),
@@ -473,7 +480,7 @@ struct Engine {
     }
     // source tiles
     launch_bbox(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, cP, ss);
-    launch_morton_order(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, scratch, &order, ss);
+    launch_hilbert_order(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, scratch, &order, ss);
     launch_build_tiles(F(L.o_pox), F(L.o_poy), F(L.o_poz), order, L.M, L.ntile, F(L.o_px),
                        F(L.o_py), F(L.o_pz), reinterpret_cast<int*>(b + L.o_perm),
                        reinterpret_cast<double4*>(b + L.o_tsph), ss);
@@ -482,7 +489,7 @@ struct Engine {
     // no previous closest point yet (int32 -1 everywhere)
     launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_nnidx), (L.M + 1) / 2, ~0ull, ss);
     // descriptor (rho_max is written by build_super above, so copy the rest around it)
-    SlotDesc D;
+    SlotDesc& D = h.D0;
     std::memset(&D, 0, sizeof D);
     D.px = F(L.o_px); D.py = F(L.o_py); D.pz = F(L.o_pz);
     D.perm = reinterpret_cast<int*>(b + L.o_perm);
@@ -520,11 +527,10 @@ struct Engine {
     split = std::min(split, std::min(kMaxSplit, L.ncl));
     D.split = std::max(1, split);
     HIP_OK(hipMemcpyAsync(d_desc + s, &D, offsetof(SlotDesc, rho_max), hipMemcpyHostToDevice, ss));
-    const int zero = 0;
-    HIP_OK(hipMemcpyAsync(d_done + s, &zero, sizeof(int), hipMemcpyHostToDevice, ss));
+    h.zero = 0;
+    HIP_OK(hipMemcpyAsync(d_done + s, &h.zero, sizeof(int), hipMemcpyHostToDevice, ss));
     h_done[s] = 0;
-    // host sources of the async copies above live in this frame / the request
-    HIP_OK(hipStreamSynchronize(ss));
+    if (sync) HIP_OK(hipStreamSynchronize(ss));
     return hipGetLastError() == hipSuccess;
   }
 
@@ -753,6 +759,10 @@ static icp_status run_sync(icp_ctx* ctx, OwnedRequest& r, icp_result* out, void*
 static void scheduler(icp_ctx* ctx) {
   Engine& E = ctx->batch_eng;
   (void)hipSetDevice(ctx->device);
+  // requests admitted in this round whose host arrays may still be read by
+  // uploads in flight; released once the pass stream (which waits on every
+  // activation) has been synchronised
+  std::vector<std::unique_ptr<OwnedRequest>> held;
   for (;;) {
     int R, running;
     {
@@ -774,7 +784,10 @@ static void scheduler(icp_ctx* ctx) {
       }
     }
     // 2) meanwhile set up queued requests on the side stream (FIFO; a request
-    //    that does not fit waits for memory unless nothing else is resident)
+    //    that does not fit waits for memory unless nothing else is resident).
+    //    The uploads and setup kernels are only enqueued here; the
+    //    synchronisation in 3) covers them, since the pass stream waits on
+    //    every activation.
     for (; ok;) {
       std::unique_ptr<OwnedRequest> req;
       int s;
@@ -787,7 +800,7 @@ static void scheduler(icp_ctx* ctx) {
         ctx->queue.pop_front();
       }
       bool oom = false;
-      const bool adm = E.admit(s, *req, &oom);
+      const bool adm = E.admit(s, *req, &oom, false);
       if (adm && oom) {
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (ctx->running == 0) {
@@ -798,14 +811,16 @@ static void scheduler(icp_ctx* ctx) {
         break;
       }
       if (!adm || !E.activate(s)) {
+        (void)hipStreamSynchronize(E.side);
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->state[req->ticket] = 4;
         E.release(s);
         ok = false;
         break;
       }
+      held.push_back(std::move(req));
       std::lock_guard<std::mutex> lk(ctx->mu);
-      ctx->state[req->ticket] = 1;
+      ctx->state[held.back()->ticket] = 1;
       ctx->running++;
     }
     // 3) completion flags after the replay (and after the boots of new slots)
@@ -813,8 +828,10 @@ static void scheduler(icp_ctx* ctx) {
       ok = hipMemcpyAsync(E.h_done, E.d_done, sizeof(int) * E.capacity, hipMemcpyDeviceToHost, E.st) ==
                hipSuccess &&
            hipStreamSynchronize(E.st) == hipSuccess;
+    if (ok) held.clear();
     if (ok && running > 0) E.collect_profile(R);
     if (!ok) {
+      (void)hipStreamSynchronize(E.side);
       std::lock_guard<std::mutex> lk(ctx->mu);
       ctx->failed = true;
       ctx->stop = true;

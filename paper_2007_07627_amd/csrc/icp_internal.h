@@ -64,7 +64,7 @@ constexpr int kP2PLVals = 29;
 
 // Static description of a slot (written once at admission).
 struct SlotDesc {
-  // sources, Morton-ordered SoA (original FP32 values)
+  // sources, Hilbert-ordered SoA (original FP32 values)
   const float* px;
   const float* py;
   const float* pz;
@@ -77,7 +77,7 @@ struct SlotDesc {
   const float* nx;
   const float* ny;
   const float* nz;
-  // cluster index (Morton order, kCluster targets per cluster, padded)
+  // cluster index (Hilbert order, kCluster targets per cluster, padded)
   const float4* qloc;         // (x - cc, y - cc, z - cc, |q - cc|^2 / 2), padding h = +inf
   const float4* qorg;         // (x, y, z, bits(original index)), padding index = -1
   const float4* ccen;         // cluster centre (x, y, z) and radius

@@ -8,24 +8,29 @@
 // target index. The key (bits(d2) << 32 | index) orders exactly that way.
 //
 // How it is computed fast without changing that result:
-//  * Targets are kept in clusters of 128 Morton-ordered points, stored relative
+//  * Targets are kept in clusters of 128 Hilbert-ordered points, stored relative
 //    to the cluster centre cc together with h = |q - cc|^2 / 2. For a source,
 //    the filter value 2 (h - (p' - cc) . (q - cc)) + |p' - cc|^2 equals the
 //    squared distance up to a rounding error that is bounded per cluster; it
-//    costs 3 FMA per pair (v_fma_f32) and one v_min3_f32 per two pairs.
-//  * Only the minimum filter value of each 32-target chunk is kept (with the
-//    runner-up chunk value via v_med3_f32). At the end the winning chunk is
-//    rescanned with the exact FP32 definition. If another chunk comes within
-//    the error bound of the winner, every candidate is rescanned exactly.
+//    costs 3 FMA per pair and a share of a min tree.
+//  * Per lane only the minimum filter value of each 16-target chunk is kept,
+//    as certified bounds: the chunk with the smallest upper bound and the
+//    smallest lower bounds among the others. At the end the winning chunk is
+//    rescanned with the exact FP32 definition; a second chunk that comes
+//    within the error bound of the winner is rescanned too, and with a third
+//    every cluster the lane can still need is rescanned exactly.
 //  * Cluster culling (method NN_CLUSTER): a bounding sphere of the 64-source
 //    tile, transformed per pass, against super-cluster and cluster AABBs gives
 //    a candidate list; per lane, a cluster whose AABB distance exceeds the
-//    current best by more than the error bound is skipped wave-uniformly.
-//  * Two kernels: the cull kernel (one wavefront per 64-source tile) builds
-//    the tile's candidate list and appends slices of it to a per-pair queue;
-//    the slice kernel (persistent, dynamic) filters one slice and merges its
-//    exact result into the key with a 64-bit atomic min (order independent),
-//    so tiles with many candidates (outliers) spread over many wavefronts.
+//    current best by more than the error bound is skipped wave-uniformly, and
+//    inside a cluster the chunks whose boxes no lane can need are skipped.
+//  * Two kernels per pass: the cull kernel (one 64-source tile per wavefront)
+//    builds the tile's candidate list and appends slices of it to a per-pair
+//    queue; the slice kernel (persistent, dynamic) filters one slice and
+//    merges its exact result into the key with a 64-bit atomic min (order
+//    independent), so tiles with many candidates (outliers) spread over many
+//    wavefronts. A third kernel runs the exhaustive method of a single
+//    resident pair: two tiles per wavefront over static ranges of clusters.
 //  * Warm start: the previous pass's closest target bounds each lane's exact
 //    minimum before any cluster is read; the candidate list keeps only the
 //    clusters some lane of the tile can still need.
@@ -105,10 +110,6 @@ __device__ __forceinline__ float box_ub2(float px, float py, float pz, float4 lo
   return dx * dx + dy * dy + dz * dz;
 }
 
-// Per lane, over the chunks run through the filter: H = min over chunks of a
-// certified upper bound on the exact squared distance of the chunk's best
-// target, A = the chunk attaining H, loA = that chunk's certified lower bound,
-// S = min certified lower bound over all other chunks.
 // Per-lane filter state over the chunks seen so far: A is the chunk with the
 // smallest upper bound H (its lower bound loA); B is the chunk with the
 // smallest lower bound S among the others, and S2 the smallest lower bound

@@ -1,5 +1,5 @@
 // Per-request setup on the device (once per registration, before the
-// iterations): layout conversion, bounding boxes, Morton ordering of both point
+// iterations): layout conversion, bounding boxes, Hilbert ordering of both point
 // sets with a stable LSD radix sort, the cluster index over the target
 // (cluster AABBs, centres, radii, centred coordinates) and bounding spheres of
 // the 64-source tiles. Also the planner that rebuilds the active work lists
@@ -29,9 +29,20 @@ __global__ __launch_bounds__(1024) void bbox_kernel(const float* __restrict__ x,
                                                     double* __restrict__ centre) {
   float mn[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
   float mx[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const float v[3] = {x[i], y[i], z[i]};
-    for (int a = 0; a < 3; ++a) { mn[a] = fminf(mn[a], v[a]); mx[a] = fmaxf(mx[a], v[a]); }
+  // eight strides' loads in flight at once; folded in index order
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * 1024) {
+    float v[8][3];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + 1024 * u;
+      v[u][0] = i < n ? x[i] : __builtin_inff();
+      v[u][1] = i < n ? y[i] : __builtin_inff();
+      v[u][2] = i < n ? z[i] : __builtin_inff();
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + 1024 * u < n)
+        for (int a = 0; a < 3; ++a) { mn[a] = fminf(mn[a], v[u][a]); mx[a] = fmaxf(mx[a], v[u][a]); }
   }
   __shared__ float s[6][16];
   for (int a = 0; a < 3; ++a) {
@@ -65,10 +76,10 @@ __device__ inline unsigned spread10(unsigned v) {
   return v;
 }
 
-// 30-bit Morton key of the 1024^3 grid over the bounding box; value = index.
-__global__ void morton_kernel(const float* __restrict__ x, const float* __restrict__ y,
-                              const float* __restrict__ z, int n, const float* __restrict__ box,
-                              unsigned* __restrict__ keys, unsigned* __restrict__ vals) {
+// 30-bit Hilbert key of the cell of the 1024^3 grid over the bounding box; value = index.
+__global__ void hilbert_kernel(const float* __restrict__ x, const float* __restrict__ y,
+                               const float* __restrict__ z, int n, const float* __restrict__ box,
+                               unsigned* __restrict__ keys, unsigned* __restrict__ vals) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float v[3] = {x[i], y[i], z[i]};
@@ -112,49 +123,96 @@ __global__ void morton_kernel(const float* __restrict__ x, const float* __restri
 
 // ------------------------------------------------------------------ radix sort
 // Stable LSD sort of (32-bit key, 32-bit value) pairs, 8 bits per pass. Each
-// block (one wavefront) owns a contiguous chunk of kSortChunk elements and
-// ranks them in order, 64 at a time, so equal keys keep their input order.
+// block (one wavefront) owns a contiguous chunk of kSortChunk elements, loads
+// all of it at once (kSortPer elements per lane) and ranks it in order, 64 at
+// a time, so equal keys keep their input order. Only LDS is shared inside a
+// block, so a wavefront fence orders it (no wait on the loads or stores).
 
-constexpr int kSortChunk = 2048;
+constexpr int kSortPer = 16;
+constexpr int kSortChunk = 64 * kSortPer;
 
 __global__ __launch_bounds__(64) void rs_hist_kernel(const unsigned* __restrict__ keys, int n,
                                                      int shift, int nblocks,
                                                      unsigned* __restrict__ hist) {
   __shared__ unsigned h[256];
-  for (int i = threadIdx.x; i < 256; i += 64) h[i] = 0u;
-  __syncthreads();
-  const int base = blockIdx.x * kSortChunk;
-  for (int s = 0; s < kSortChunk; s += 64) {
-    const int e = base + s + threadIdx.x;
-    if (e < n) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+  const int lane = threadIdx.x;
+  const int base = blockIdx.x * kSortChunk + lane;
+  unsigned d[kSortPer];
+#pragma unroll
+  for (int s = 0; s < kSortPer; ++s) {
+    const int e = base + 64 * s;
+    d[s] = e < n ? (ldg(keys, e) >> shift) & 255u : 256u;
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 256; i += 64) hist[(size_t)i * nblocks + blockIdx.x] = h[i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) h[lane + 64 * i] = 0u;
+  wave_lds_sync();
+#pragma unroll
+  for (int s = 0; s < kSortPer; ++s)
+    if (d[s] < 256u) atomicAdd(&h[d[s]], 1u);
+  wave_lds_sync();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) hist[(size_t)(lane + 64 * i) * nblocks + blockIdx.x] = h[lane + 64 * i];
 }
 
-// Exclusive scan of the digit-major histogram (single block of 1024 threads).
-__global__ __launch_bounds__(1024) void rs_scan_kernel(unsigned* __restrict__ hist, int total) {
-  __shared__ unsigned s[1024];
-  const int per = (total + 1023) / 1024;
-  const int b = threadIdx.x * per;
-  unsigned sum = 0;
-  for (int i = 0; i < per; ++i)
-    if (b + i < total) sum += hist[b + i];
-  s[threadIdx.x] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const unsigned v = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
-    __syncthreads();
-    s[threadIdx.x] += v;
-    __syncthreads();
+// Exclusive scan of the digit-major histogram hist[digit * nb + block]: the
+// offset of (digit, block) is the count of all smaller digits plus that of
+// the digit in earlier blocks. One block of 16 wavefronts, 16 digits per
+// wavefront; each pass over 64 blocks loads the 16 digits' rows at once.
+__global__ __launch_bounds__(1024) void rs_scan_kernel(unsigned* __restrict__ hist, int nb) {
+  constexpr int kDig = 16;
+  __shared__ unsigned s_tot[256];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned* row = hist + (size_t)wv * kDig * nb;
+  unsigned sum[kDig];
+#pragma unroll
+  for (int j = 0; j < kDig; ++j) sum[j] = 0u;
+  for (int b = lane; b < nb; b += 64) {
+#pragma unroll
+    for (int j = 0; j < kDig; ++j) sum[j] += row[(size_t)j * nb + b];
   }
-  unsigned run = s[threadIdx.x] - sum;
-  for (int i = 0; i < per; ++i)
-    if (b + i < total) {
-      const unsigned v = hist[b + i];
-      hist[b + i] = run;
-      run += v;
+#pragma unroll
+  for (int j = 0; j < kDig; ++j) {
+    unsigned v = sum[j];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) s_tot[wv * kDig + j] = v;
+  }
+  __syncthreads();
+  // exclusive scan of the 256 digit totals by wavefront 0 (four per lane)
+  if (wv == 0) {
+    const unsigned t0 = s_tot[4 * lane], t1 = s_tot[4 * lane + 1], t2 = s_tot[4 * lane + 2],
+                   t3 = s_tot[4 * lane + 3];
+    const unsigned own = t0 + t1 + t2 + t3;
+    unsigned inc = own;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned u = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += u;
     }
+    const unsigned ex = inc - own;
+    s_tot[4 * lane] = ex;
+    s_tot[4 * lane + 1] = ex + t0;
+    s_tot[4 * lane + 2] = ex + t0 + t1;
+    s_tot[4 * lane + 3] = ex + t0 + t1 + t2;
+  }
+  __syncthreads();
+  unsigned carry[kDig];
+#pragma unroll
+  for (int j = 0; j < kDig; ++j) carry[j] = s_tot[wv * kDig + j];
+  for (int b0 = 0; b0 < nb; b0 += 64) {
+    const int b = b0 + lane;
+    unsigned v[kDig];
+#pragma unroll
+    for (int j = 0; j < kDig; ++j) v[j] = b < nb ? row[(size_t)j * nb + b] : 0u;
+#pragma unroll
+    for (int j = 0; j < kDig; ++j) {
+      unsigned inc = v[j];
+      for (int o = 1; o < 64; o <<= 1) {
+        const unsigned u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+      }
+      if (b < nb) row[(size_t)j * nb + b] = carry[j] + inc - v[j];
+      carry[j] += __shfl(inc, 63, 64);
+    }
+  }
 }
 
 __global__ __launch_bounds__(64) void rs_scatter_kernel(const unsigned* __restrict__ kin,
@@ -164,35 +222,38 @@ __global__ __launch_bounds__(64) void rs_scatter_kernel(const unsigned* __restri
                                                         unsigned* __restrict__ kout,
                                                         unsigned* __restrict__ vout) {
   __shared__ unsigned cnt[256];
-  for (int i = threadIdx.x; i < 256; i += 64) cnt[i] = hist[(size_t)i * nblocks + blockIdx.x];
-  __syncthreads();
   const int lane = threadIdx.x;
+  const int base = blockIdx.x * kSortChunk + lane;
+  unsigned kk[kSortPer], vv[kSortPer];
+#pragma unroll
+  for (int s = 0; s < kSortPer; ++s) {
+    const int e = base + 64 * s;
+    kk[s] = e < n ? ldg(kin, e) : 0u;
+    vv[s] = e < n ? ldg(vin, e) : 0u;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) cnt[lane + 64 * i] = ldg(hist, (size_t)(lane + 64 * i) * nblocks + blockIdx.x);
+  wave_lds_sync();
   const unsigned long long lt = (1ull << lane) - 1ull;
-  const int base = blockIdx.x * kSortChunk;
-  for (int s = 0; s < kSortChunk; s += 64) {
-    const int e = base + s + lane;
-    const bool valid = e < n;
-    unsigned k = 0, v = 0, d = 0;
-    if (valid) {
-      k = kin[e];
-      v = vin[e];
-      d = (k >> shift) & 255u;
-    }
+#pragma unroll
+  for (int s = 0; s < kSortPer; ++s) {
+    const bool valid = base + 64 * s < n;
+    const unsigned d = (kk[s] >> shift) & 255u;
     unsigned long long m = __ballot(valid);
+#pragma unroll
     for (int b = 0; b < 8; ++b) {
       const bool bit = (d >> b) & 1u;
       const unsigned long long bb = __ballot(valid && bit);
       m &= bit ? bb : ~bb;
     }
     const unsigned rank = (unsigned)__popcll(m & lt);
-    unsigned pos = 0;
-    if (valid) pos = cnt[d] + rank;
-    __syncthreads();
+    const unsigned pos = cnt[d] + rank;
+    wave_lds_sync();
     if (valid && rank == 0) cnt[d] += (unsigned)__popcll(m);
-    __syncthreads();
+    wave_lds_sync();
     if (valid) {
-      kout[pos] = k;
-      vout[pos] = v;
+      kout[pos] = kk[s];
+      vout[pos] = vv[s];
     }
   }
 }
@@ -429,21 +490,21 @@ size_t sort_scratch_words(int n) {
   return (size_t)4 * n + (size_t)256 * nb + 64;
 }
 
-// Morton order of n points: returns (through out_vals) the permutation sorted
+// Hilbert order of n points: returns (through out_vals) the permutation sorted
 // by (cell key, original index). scratch: sort_scratch_words(n) unsigned words.
-void launch_morton_order(const float* x, const float* y, const float* z, int n, const float* box,
-                         unsigned* scratch, unsigned** out_vals, hipStream_t st) {
+void launch_hilbert_order(const float* x, const float* y, const float* z, int n, const float* box,
+                          unsigned* scratch, unsigned** out_vals, hipStream_t st) {
   unsigned* ka = scratch;
   unsigned* va = ka + n;
   unsigned* kb = va + n;
   unsigned* vb = kb + n;
   unsigned* hist = vb + n;
   const int nb = cdiv(n, kSortChunk);
-  hipLaunchKernelGGL(morton_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, x, y, z, n, box, ka, va);
+  hipLaunchKernelGGL(hilbert_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, x, y, z, n, box, ka, va);
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 8 * pass;
     hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(64), 0, st, ka, n, shift, nb, hist);
-    hipLaunchKernelGGL(rs_scan_kernel, dim3(1), dim3(1024), 0, st, hist, 256 * nb);
+    hipLaunchKernelGGL(rs_scan_kernel, dim3(1), dim3(1024), 0, st, hist, nb);
     hipLaunchKernelGGL(rs_scatter_kernel, dim3(nb), dim3(64), 0, st, ka, va, n, shift, nb, hist, kb,
                        vb);
     unsigned* t = ka; ka = kb; kb = t;
