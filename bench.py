@@ -199,6 +199,7 @@ def batch_bench(args):
     log("batched run")
     t0 = time.perf_counter()
     tickets = B.icp_batch_submit(ctx, reqs)
+    t_sub = time.perf_counter() - t0
     res = _wait_tickets(B, ctx, tickets)
     wall = time.perf_counter() - t0
     log(f"batched: {count} registrations in {wall:.2f} s; plain loop")
@@ -226,6 +227,7 @@ def batch_bench(args):
                                "robust p2p / p2pl by seeded coin", "sum_M": M, "sum_N": N,
                    "passes_per_replay": args.passes_per_replay},
         "nn_queries_per_s": queries / wall,
+        "submit_ms": t_sub * 1e3,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "plain_loop": {"value": count / wall_p, "unit": "registrations/s",
                        "nn_queries_per_s": queries / wall_p},

@@ -223,18 +223,22 @@ icp_status icp_nu_min_auto(icp_ctx *ctx, const float *Q, const float *Qn, int64_
  * Q: host AoS N x 3 FP32, N >= 30; normals_out: host N x 3 FP32. Synchronous. */
 icp_status icp_estimate_normals(icp_ctx *ctx, const float *Q, int64_t N, float *normals_out);
 
-/* Batched / served registration. Each request is validated and its arrays are
- * copied to pinned staging before the call returns (the caller may free them
- * at once); tickets_out[i] receives a unique ticket. A background scheduler
- * admits queued requests when a slot and enough HBM are free, advances all
- * admitted pairs together (one pass per captured graph node group) and
- * retires them as they finish, so requests that arrive while others run join
- * in flight. On the first invalid request nothing is queued and its status is
- * returned. */
+/* Batched / served registration. Every request is validated first; on the
+ * first invalid one nothing is queued and its status is returned. Then the
+ * tickets are issued (tickets_out[i] receives a unique ticket) and each
+ * request's arrays are copied into host memory the library owns and queued in
+ * turn, all before the call returns (the caller may free its arrays at once).
+ * A background scheduler admits queued requests when a slot and enough HBM
+ * are free, advances all admitted pairs together (one pass per captured graph
+ * node group) and retires them as they finish, so requests that arrive while
+ * others run join in flight, and the first requests of a large submission
+ * start while the later ones are being copied. */
 icp_status icp_batch_submit(icp_ctx *ctx, const icp_request *reqs, int n, uint64_t *tickets_out);
 
 /* ICP_OK and the result (handed out exactly once), ICP_ERR_NOT_READY while
- * pending, ICP_ERR_UNKNOWN_TICKET otherwise. */
+ * pending, ICP_ERR_OOM (once) for a request that can never fit the HBM budget
+ * or whose host copy could not be allocated, ICP_ERR_DEVICE after a HIP
+ * failure of the scheduler, ICP_ERR_UNKNOWN_TICKET otherwise. */
 icp_status icp_poll(icp_ctx *ctx, uint64_t ticket, icp_result *out);
 
 /* Block until every submitted request has finished (results stay pollable). */

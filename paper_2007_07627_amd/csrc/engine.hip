@@ -15,6 +15,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -582,6 +583,7 @@ struct icp_ctx {
   bool started = false;
   bool failed = false;
   uint64_t next_ticket = 1;
+  size_t reserved = 0;  // tickets handed out whose requests are still being copied
   int passes_per_replay = 4;
   int max_slots = 256;
   int running = 0;
@@ -589,13 +591,47 @@ struct icp_ctx {
 };
 
 static const size_t kQueueCap = 1 << 20;
+static const unsigned kSubmitThreads = 8;  // host threads of a large icp_batch_submit
 
+// Every coordinate finite with |v| <= 1e15. On the bit patterns: |v| > 1e15f,
+// Inf and NaN are exactly the magnitudes above that of 1e15f (0x58635fa9),
+// tested branch-free over blocks so that the loop vectorises.
 static bool finite_coords(const float* p, int64_t n) {
-  for (int64_t i = 0; i < 3 * n; ++i) {
-    const float v = p[i];
-    if (!std::isfinite(v) || std::fabs(v) > 1e15f) return false;
+  const int64_t m = 3 * n;
+  for (int64_t i0 = 0; i0 < m; i0 += 4096) {
+    const int64_t e = std::min<int64_t>(i0 + 4096, m);
+    unsigned bad = 0;
+    for (int64_t i = i0; i < e; ++i) {
+      uint32_t b;
+      std::memcpy(&b, p + i, 4);
+      bad |= (b & 0x7fffffffu) > 0x58635fa9u;
+    }
+    if (bad) return false;
   }
   return true;
+}
+
+// fn(i) for i in [0, n) on up to `threads` threads (thread k takes k, k + T, ...).
+template <class Fn>
+static void parallel_items(int n, int threads, Fn fn) {
+  const int T = std::max(1, std::min(threads, n));
+  if (T == 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  int started = 1;
+  try {
+    th.reserve(T - 1);
+    for (int k = 1; k < T; ++k, ++started)
+      th.emplace_back([&fn, n, T, k] { for (int i = k; i < n; i += T) fn(i); });
+  } catch (...) {
+  }
+  // the calling thread takes its own share and that of any thread that did not start
+  for (int k = 0; k < T; ++k)
+    if (k == 0 || k >= started)
+      for (int i = k; i < n; i += T) fn(i);
+  for (auto& t : th) t.join();
 }
 
 static bool rigid_ok(const double* T) {
@@ -1194,40 +1230,68 @@ icp_status icp_batch_config(icp_ctx* ctx, int passes_per_replay, int max_slots) 
 
 icp_status icp_batch_submit(icp_ctx* ctx, const icp_request* reqs, int n, uint64_t* tickets_out) {
   if (!ctx || n < 0 || (n > 0 && (!reqs || !tickets_out))) return ICP_ERR_INVALID_ARG;
-  for (int i = 0; i < n; ++i) {
-    const icp_request& q = reqs[i];
-    const icp_status v = validate_host(q.P, q.M, q.Q, q.Qn, q.N, &q.params);
-    if (v != ICP_OK) return v;
+  // host threads for validating and copying a large submission
+  int64_t points = 0;
+  for (int i = 0; i < n; ++i) points += std::max<int64_t>(reqs[i].M, 0) + std::max<int64_t>(reqs[i].N, 0);
+  const int threads = points >= (int64_t)1 << 20
+                          ? (int)std::min<unsigned>(kSubmitThreads, std::max(1u, std::thread::hardware_concurrency()))
+                          : 1;
+  {
+    std::vector<icp_status> v(n, ICP_OK);
+    parallel_items(n, threads, [&](int i) {
+      const icp_request& q = reqs[i];
+      v[i] = validate_host(q.P, q.M, q.Q, q.Qn, q.N, &q.params);
+    });
+    for (int i = 0; i < n; ++i)
+      if (v[i] != ICP_OK) return v[i];
   }
-  std::vector<std::unique_ptr<OwnedRequest>> owned;
-  owned.reserve(n);
   const auto now = Clock::now();
-  for (int i = 0; i < n; ++i) {
-    const icp_request& q = reqs[i];
-    auto r = std::make_unique<OwnedRequest>();
-    r->P.assign(q.P, q.P + 3 * q.M);
-    r->Q.assign(q.Q, q.Q + 3 * q.N);
-    if (mode_plane(q.params.mode)) r->Qn.assign(q.Qn, q.Qn + 3 * q.N);
-    r->M = q.M; r->N = q.N; r->prm = q.params;
-    r->t_submit = now;
-    owned.push_back(std::move(r));
-  }
+  uint64_t first;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (ctx->failed) return ICP_ERR_DEVICE;
-    if (ctx->queue.size() + n > kQueueCap) return ICP_ERR_QUEUE_FULL;
+    if (ctx->queue.size() + ctx->reserved + n > kQueueCap) return ICP_ERR_QUEUE_FULL;
+    first = ctx->next_ticket;
+    ctx->next_ticket += (uint64_t)n;
+    ctx->reserved += (size_t)n;
     for (int i = 0; i < n; ++i) {
-      owned[i]->ticket = ctx->next_ticket++;
-      tickets_out[i] = owned[i]->ticket;
-      ctx->state[owned[i]->ticket] = 0;
-      ctx->queue.push_back(std::move(owned[i]));
+      tickets_out[i] = first + (uint64_t)i;
+      ctx->state[tickets_out[i]] = 0;
     }
-    if (!ctx->started) {
+    if (!ctx->started && n > 0) {
       ctx->started = true;
       ctx->worker = std::thread(scheduler, ctx);
     }
   }
-  ctx->cv.notify_all();
+  // Copy and queue one request at a time: the scheduler sets up and advances
+  // the first requests while the later ones are still being copied. A
+  // request whose host copy cannot be allocated is reported as ICP_ERR_OOM
+  // by icp_poll.
+  parallel_items(n, threads, [&](int i) {
+    const icp_request& q = reqs[i];
+    std::unique_ptr<OwnedRequest> r;
+    try {
+      r = std::make_unique<OwnedRequest>();
+      r->P.assign(q.P, q.P + 3 * q.M);
+      r->Q.assign(q.Q, q.Q + 3 * q.N);
+      if (mode_plane(q.params.mode)) r->Qn.assign(q.Qn, q.Qn + 3 * q.N);
+    } catch (const std::bad_alloc&) {
+      r.reset();
+    }
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->reserved--;
+      if (!r) {
+        ctx->state[tickets_out[i]] = 3;
+        return;
+      }
+      r->M = q.M; r->N = q.N; r->prm = q.params;
+      r->t_submit = now;
+      r->ticket = tickets_out[i];
+      ctx->queue.push_back(std::move(r));
+    }
+    ctx->cv.notify_all();
+  });
   return ICP_OK;
 }
 

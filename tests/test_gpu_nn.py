@@ -82,6 +82,17 @@ def test_nn_empty_and_invalid(ctx):
     P[2, 1] = np.nan
     rc, _, _ = B.icp_nn_query(ctx, P, Q, raw=True)
     assert rc == B.ICP_ERR_NONFINITE
+    # coordinates are accepted up to |v| <= 1e15 (as FP32), anywhere in the array
+    for bad in (np.float32(2e15), np.float32(-2e15), np.float32(-np.inf), np.float32(np.nan)):
+        Pb = np.zeros((5000, 3), np.float32)
+        Pb[-1, 2] = bad
+        rc, _, _ = B.icp_nn_query(ctx, Pb, Q, raw=True)
+        assert rc == B.ICP_ERR_NONFINITE, bad
+    Pl = np.zeros((5000, 3), np.float32)
+    Pl[-1, 2] = np.float32(-1e15)
+    Pl[4095 // 3, 4095 % 3] = np.float32(1e15)
+    rc, _, _ = B.icp_nn_query(ctx, Pl, Q, raw=True)
+    assert rc == B.ICP_OK
     T = np.eye(4)
     T[0, 0] = 1.1
     rc, _, _ = B.icp_nn_query(ctx, np.zeros((5, 3), np.float32), Q, T, raw=True)
