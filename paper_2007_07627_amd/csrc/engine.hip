@@ -250,6 +250,11 @@ struct Engine {
   int target_items = 4096;   // NN work items aimed for when choosing splits
   hipStream_t st = nullptr;  // passes
   hipStream_t side = nullptr;  // admission / setup
+  // Uploads of the admission. Host arrays are pageable, and a pageable copy
+  // returns only once it has run, so on their own stream the host waits for
+  // the copy itself, not for the setup kernels queued before it on `side`.
+  hipStream_t up = nullptr;
+  hipEvent_t up_done = nullptr;
   SlotDesc* d_desc = nullptr;
   SlotState* d_state = nullptr;
   WorkList* d_wl = nullptr;
@@ -278,6 +283,8 @@ struct Engine {
     HIP_OK(hipSetDevice(dev));
     HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     HIP_OK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    HIP_OK(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&up_done, hipEventDisableTiming));
     HIP_OK(hipMalloc(&d_desc, sizeof(SlotDesc) * kMaxSlots));
     HIP_OK(hipMalloc(&d_state, sizeof(SlotState) * kMaxSlots));
     HIP_OK(hipMalloc(&d_wl, sizeof(WorkList)));
@@ -313,8 +320,10 @@ struct Engine {
     if (h_done) (void)hipHostFree(h_done);
     if (st) (void)hipStreamDestroy(st);
     if (side) (void)hipStreamDestroy(side);
+    if (up) (void)hipStreamDestroy(up);
+    if (up_done) (void)hipEventDestroy(up_done);
     d_desc = nullptr; d_state = nullptr; d_wl = nullptr; d_done = nullptr; h_done = nullptr;
-    st = nullptr; side = nullptr;
+    st = nullptr; side = nullptr; up = nullptr; up_done = nullptr;
   }
 
   bool ensure_events(int passes) {
@@ -417,7 +426,6 @@ struct Engine {
     char* b = h.mem;
     auto F = [&](size_t o) { return reinterpret_cast<float*>(b + o); };
     auto F4 = [&](size_t o) { return reinterpret_cast<float4*>(b + o); };
-    float* stage = F(L.o_scratch);
     unsigned* scratch = reinterpret_cast<unsigned*>(b + L.o_scratch);
     hipStream_t ss = side;
     char* st_base = reinterpret_cast<char*>(d_state + s);
@@ -446,21 +454,24 @@ struct Engine {
     hs[s].want_median = S.want_median != 0;
     S.k = 1;
     std::memcpy(S.Tkm1, (r.query || r.eval) ? r.Tq : r.prm.T0, sizeof S.Tkm1);
-    HIP_OK(hipMemcpyAsync(d_state + s, &S, sizeof S, hipMemcpyHostToDevice, ss));
+    // Uploads on their own stream, each AoS array into a region of the slot
+    // that is free until the setup below overwrites it: Q into the sort
+    // scratch (12 N <= its size), the normals into the centred cluster
+    // coordinates (16 N), P into the candidate lists (32 B per source).
+    HIP_OK(hipMemcpyAsync(d_state + s, &S, sizeof S, hipMemcpyHostToDevice, up));
+    const float* srcQ = r.Q_dev ? r.Q_dev : F(L.o_scratch);
+    const float* srcN = r.Qn_dev ? r.Qn_dev : F(L.o_qorg);
+    const float* srcP = r.P_dev ? r.P_dev : F(L.o_clist);
+    if (!r.Q_dev) HIP_OK(hipMemcpyAsync(F(L.o_scratch), r.Q.data(), 12ull * L.N, hipMemcpyHostToDevice, up));
+    if (p2pl && !r.Qn_dev)
+      HIP_OK(hipMemcpyAsync(F(L.o_qorg), r.Qn.data(), 12ull * L.N, hipMemcpyHostToDevice, up));
+    if (!r.P_dev) HIP_OK(hipMemcpyAsync(F(L.o_clist), r.P.data(), 12ull * L.M, hipMemcpyHostToDevice, up));
+    HIP_OK(hipEventRecord(up_done, up));
+    HIP_OK(hipStreamWaitEvent(ss, up_done, 0));
     // inputs -> SoA
-    auto upload = [&](const std::vector<float>& hv, const float* dv, int n, float* x, float* y,
-                      float* z) -> bool {
-      const float* src = dv;
-      if (!dv) {
-        HIP_OK(hipMemcpyAsync(stage, hv.data(), 12ull * n, hipMemcpyHostToDevice, ss));
-        src = stage;
-      }
-      launch_aos_to_soa(src, n, x, y, z, ss);
-      return true;
-    };
-    if (!upload(r.Q, r.Q_dev, L.N, F(L.o_qx), F(L.o_qy), F(L.o_qz))) return false;
-    if (p2pl && !upload(r.Qn, r.Qn_dev, L.N, F(L.o_nx), F(L.o_ny), F(L.o_nz))) return false;
-    if (!upload(r.P, r.P_dev, L.M, F(L.o_pox), F(L.o_poy), F(L.o_poz))) return false;
+    launch_aos_to_soa(srcQ, L.N, F(L.o_qx), F(L.o_qy), F(L.o_qz), ss);
+    if (p2pl) launch_aos_to_soa(srcN, L.N, F(L.o_nx), F(L.o_ny), F(L.o_nz), ss);
+    launch_aos_to_soa(srcP, L.M, F(L.o_pox), F(L.o_poy), F(L.o_poz), ss);
     // target cluster index
     launch_bbox(F(L.o_qx), F(L.o_qy), F(L.o_qz), L.N, bbQ, cQ, ss);
     unsigned* order = nullptr;
@@ -527,9 +538,11 @@ struct Engine {
     int split = std::max(1, cdiv(target_items, std::max(1, L.ntile)));
     split = std::min(split, std::min(kMaxSplit, L.ncl));
     D.split = std::max(1, split);
-    HIP_OK(hipMemcpyAsync(d_desc + s, &D, offsetof(SlotDesc, rho_max), hipMemcpyHostToDevice, ss));
+    HIP_OK(hipMemcpyAsync(d_desc + s, &D, offsetof(SlotDesc, rho_max), hipMemcpyHostToDevice, up));
     h.zero = 0;
-    HIP_OK(hipMemcpyAsync(d_done + s, &h.zero, sizeof(int), hipMemcpyHostToDevice, ss));
+    HIP_OK(hipMemcpyAsync(d_done + s, &h.zero, sizeof(int), hipMemcpyHostToDevice, up));
+    HIP_OK(hipEventRecord(up_done, up));
+    HIP_OK(hipStreamWaitEvent(ss, up_done, 0));  // the activation on `side` covers the uploads
     h_done[s] = 0;
     if (sync) HIP_OK(hipStreamSynchronize(ss));
     return hipGetLastError() == hipSuccess;

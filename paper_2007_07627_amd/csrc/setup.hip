@@ -132,8 +132,7 @@ constexpr int kSortPer = 16;
 constexpr int kSortChunk = 64 * kSortPer;
 
 __global__ __launch_bounds__(64) void rs_hist_kernel(const unsigned* __restrict__ keys, int n,
-                                                     int shift, int nblocks,
-                                                     unsigned* __restrict__ hist) {
+                                                     int shift, unsigned* __restrict__ hist) {
   __shared__ unsigned h[256];
   const int lane = threadIdx.x;
   const int base = blockIdx.x * kSortChunk + lane;
@@ -151,73 +150,56 @@ __global__ __launch_bounds__(64) void rs_hist_kernel(const unsigned* __restrict_
     if (d[s] < 256u) atomicAdd(&h[d[s]], 1u);
   wave_lds_sync();
 #pragma unroll
-  for (int i = 0; i < 4; ++i) hist[(size_t)(lane + 64 * i) * nblocks + blockIdx.x] = h[lane + 64 * i];
+  for (int i = 0; i < 4; ++i) hist[(size_t)blockIdx.x * 256 + lane + 64 * i] = h[lane + 64 * i];
 }
 
-// Exclusive scan of the digit-major histogram hist[digit * nb + block]: the
-// offset of (digit, block) is the count of all smaller digits plus that of
-// the digit in earlier blocks. One block of 16 wavefronts, 16 digits per
-// wavefront; each pass over 64 blocks loads the 16 digits' rows at once.
+// Exclusive scan of the block-major histogram hist[block * 256 + digit]: the
+// offset of (block, digit) is the count of all smaller digits plus that of
+// the digit in earlier blocks. One block of 1024 threads: thread (q, d) owns
+// digit d in the q-th quarter of the blocks (reads of 256 consecutive words).
 __global__ __launch_bounds__(1024) void rs_scan_kernel(unsigned* __restrict__ hist, int nb) {
-  constexpr int kDig = 16;
-  __shared__ unsigned s_tot[256];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  unsigned* row = hist + (size_t)wv * kDig * nb;
-  unsigned sum[kDig];
+  __shared__ unsigned s_part[4][256];
+  __shared__ unsigned s_inc[256];
+  const int d = threadIdx.x & 255, q = threadIdx.x >> 8;
+  const int per = (nb + 3) / 4;
+  const int b0 = q * per, b1 = min(nb, b0 + per);
+  unsigned sum = 0;
+  for (int bb = b0; bb < b1; bb += 8) {
+    unsigned v[8];
 #pragma unroll
-  for (int j = 0; j < kDig; ++j) sum[j] = 0u;
-  for (int b = lane; b < nb; b += 64) {
+    for (int j = 0; j < 8; ++j) v[j] = bb + j < b1 ? hist[(size_t)(bb + j) * 256 + d] : 0u;
 #pragma unroll
-    for (int j = 0; j < kDig; ++j) sum[j] += row[(size_t)j * nb + b];
+    for (int j = 0; j < 8; ++j) sum += v[j];
   }
-#pragma unroll
-  for (int j = 0; j < kDig; ++j) {
-    unsigned v = sum[j];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) s_tot[wv * kDig + j] = v;
-  }
+  s_part[q][d] = sum;
   __syncthreads();
-  // exclusive scan of the 256 digit totals by wavefront 0 (four per lane)
-  if (wv == 0) {
-    const unsigned t0 = s_tot[4 * lane], t1 = s_tot[4 * lane + 1], t2 = s_tot[4 * lane + 2],
-                   t3 = s_tot[4 * lane + 3];
-    const unsigned own = t0 + t1 + t2 + t3;
-    unsigned inc = own;
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned u = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += u;
-    }
-    const unsigned ex = inc - own;
-    s_tot[4 * lane] = ex;
-    s_tot[4 * lane + 1] = ex + t0;
-    s_tot[4 * lane + 2] = ex + t0 + t1;
-    s_tot[4 * lane + 3] = ex + t0 + t1 + t2;
-  }
+  const unsigned tot = s_part[0][d] + s_part[1][d] + s_part[2][d] + s_part[3][d];
+  if (q == 0) s_inc[d] = tot;
   __syncthreads();
-  unsigned carry[kDig];
+  for (int o = 1; o < 256; o <<= 1) {
+    const unsigned v = (q == 0 && d >= o) ? s_inc[d - o] : 0u;
+    __syncthreads();
+    if (q == 0) s_inc[d] += v;
+    __syncthreads();
+  }
+  unsigned run = s_inc[d] - tot;
+  for (int k = 0; k < q; ++k) run += s_part[k][d];
+  for (int bb = b0; bb < b1; bb += 8) {
+    unsigned v[8];
 #pragma unroll
-  for (int j = 0; j < kDig; ++j) carry[j] = s_tot[wv * kDig + j];
-  for (int b0 = 0; b0 < nb; b0 += 64) {
-    const int b = b0 + lane;
-    unsigned v[kDig];
+    for (int j = 0; j < 8; ++j) v[j] = bb + j < b1 ? hist[(size_t)(bb + j) * 256 + d] : 0u;
 #pragma unroll
-    for (int j = 0; j < kDig; ++j) v[j] = b < nb ? row[(size_t)j * nb + b] : 0u;
-#pragma unroll
-    for (int j = 0; j < kDig; ++j) {
-      unsigned inc = v[j];
-      for (int o = 1; o < 64; o <<= 1) {
-        const unsigned u = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += u;
+    for (int j = 0; j < 8; ++j)
+      if (bb + j < b1) {
+        hist[(size_t)(bb + j) * 256 + d] = run;
+        run += v[j];
       }
-      if (b < nb) row[(size_t)j * nb + b] = carry[j] + inc - v[j];
-      carry[j] += __shfl(inc, 63, 64);
-    }
   }
 }
 
 __global__ __launch_bounds__(64) void rs_scatter_kernel(const unsigned* __restrict__ kin,
                                                         const unsigned* __restrict__ vin, int n,
-                                                        int shift, int nblocks,
+                                                        int shift,
                                                         const unsigned* __restrict__ hist,
                                                         unsigned* __restrict__ kout,
                                                         unsigned* __restrict__ vout) {
@@ -232,7 +214,7 @@ __global__ __launch_bounds__(64) void rs_scatter_kernel(const unsigned* __restri
     vv[s] = e < n ? ldg(vin, e) : 0u;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) cnt[lane + 64 * i] = ldg(hist, (size_t)(lane + 64 * i) * nblocks + blockIdx.x);
+  for (int i = 0; i < 4; ++i) cnt[lane + 64 * i] = ldg(hist, (size_t)blockIdx.x * 256 + lane + 64 * i);
   wave_lds_sync();
   const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
@@ -503,10 +485,9 @@ void launch_hilbert_order(const float* x, const float* y, const float* z, int n,
   hipLaunchKernelGGL(hilbert_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, x, y, z, n, box, ka, va);
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 8 * pass;
-    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(64), 0, st, ka, n, shift, nb, hist);
+    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(64), 0, st, ka, n, shift, hist);
     hipLaunchKernelGGL(rs_scan_kernel, dim3(1), dim3(1024), 0, st, hist, nb);
-    hipLaunchKernelGGL(rs_scatter_kernel, dim3(nb), dim3(64), 0, st, ka, va, n, shift, nb, hist, kb,
-                       vb);
+    hipLaunchKernelGGL(rs_scatter_kernel, dim3(nb), dim3(64), 0, st, ka, va, n, shift, hist, kb, vb);
     unsigned* t = ka; ka = kb; kb = t;
     t = va; va = vb; vb = t;
   }
