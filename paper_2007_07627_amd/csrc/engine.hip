@@ -212,18 +212,22 @@ struct OwnedRequest {
 // nu_min <= 0 selects the automatic rule for the Welsch modes.
 static bool auto_nu_min(const icp_params* p) { return !mode_l2(p->mode) && !(p->nu_min > 0.0); }
 
+// Closest-point work counters of a slot (per-die statistics lines).
+static void stats_from(const unsigned long long* v, icp_result* r) {
+  double a = 0.0, b = 0.0;
+  for (int q = 0; q < kQueues; ++q) {
+    a += (double)v[q * kStatStride];
+    b += (double)v[q * kStatStride + 1];
+  }
+  r->nn_pairs = a;
+  r->nn_exact_pairs = b;
+}
+
 static void fill_stats(const HostSlot& h, hipStream_t st, icp_result* r) {
   unsigned long long v[kQueues * kStatStride] = {};
   if (h.mem && hipMemcpyAsync(v, h.mem + h.L.o_stats, sizeof v, hipMemcpyDeviceToHost, st) == hipSuccess &&
-      hipStreamSynchronize(st) == hipSuccess) {
-    double a = 0.0, b = 0.0;
-    for (int q = 0; q < kQueues; ++q) {
-      a += (double)v[q * kStatStride];
-      b += (double)v[q * kStatStride + 1];
-    }
-    r->nn_pairs = a;
-    r->nn_exact_pairs = b;
-  }
+      hipStreamSynchronize(st) == hipSuccess)
+    stats_from(v, r);
 }
 
 static void fill_result(const SlotState& S, icp_result* r) {
@@ -260,6 +264,11 @@ struct Engine {
   WorkList* d_wl = nullptr;
   int* d_done = nullptr;
   int* h_done = nullptr;
+  // pinned landing buffers of the batch retirement (all finished slots of a
+  // round are read back with one synchronisation) and its reset values
+  SlotState* h_fin_state = nullptr;
+  unsigned long long* h_fin_stats = nullptr;  // kQueues * kStatStride per slot
+  int* h_reset = nullptr;                     // {0, ST_FREE}
   std::vector<HostSlot> hs;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -290,6 +299,11 @@ struct Engine {
     HIP_OK(hipMalloc(&d_wl, sizeof(WorkList)));
     HIP_OK(hipMalloc(&d_done, sizeof(int) * kMaxSlots));
     HIP_OK(hipHostMalloc((void**)&h_done, sizeof(int) * kMaxSlots, hipHostMallocDefault));
+    HIP_OK(hipHostMalloc((void**)&h_fin_state, sizeof(SlotState) * kMaxSlots, hipHostMallocDefault));
+    HIP_OK(hipHostMalloc((void**)&h_fin_stats, 8ull * kQueues * kStatStride * kMaxSlots, hipHostMallocDefault));
+    HIP_OK(hipHostMalloc((void**)&h_reset, 2 * sizeof(int), hipHostMallocDefault));
+    h_reset[0] = 0;
+    h_reset[1] = ST_FREE;
     HIP_OK(hipMemset(d_desc, 0, sizeof(SlotDesc) * kMaxSlots));
     HIP_OK(hipMemset(d_state, 0, sizeof(SlotState) * kMaxSlots));
     HIP_OK(hipMemset(d_done, 0, sizeof(int) * kMaxSlots));
@@ -318,6 +332,10 @@ struct Engine {
     if (d_wl) (void)hipFree(d_wl);
     if (d_done) (void)hipFree(d_done);
     if (h_done) (void)hipHostFree(h_done);
+    if (h_fin_state) (void)hipHostFree(h_fin_state);
+    if (h_fin_stats) (void)hipHostFree(h_fin_stats);
+    if (h_reset) (void)hipHostFree(h_reset);
+    h_fin_state = nullptr; h_fin_stats = nullptr; h_reset = nullptr;
     if (st) (void)hipStreamDestroy(st);
     if (side) (void)hipStreamDestroy(side);
     if (up) (void)hipStreamDestroy(up);
@@ -887,21 +905,32 @@ static void scheduler(icp_ctx* ctx) {
       ctx->cv_done.notify_all();
       return;
     }
-    // 4) retire finished pairs
-    for (int s = 0; s < E.capacity; ++s) {
-      if (!E.hs[s].used || !E.h_done[s]) continue;
-      SlotState S;
+    // 4) retire finished pairs: read back their states and counters and free
+    //    their slots on the device, all with one synchronisation
+    constexpr int kStatWords = kQueues * kStatStride;
+    std::vector<int> fin;
+    for (int s = 0; s < E.capacity; ++s)
+      if (E.hs[s].used && E.h_done[s]) fin.push_back(s);
+    bool got = true;
+    for (int s : fin) {
+      got = got &&
+            hipMemcpyAsync(E.h_fin_state + s, E.d_state + s, sizeof(SlotState), hipMemcpyDeviceToHost, E.st) ==
+                hipSuccess &&
+            hipMemcpyAsync(E.h_fin_stats + (size_t)s * kStatWords, E.hs[s].mem + E.hs[s].L.o_stats,
+                           8ull * kStatWords, hipMemcpyDeviceToHost, E.st) == hipSuccess;
+      (void)hipMemcpyAsync(E.d_done + s, E.h_reset, sizeof(int), hipMemcpyHostToDevice, E.st);
+      (void)hipMemcpyAsync(reinterpret_cast<char*>(E.d_state + s) + offsetof(SlotState, status), E.h_reset + 1,
+                           sizeof(int), hipMemcpyHostToDevice, E.st);
+    }
+    if (!fin.empty()) got = hipStreamSynchronize(E.st) == hipSuccess && got;
+    for (int s : fin) {
       icp_result res;
       std::memset(&res, 0, sizeof res);
-      if (E.read_state(s, &S)) fill_result(S, &res);
-      fill_stats(E.hs[s], E.st, &res);
+      if (got) {
+        fill_result(E.h_fin_state[s], &res);
+        stats_from(E.h_fin_stats + (size_t)s * kStatWords, &res);
+      }
       res.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - E.hs[s].t_submit).count();
-      const int zero = 0;
-      const int st_free = ST_FREE;
-      (void)hipMemcpyAsync(E.d_done + s, &zero, sizeof(int), hipMemcpyHostToDevice, E.st);
-      (void)hipMemcpyAsync(reinterpret_cast<char*>(E.d_state + s) + offsetof(SlotState, status), &st_free,
-                           sizeof(int), hipMemcpyHostToDevice, E.st);
-      (void)hipStreamSynchronize(E.st);
       const uint64_t t = E.hs[s].ticket;
       E.release(s);
       std::lock_guard<std::mutex> lk(ctx->mu);
