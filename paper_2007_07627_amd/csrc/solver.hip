@@ -970,8 +970,6 @@ stage_end:
 
 // ------------------------------------------------------------------ kernels
 
-// Merge the partials of one slot in a fixed order (lane-strided sums, then a
-// fixed shuffle tree) and advance the state machine on lane 0.
 // Median of the slot's median keys (the element of rank M/2 of non-negative
 // FP64 values, ordered by their bit patterns) by an 8-bit radix select.
 __global__ __launch_bounds__(1024) void median_kernel(const SlotDesc* __restrict__ descs,
@@ -981,34 +979,51 @@ __global__ __launch_bounds__(1024) void median_kernel(const SlotDesc* __restrict
   SlotState& S = states[slot];
   if (S.status != ST_RUNNING || !S.want_median) return;
   const SlotDesc& D = descs[slot];
+  const int t = threadIdx.x;
   __shared__ unsigned hist[256];
+  __shared__ unsigned s_inc[256];
   __shared__ unsigned long long s_prefix, s_mask;
   __shared__ long long s_k;
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     s_prefix = 0ull;
     s_mask = 0ull;
     s_k = D.M / 2;
   }
   __syncthreads();
   for (int shift = 56; shift >= 0; shift -= 8) {
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0u;
+    if (t < 256) hist[t] = 0u;
     __syncthreads();
     const unsigned long long pre = s_prefix, msk = s_mask;
-    for (int i = threadIdx.x; i < D.M; i += blockDim.x) {
-      const unsigned long long key = (unsigned long long)__double_as_longlong(D.medkey[i]);
-      if ((key & msk) == pre) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
+    const long long k = s_k;
+    // eight keys per thread in flight at once
+    for (int i0 = t; i0 < D.M; i0 += 8 * 1024) {
+      unsigned long long key[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + 1024 * u;
+        key[u] = i < D.M ? (unsigned long long)__double_as_longlong(ldg(D.medkey, i)) : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + 1024 * u < D.M && (key[u] & msk) == pre) atomicAdd(&hist[(key[u] >> shift) & 255ull], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      long long k = s_k;
-      int d = 0;
-      for (; d < 256; ++d) {
-        if (k < (long long)hist[d]) break;
-        k -= hist[d];
+    // the digit holding rank k: inclusive prefix counts over the 256 digits
+    if (t < 256) s_inc[t] = hist[t];
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      const unsigned v = (t < 256 && t >= o) ? s_inc[t - o] : 0u;
+      __syncthreads();
+      if (t < 256) s_inc[t] += v;
+      __syncthreads();
+    }
+    if (t < 256) {
+      const long long lo = t > 0 ? (long long)s_inc[t - 1] : 0ll, hi = (long long)s_inc[t];
+      if (lo <= k && k < hi) {
+        s_k = k - lo;
+        s_prefix = pre | ((unsigned long long)t << shift);
+        s_mask = msk | (255ull << shift);
       }
-      s_k = k;
-      s_prefix = pre | ((unsigned long long)d << shift);
-      s_mask = msk | (255ull << shift);
     }
     __syncthreads();
   }
