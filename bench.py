@@ -163,6 +163,34 @@ def brute_roofline(ctx, B, torch):
             "frac": tf / FP32_PEAK_TFLOPS}
 
 
+def brute_batch_roofline(B, count=256):
+    """Exhaustive closest point over a batch of config-1 shapes: `count` Fast
+    ICP pairs of 4096 x 4096 (L2 + Anderson m = 5, brute force) advanced
+    together by the batch engine, each pass's closest-point kernels timed
+    with HIP events on the library's stream; work = the pairs examined."""
+    from paper_2007_07627_amd import synth
+    prm = lambda: B.icp_params_default(B.ICP_P2P_L2, eps=1e-6, iter_first=50, iter_cap=50, nn=B.ICP_NN_BRUTE)
+    ds = [synth.fast_icp_pair(synth.rng_for(1, i)) for i in range(count)]
+    reqs = [(d["P"], d["Q"], None, prm()) for d in ds]
+    ctx = B.icp_create(0, 8 << 30)
+    B.icp_batch_config(ctx, 4, count)
+    _wait_tickets(B, ctx, B.icp_batch_submit(ctx, reqs[:8]))  # warm-up
+    B.icp_profile(ctx, True)
+    t0 = time.perf_counter()
+    res = _wait_tickets(B, ctx, B.icp_batch_submit(ctx, reqs))
+    wall = time.perf_counter() - t0
+    st = B.icp_profile_read(ctx)
+    B.icp_profile(ctx, False)
+    B.icp_destroy(ctx)
+    pairs = float(sum(r["nn_pairs"] for r in res))
+    passes = max(1, st["passes"])
+    tf = pairs * FLOPS_PER_PAIR / (max(st["nn_ms"], 1e-9) * 1e-3) / 1e12
+    return {"kernel": "nn_kernel (exhaustive, batch engine)", "pairs": count, "M": 4096, "N": 4096,
+            "batch_passes": passes, "pairs_examined_per_pass": pairs / passes,
+            "nn_ms_per_pass": st["nn_ms"] / passes, "achieved_tflops": tf, "peak_tflops": FP32_PEAK_TFLOPS,
+            "frac": tf / FP32_PEAK_TFLOPS, "registrations_per_s_profiled": count / wall}
+
+
 def _params_for(B, d):
     if d["mode"] == 2:
         return B.icp_params_default(B.ICP_P2PL_WELSCH, anderson_m=6, nu_min=d["nu_min"])
@@ -461,11 +489,14 @@ def main():
         "effective_pairs_per_s": M * float(len(ds[0]["Q"])) * passes * K / wall,
         "roofline": roof,
     }
-    if not args.no_concurrent:
+    if not args.no_concurrent and npair > 1:
         out["in_flight"] = concurrent_run(args, B, ctx, ds, prms, ref)
     if not args.no_brute:
         log("exhaustive kernel roofline (100k x 100k)")
         out["nn_brute_roofline"] = brute_roofline(ctx, B, torch)
+        if args.workload == "fast-icp-4096":
+            log("exhaustive closest point over 256 config-1 pairs in the batch engine")
+            out["nn_brute_batch_roofline"] = brute_batch_roofline(B)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(ds[0], prms[0], passes)
