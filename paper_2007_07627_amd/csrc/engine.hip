@@ -251,7 +251,6 @@ struct Engine {
   int capacity = 1;
   bool single = false;       // one slot at a time, planned by its own solver
   bool brute = false;        // one-slot engine: the resident pair uses the exhaustive method
-  int target_items = 4096;   // NN work items aimed for when choosing splits
   hipStream_t st = nullptr;  // passes
   hipStream_t side = nullptr;  // admission / setup
   // Uploads of the admission. Host arrays are pageable, and a pageable copy
@@ -284,11 +283,10 @@ struct Engine {
   double prof_ms[3] = {0.0, 0.0, 0.0};  // closest point, reduction, median + solver
   long long prof_passes = 0;
 
-  bool init(int device, int cap, Arena* a, int items) {
+  bool init(int device, int cap, Arena* a) {
     dev = device;
     capacity = cap;
     arena = a;
-    target_items = items;
     HIP_OK(hipSetDevice(dev));
     HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     HIP_OK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
@@ -553,9 +551,6 @@ struct Engine {
     D.method = meth == ICP_NN_BRUTE ? NN_BRUTE : NN_CLUSTER;
     if (single) brute = D.method == NN_BRUTE;
     D.mode = S.mode;
-    int split = std::max(1, cdiv(target_items, std::max(1, L.ntile)));
-    split = std::min(split, std::min(kMaxSplit, L.ncl));
-    D.split = std::max(1, split);
     HIP_OK(hipMemcpyAsync(d_desc + s, &D, offsetof(SlotDesc, rho_max), hipMemcpyHostToDevice, up));
     h.zero = 0;
     HIP_OK(hipMemcpyAsync(d_done + s, &h.zero, sizeof(int), hipMemcpyHostToDevice, up));
@@ -1016,12 +1011,8 @@ icp_status icp_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
   c->device = device;
   if (hbm_budget_bytes == 0) hbm_budget_bytes = size_t(8) << 30;
   if (!c->arena.init(hbm_budget_bytes)) { delete c; return ICP_ERR_OOM; }
-  // closest-point work items aimed for per pass when splitting source tiles
-  // over target subsets (tunable: ICP_NN_TARGET_ITEMS)
-  int items = 4096;
-  if (const char* e = std::getenv("ICP_NN_TARGET_ITEMS")) items = std::max(1, std::atoi(e));
   c->sync_eng.single = true;
-  if (!c->sync_eng.init(device, 1, &c->arena, items) || !c->batch_eng.init(device, c->max_slots, &c->arena, 64)) {
+  if (!c->sync_eng.init(device, 1, &c->arena) || !c->batch_eng.init(device, c->max_slots, &c->arena)) {
     c->sync_eng.destroy();
     c->batch_eng.destroy();
     delete c;

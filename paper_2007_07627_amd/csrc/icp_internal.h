@@ -19,7 +19,6 @@ constexpr int kPartStride = 32;  // doubles per reduction partial
 constexpr int kHist = 8;         // Anderson ring capacity (m <= 6 needs m + 1)
 constexpr int kCandCap = 1024;   // LDS candidate list capacity per NN work item
 constexpr int kSupCap = 512;     // LDS candidate super-cluster capacity per NN work item
-constexpr int kMaxSplit = 8;
 constexpr int kListCap = 512;    // candidate clusters stored per tile
 constexpr int kMaxSlices = 64;   // slices per tile in cluster mode
 // Long candidate sequences (lists whose length forced slices longer than
@@ -104,7 +103,6 @@ struct SlotDesc {
                               // [cycles, clusters filtered, candidates, flags]
   int trace_cap;
   int M, N, ntile, ncl, nsup, nepi;
-  int split;                  // brute mode: slices per tile
   int method;                 // NN_BRUTE or NN_CLUSTER
   int mode;
   float rho_max;              // max cluster radius (upper bound)
@@ -187,11 +185,23 @@ struct WorkList {
   int nn_base[1025];          // prefix of NN items over the compacted list
   int epi_base[1025];
   int s_base[1025];           // prefix of queued slices over the compacted list
+  int b_total;                // exhaustive-method items this pass (multi-slot engine)
+  int b_base[1025];           // prefix of exhaustive-method items over the compacted list
   // dynamic work counters (reset by the planners): kQueues sub-queues each
   int q_nn[kQueues * kQueueStride];
   int q_epi[kQueues * kQueueStride];
   int q_s[kQueues * kQueueStride];
 };
+
+// Exhaustive method in the multi-slot engine: one item = a pair of 64-source
+// tiles against a range of about kBruteItemClusters clusters.
+constexpr int kBruteItemClusters = 32;
+__host__ __device__ inline int brute_split(int ncl) {
+  return ncl > 0 ? (ncl + kBruteItemClusters - 1) / kBruteItemClusters : 1;
+}
+__host__ __device__ inline int brute_items(int ntile, int ncl) {
+  return ((ntile + 1) / 2) * brute_split(ncl);
+}
 
 // Element i of a device array through a global-address-space pointer. The
 // descriptor's pointers are generic, and generic loads also hold the LDS

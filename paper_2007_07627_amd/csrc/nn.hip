@@ -288,193 +288,182 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
     const bool valid = si < D.M;
     const double* T = S.Teval;
     int flags = 0, n = 0, first = -1;
-    if (D.method == NN_BRUTE) {
-      flags = TI_RANGE;
-      n = D.ncl;
-    } else {
-      float ptx, pty, ptz, W;
-      lane_point(D, T, si, valid, true, ptx, pty, ptz, W);
-      const bool warm = __all(!valid || W < __builtin_inff());
-      const double4 ts = D.tsph[tile];
-      float cx, cy, cz;
-      {
-        const double X = ts.x, Y = ts.y, Z = ts.z;
-        cx = (float)__builtin_fma(T[2], Z, __builtin_fma(T[1], Y, __builtin_fma(T[0], X, T[3])));
-        cy = (float)__builtin_fma(T[6], Z, __builtin_fma(T[5], Y, __builtin_fma(T[4], X, T[7])));
-        cz = (float)__builtin_fma(T[10], Z, __builtin_fma(T[9], Y, __builtin_fma(T[8], X, T[11])));
+    float ptx, pty, ptz, W;
+    lane_point(D, T, si, valid, true, ptx, pty, ptz, W);
+    const bool warm = __all(!valid || W < __builtin_inff());
+    const double4 ts = D.tsph[tile];
+    float cx, cy, cz;
+    {
+      const double X = ts.x, Y = ts.y, Z = ts.z;
+      cx = (float)__builtin_fma(T[2], Z, __builtin_fma(T[1], Y, __builtin_fma(T[0], X, T[3])));
+      cy = (float)__builtin_fma(T[6], Z, __builtin_fma(T[5], Y, __builtin_fma(T[4], X, T[7])));
+      cz = (float)__builtin_fma(T[10], Z, __builtin_fma(T[9], Y, __builtin_fma(T[8], X, T[11])));
+    }
+    const float cn = sqrtf(cx * cx + cy * cy + cz * cz);
+    const float r = (float)ts.w * 1.00001f + 1e-5f * cn + 1e-30f;
+    // every lane's winner lies within U of the tile centre's sphere
+    float U = warm ? sqrtf(wave_max(valid ? winner_threshold(W) : 0.0f)) * 1.000001f + 1e-30f
+                   : __builtin_inff();
+    for (int s2 = lane; s2 < D.nsup; s2 += 64)
+      U = fminf(U, sqrtf(box_ub2(cx, cy, cz, load_global(D.slo, s2), load_global(D.shi, s2))) * 1.000001f + r);
+    U = wave_min(U);
+    // Warm lists are kept for later passes while every source stays within
+    // the margin of its position now; a later pass's winner is then within
+    // its bound here plus twice the margin (the point and its winner's
+    // distance each move by at most the margin).
+    const float margin = warm ? 2.0f * D.verlet : 0.0f;
+    U += margin;
+    // per-lane bound with the margin: (sqrt(thr(W)) + margin)^2, rounded up
+    const float bw = sqrtf(winner_threshold(W)) * (1.0f + 0x1.0p-20f) + margin;
+    const float thr_m = bw * bw * (1.0f + 0x1.0p-20f);
+    // candidate super-clusters: tile-level test, then (warm) each lane's own
+    // bound against the boxes staged in LDS
+    int nsc = 0;
+    for (int base = 0; base < D.nsup; base += 64) {
+      const int s2 = base + lane;
+      bool c = false;
+      float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = blo;
+      if (s2 < D.nsup) {
+        blo = load_global(D.slo, s2);
+        bhi = load_global(D.shi, s2);
+        c = sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r <= U * 1.00001f;
       }
-      const float cn = sqrtf(cx * cx + cy * cy + cz * cz);
-      const float r = (float)ts.w * 1.00001f + 1e-5f * cn + 1e-30f;
-      // every lane's winner lies within U of the tile centre's sphere
-      float U = warm ? sqrtf(wave_max(valid ? winner_threshold(W) : 0.0f)) * 1.000001f + 1e-30f
-                     : __builtin_inff();
-      for (int s2 = lane; s2 < D.nsup; s2 += 64)
-        U = fminf(U, sqrtf(box_ub2(cx, cy, cz, load_global(D.slo, s2), load_global(D.shi, s2))) * 1.000001f + r);
-      U = wave_min(U);
-      // Warm lists are kept for later passes while every source stays within
-      // the margin of its position now; a later pass's winner is then within
-      // its bound here plus twice the margin (the point and its winner's
-      // distance each move by at most the margin).
-      const float margin = warm ? 2.0f * D.verlet : 0.0f;
-      U += margin;
-      // per-lane bound with the margin: (sqrt(thr(W)) + margin)^2, rounded up
-      const float bw = sqrtf(winner_threshold(W)) * (1.0f + 0x1.0p-20f) + margin;
-      const float thr_m = bw * bw * (1.0f + 0x1.0p-20f);
-      // candidate super-clusters: tile-level test, then (warm) each lane's own
-      // bound against the boxes staged in LDS
-      int nsc = 0;
-      for (int base = 0; base < D.nsup; base += 64) {
-        const int s2 = base + lane;
-        bool c = false;
-        float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = blo;
-        if (s2 < D.nsup) {
-          blo = load_global(D.slo, s2);
-          bhi = load_global(D.shi, s2);
-          c = sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r <= U * 1.00001f;
-        }
-        unsigned long long bal = __ballot(c);
-        if (warm && bal) {
-          wave_lds_sync();
-          s_box[lane] = blo;
-          s_box[64 + lane] = bhi;
-          wave_lds_sync();
-          const float thr = thr_m;
-          unsigned long long need = 0ull;
-          for (unsigned long long m = bal; m; m &= m - 1ull) {
-            const int j = __builtin_ctzll(m);
-            const float lb2 = box_lb2(ptx, pty, ptz, s_box[j], s_box[64 + j]);
-            if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr)) need |= 1ull << j;
-          }
-          bal = need;
-          c = (bal >> lane) & 1ull;
-        }
-        const int pos = nsc + __popcll(bal & ((1ull << lane) - 1ull));
-        if (c && pos < kSupCap) s_sup[pos] = s2;
-        nsc += __popcll(bal);
-      }
-      __syncthreads();
-      const int nflat = nsc > kSupCap ? D.ncl : nsc * kSuper;  // all clusters on overflow
-      auto flat_cluster = [&](int f) -> int {
-        if (nsc > kSupCap) return f;
-        const int c = s_sup[f / kSuper] * kSuper + (f % kSuper);
-        return c < D.ncl ? c : -1;
-      };
-      if (warm) {
-        // Stream the candidate clusters in batches of 64: tile-level test, then
-        // every lane tests the batch's boxes (staged in LDS) against its own
-        // bound; the clusters some lane needs are appended to the list.
+      unsigned long long bal = __ballot(c);
+      if (warm && bal) {
+        wave_lds_sync();
+        s_box[lane] = blo;
+        s_box[64 + lane] = bhi;
+        wave_lds_sync();
         const float thr = thr_m;
-        // the candidate batches are shared out among the block's wavefronts;
-        // needed clusters are appended through a block counter (the list's
-        // order varies, its contents do not)
-        if (threadIdx.x == 0) s_n2 = 0;
-        __syncthreads();
-        for (int base = 64 * wv; base < nflat; base += 64 * kCullWaves) {
-          const int f = base + lane;
-          int cid = f < nflat ? flat_cluster(f) : -1;
-          float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = blo;
-          if (cid >= 0) {
-            blo = load_global(D.clo, cid);
-            bhi = load_global(D.chi, cid);
-            if (!(sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r <= U * 1.00001f)) cid = -1;
-          }
-          const unsigned long long cand = __ballot(cid >= 0);
-          if (cand == 0ull) continue;
-          wave_lds_sync();
-          s_box[lane] = blo;
-          s_box[64 + lane] = bhi;
-          wave_lds_sync();
-          unsigned long long need = 0ull;
-          for (unsigned long long m = cand; m; m &= m - 1ull) {
-            const int j = __builtin_ctzll(m);
-            const float lb2 = box_lb2(ptx, pty, ptz, s_box[j], s_box[64 + j]);
-            if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr)) need |= 1ull << j;
-          }
-          if (need == 0ull) continue;
-          int at = 0;
-          if (lane == 0) at = atomicAdd(&s_n2, __popcll(need));
-          at = __shfl(at, 0, 64);
-          const int pos = at + __popcll(need & ((1ull << lane) - 1ull));
-          if (((need >> lane) & 1ull) && pos < kListCap) D.clist[(size_t)tile * kListCap + pos] = cid;
+        unsigned long long need = 0ull;
+        for (unsigned long long m = bal; m; m &= m - 1ull) {
+          const int j = __builtin_ctzll(m);
+          const float lb2 = box_lb2(ptx, pty, ptz, s_box[j], s_box[64 + j]);
+          if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr)) need |= 1ull << j;
         }
-        __syncthreads();
-        const int n2 = s_n2;
-        if (n2 > kListCap || n2 == 0) {
-          // more needed clusters than a list holds (or none, which valid lanes
-          // exclude): slices over all clusters, tested per lane
-          flags = TI_RANGE | TI_LANETEST | TI_WARM;
-          n = D.ncl;
-        } else {
-          flags = TI_LIST | TI_WARM;
-          n = n2;
+        bal = need;
+        c = (bal >> lane) & 1ull;
+      }
+      const int pos = nsc + __popcll(bal & ((1ull << lane) - 1ull));
+      if (c && pos < kSupCap) s_sup[pos] = s2;
+      nsc += __popcll(bal);
+    }
+    __syncthreads();
+    const int nflat = nsc > kSupCap ? D.ncl : nsc * kSuper;  // all clusters on overflow
+    auto flat_cluster = [&](int f) -> int {
+      if (nsc > kSupCap) return f;
+      const int c = s_sup[f / kSuper] * kSuper + (f % kSuper);
+      return c < D.ncl ? c : -1;
+    };
+    if (warm) {
+      // Stream the candidate clusters in batches of 64: tile-level test, then
+      // every lane tests the batch's boxes (staged in LDS) against its own
+      // bound; the clusters some lane needs are appended to the list.
+      const float thr = thr_m;
+      // the candidate batches are shared out among the block's wavefronts;
+      // needed clusters are appended through a block counter (the list's
+      // order varies, its contents do not)
+      if (threadIdx.x == 0) s_n2 = 0;
+      __syncthreads();
+      for (int base = 64 * wv; base < nflat; base += 64 * kCullWaves) {
+        const int f = base + lane;
+        int cid = f < nflat ? flat_cluster(f) : -1;
+        float4 blo = make_float4(0.f, 0.f, 0.f, 0.f), bhi = blo;
+        if (cid >= 0) {
+          blo = load_global(D.clo, cid);
+          bhi = load_global(D.chi, cid);
+          if (!(sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r <= U * 1.00001f)) cid = -1;
         }
-      } else {
-        // No warm start (first pass): tile-level candidates, tightened by the
-        // best cluster upper bound; the nearest cluster seeds every slice.
-        float bestub = __builtin_inff();
-        int bestc = 0x7fffffff;
-        int ncand = 0;
-        for (int base = 0; base < nflat; base += 64) {
-          const int f = base + lane;
-          bool c = false;
-          const int cid = f < nflat ? flat_cluster(f) : -1;
-          if (cid >= 0) {
-            const float4 blo = load_global(D.clo, cid), bhi = load_global(D.chi, cid);
-            const float lb = sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r;
-            const float ub = sqrtf(box_ub2(cx, cy, cz, blo, bhi)) * 1.000001f + r;
-            if (ub < bestub || (ub == bestub && cid < bestc)) { bestub = ub; bestc = cid; }
-            c = lb <= U * 1.00001f;
-          }
-          const unsigned long long bal = __ballot(c);
-          const int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
-          if (c && pos < kCandCap) s_cand[pos] = cid;
-          ncand += __popcll(bal);
+        const unsigned long long cand = __ballot(cid >= 0);
+        if (cand == 0ull) continue;
+        wave_lds_sync();
+        s_box[lane] = blo;
+        s_box[64 + lane] = bhi;
+        wave_lds_sync();
+        unsigned long long need = 0ull;
+        for (unsigned long long m = cand; m; m &= m - 1ull) {
+          const int j = __builtin_ctzll(m);
+          const float lb2 = box_lb2(ptx, pty, ptz, s_box[j], s_box[64 + j]);
+          if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr)) need |= 1ull << j;
         }
-        const float Uc = wave_min(bestub);
-        int cfirst = (bestub == Uc) ? bestc : 0x7fffffff;
-        for (int o = 32; o > 0; o >>= 1) cfirst = min(cfirst, __shfl_xor(cfirst, o, 64));
-        first = cfirst;
-        if (ncand > kListCap) {
-          flags = TI_RANGE | TI_LANETEST;
-          n = D.ncl;
-        } else {
-          U = fminf(U, Uc);
-          __syncthreads();
-          int n2 = 0;
-          for (int base = 0; base < ncand; base += 64) {
-            const int f = base + lane;
-            int cid = -1;
-            if (f < ncand) {
-              cid = s_cand[f];
-              const float lb = sqrtf(box_lb2(cx, cy, cz, load_global(D.clo, cid), load_global(D.chi, cid))) * 0.999999f - r;
-              if (!(lb <= U * 1.00001f) || cid == first) cid = -1;
-            }
-            const unsigned long long keep = __ballot(cid >= 0);
-            const int pos = n2 + __popcll(keep & ((1ull << lane) - 1ull));
-            if (cid >= 0) D.clist[(size_t)tile * kListCap + pos] = cid;
-            n2 += __popcll(keep);
-          }
-          flags = TI_LIST | TI_LANETEST;
-          n = n2;
-        }
+        if (need == 0ull) continue;
+        int at = 0;
+        if (lane == 0) at = atomicAdd(&s_n2, __popcll(need));
+        at = __shfl(at, 0, 64);
+        const int pos = at + __popcll(need & ((1ull << lane) - 1ull));
+        if (((need >> lane) & 1ull) && pos < kListCap) D.clist[(size_t)tile * kListCap + pos] = cid;
       }
       __syncthreads();
-    }
-    // slices: brute mode uses the pair's split count, cluster mode a length
-    int len, nsl;
-    if (D.method == NN_BRUTE) {
-      len = (n + D.split - 1) / D.split;
-      nsl = (n + len - 1) / len;
+      const int n2 = s_n2;
+      if (n2 > kListCap || n2 == 0) {
+        // more needed clusters than a list holds (or none, which valid lanes
+        // exclude): slices over all clusters, tested per lane
+        flags = TI_RANGE | TI_LANETEST | TI_WARM;
+        n = D.ncl;
+      } else {
+        flags = TI_LIST | TI_WARM;
+        n = n2;
+      }
     } else {
-      len = max(kSliceMin, (n + kMaxSlices - 1) / kMaxSlices);
-      nsl = max(1, (n + len - 1) / len);
+      // No warm start (first pass): tile-level candidates, tightened by the
+      // best cluster upper bound; the nearest cluster seeds every slice.
+      float bestub = __builtin_inff();
+      int bestc = 0x7fffffff;
+      int ncand = 0;
+      for (int base = 0; base < nflat; base += 64) {
+        const int f = base + lane;
+        bool c = false;
+        const int cid = f < nflat ? flat_cluster(f) : -1;
+        if (cid >= 0) {
+          const float4 blo = load_global(D.clo, cid), bhi = load_global(D.chi, cid);
+          const float lb = sqrtf(box_lb2(cx, cy, cz, blo, bhi)) * 0.999999f - r;
+          const float ub = sqrtf(box_ub2(cx, cy, cz, blo, bhi)) * 1.000001f + r;
+          if (ub < bestub || (ub == bestub && cid < bestc)) { bestub = ub; bestc = cid; }
+          c = lb <= U * 1.00001f;
+        }
+        const unsigned long long bal = __ballot(c);
+        const int pos = ncand + __popcll(bal & ((1ull << lane) - 1ull));
+        if (c && pos < kCandCap) s_cand[pos] = cid;
+        ncand += __popcll(bal);
+      }
+      const float Uc = wave_min(bestub);
+      int cfirst = (bestub == Uc) ? bestc : 0x7fffffff;
+      for (int o = 32; o > 0; o >>= 1) cfirst = min(cfirst, __shfl_xor(cfirst, o, 64));
+      first = cfirst;
+      if (ncand > kListCap) {
+        flags = TI_RANGE | TI_LANETEST;
+        n = D.ncl;
+      } else {
+        U = fminf(U, Uc);
+        __syncthreads();
+        int n2 = 0;
+        for (int base = 0; base < ncand; base += 64) {
+          const int f = base + lane;
+          int cid = -1;
+          if (f < ncand) {
+            cid = s_cand[f];
+            const float lb = sqrtf(box_lb2(cx, cy, cz, load_global(D.clo, cid), load_global(D.chi, cid))) * 0.999999f - r;
+            if (!(lb <= U * 1.00001f) || cid == first) cid = -1;
+          }
+          const unsigned long long keep = __ballot(cid >= 0);
+          const int pos = n2 + __popcll(keep & ((1ull << lane) - 1ull));
+          if (cid >= 0) D.clist[(size_t)tile * kListCap + pos] = cid;
+          n2 += __popcll(keep);
+        }
+        flags = TI_LIST | TI_LANETEST;
+        n = n2;
+      }
     }
+    __syncthreads();
+    // slices of at least kSliceMin candidates, at most kMaxSlices per tile
+    int len = max(kSliceMin, (n + kMaxSlices - 1) / kMaxSlices);
+    int nsl = max(1, (n + len - 1) / len);
     // each slice record carries everything the slice kernel needs, so that
     // its first loads do not wait on a tile record
     if (wv == 0) {
       int base = 0;
       if (lane == 0) {
-        if (D.method != NN_BRUTE && len > kSliceMin) {
+        if (len > kSliceMin) {
           // a long candidate sequence (rare) is cut into shorter slices while
           // the pair's budget of extra slices lasts: its slices would set the tail
           const int l2 = max(kSliceMin, (n + kMaxLongSlices - 1) / kMaxLongSlices);
@@ -505,7 +494,8 @@ __global__ __launch_bounds__(1024) void slice_plan_kernel(const SlotDesc* __rest
   int v = 0;
   // slots that search this pass: their slices from this pass's cull or, when
   // the lists are reused, from the last one
-  if (t < na && !states[wl->slot[t]].reuse) v = *descs[wl->slot[t]].scount;
+  if (t < na && !states[wl->slot[t]].reuse && descs[wl->slot[t]].method != NN_BRUTE)
+    v = *descs[wl->slot[t]].scount;
   s[t] = v;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -792,10 +782,104 @@ __device__ __forceinline__ void filter_cluster_pair(const float4* __restrict__ t
   }
 }
 
+// One exhaustive item: the tiles 2 pi and 2 pi + 1 of a pair (two sources per
+// lane) against clusters [c0, c1).
+__device__ __forceinline__ void brute_item(const SlotDesc& D, const SlotState& S, int pi, int c0,
+                                           int c1, float4* s_tgt) {
+  const int lane = threadIdx.x;
+  constexpr int kRows = kCluster / 64;
+  const int sa = 2 * pi * kTile + lane, sb = sa + kTile;
+  const bool va = sa < D.M, vb = sb < D.M;
+  const int ca = va ? sa : D.M - 1, cb = vb ? sb : D.M - 1;
+  const float xa = ldg(D.px, ca), ya = ldg(D.py, ca), za = ldg(D.pz, ca);
+  const float xb = ldg(D.px, cb), yb = ldg(D.py, cb), zb = ldg(D.pz, cb);
+  float4 r[kRows];
+#pragma unroll
+  for (int t = 0; t < kRows; ++t) r[t] = load_global(D.qloc, (size_t)c0 * kCluster + 64 * t + lane);
+  float4 cc = load_global(D.ccen, c0);
+  float ax, ay, az, Wa, bx, by, bz, Wb;
+  lane_point_from(D, S.Teval, va, xa, ya, za, -1, ax, ay, az, Wa);
+  lane_point_from(D, S.Teval, vb, xb, yb, zb, -1, bx, by, bz, Wb);
+  LaneBest La{__builtin_inff(), __builtin_inff(), __builtin_inff(), __builtin_inff(), -1, -1};
+  LaneBest Lb = La;
+  for (int c = c0; c < c1; ++c) {
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < kRows; ++t) s_tgt[64 * t + lane] = r[t];
+    wave_lds_sync();
+    const float4 cur = cc;
+    if (c + 1 < c1) {
+#pragma unroll
+      for (int t = 0; t < kRows; ++t) r[t] = load_global(D.qloc, (size_t)(c + 1) * kCluster + 64 * t + lane);
+      cc = load_global(D.ccen, c + 1);
+    }
+    const float pa[3] = {ax - cur.x, ay - cur.y, az - cur.z};
+    const float pb[3] = {bx - cur.x, by - cur.y, bz - cur.z};
+    filter_cluster_pair(s_tgt, c, pa, pb, cur.w, La, Lb);
+  }
+  // resolution as in the slice kernel, for both sources of the lane
+  int nexact = 0;
+  auto resolve = [&](const LaneBest& Lx, float x, float y, float z, bool vx,
+                     unsigned long long& keyx, bool& ambx) -> bool {
+    const float thr_h = winner_threshold(Lx.H);
+    const bool has = vx && Lx.A >= 0;
+    const bool two = has && Lx.S <= thr_h;
+    ambx = two && Lx.S2 <= thr_h;
+    keyx = ~0ull;
+    if (has && !ambx) {
+      keyx = exact_scan<true>(D.qorg, Lx.A * kBruteGroup, kBruteGroup, x, y, z, keyx);
+      nexact += kBruteGroup;
+      if (two) {
+        keyx = exact_scan<true>(D.qorg, Lx.B * kBruteGroup, kBruteGroup, x, y, z, keyx);
+        nexact += kBruteGroup;
+      }
+    }
+    return has;
+  };
+  unsigned long long ka, kb;
+  bool amba, ambb;
+  const bool hasa = resolve(La, ax, ay, az, va, ka, amba);
+  const bool hasb = resolve(Lb, bx, by, bz, vb, kb, ambb);
+  if (__any(amba || ambb)) {
+    // near-ties: the item's clusters again, exactly, for those lanes
+    const float tha = winner_threshold(La.H), thb = winner_threshold(Lb.H);
+    for (int c = c0; c < c1; ++c) {
+      const float4 blo = load_global(D.clo, c), bhi = load_global(D.chi, c);
+      const bool na = amba && box_lb2(ax, ay, az, blo, bhi) * (1.0f - 0x1.0p-20f) <= tha;
+      const bool nb = ambb && box_lb2(bx, by, bz, blo, bhi) * (1.0f - 0x1.0p-20f) <= thb;
+      if (!__any(na || nb)) continue;
+      wave_lds_sync();
+      for (int t = 0; t < kRows; ++t)
+        s_tgt[64 * t + lane] = load_global(D.qorg, (size_t)c * kCluster + 64 * t + lane);
+      wave_lds_sync();
+      if (na) {
+        ka = exact_scan<false>(s_tgt, 0, kCluster, ax, ay, az, ka);
+        nexact += kCluster;
+      }
+      if (nb) {
+        kb = exact_scan<false>(s_tgt, 0, kCluster, bx, by, bz, kb);
+        nexact += kCluster;
+      }
+    }
+  }
+  if (hasa) atomicMin(&D.keys[sa], ka);
+  if (hasb) atomicMin(&D.keys[sb], kb);
+  int nv = (va ? 1 : 0) + (vb ? 1 : 0);
+  int ne = nexact;
+  for (int o = 32; o > 0; o >>= 1) {
+    nv += __shfl_xor(nv, o, 64);
+    ne += __shfl_xor(ne, o, 64);
+  }
+  if (lane == 0 && D.stats) {
+    unsigned long long* st = D.stats + (blockIdx.x % kQueues) * kStatStride;
+    atomicAdd(&st[0], (unsigned long long)(c1 - c0) * kCluster * (unsigned long long)nv);
+    atomicAdd(&st[1], (unsigned long long)ne);
+  }
+}
+
 __global__ __launch_bounds__(64) void nn_brute_kernel(const SlotDesc* __restrict__ descs,
                                                       const SlotState* __restrict__ states) {
   __shared__ float4 s_tgt[kCluster];
-  const int lane = threadIdx.x;
   const SlotDesc& D = descs[0];
   const SlotState& S = states[0];
   if (S.status != ST_RUNNING || S.reuse) return;
@@ -804,98 +888,34 @@ __global__ __launch_bounds__(64) void nn_brute_kernel(const SlotDesc* __restrict
   const int split = min(ncl, max(1, (kBruteItems + npair - 1) / npair));
   const int len = (ncl + split - 1) / split;
   const int nitems = npair * split;
-  constexpr int kRows = kCluster / 64;
   for (int g = blockIdx.x; g < nitems; g += gridDim.x) {
     const int pi = g / split, k = g - (g / split) * split;
     const int c0 = k * len, c1 = min(ncl, c0 + len);
     if (c0 >= c1) continue;
-    const int sa = 2 * pi * kTile + lane, sb = sa + kTile;
-    const bool va = sa < D.M, vb = sb < D.M;
-    const int ca = va ? sa : D.M - 1, cb = vb ? sb : D.M - 1;
-    const float xa = ldg(D.px, ca), ya = ldg(D.py, ca), za = ldg(D.pz, ca);
-    const float xb = ldg(D.px, cb), yb = ldg(D.py, cb), zb = ldg(D.pz, cb);
-    float4 r[kRows];
-#pragma unroll
-    for (int t = 0; t < kRows; ++t) r[t] = load_global(D.qloc, (size_t)c0 * kCluster + 64 * t + lane);
-    float4 cc = load_global(D.ccen, c0);
-    float ax, ay, az, Wa, bx, by, bz, Wb;
-    lane_point_from(D, S.Teval, va, xa, ya, za, -1, ax, ay, az, Wa);
-    lane_point_from(D, S.Teval, vb, xb, yb, zb, -1, bx, by, bz, Wb);
-    LaneBest La{__builtin_inff(), __builtin_inff(), __builtin_inff(), __builtin_inff(), -1, -1};
-    LaneBest Lb = La;
-    for (int c = c0; c < c1; ++c) {
-      wave_lds_sync();
-#pragma unroll
-      for (int t = 0; t < kRows; ++t) s_tgt[64 * t + lane] = r[t];
-      wave_lds_sync();
-      const float4 cur = cc;
-      if (c + 1 < c1) {
-#pragma unroll
-        for (int t = 0; t < kRows; ++t) r[t] = load_global(D.qloc, (size_t)(c + 1) * kCluster + 64 * t + lane);
-        cc = load_global(D.ccen, c + 1);
-      }
-      const float pa[3] = {ax - cur.x, ay - cur.y, az - cur.z};
-      const float pb[3] = {bx - cur.x, by - cur.y, bz - cur.z};
-      filter_cluster_pair(s_tgt, c, pa, pb, cur.w, La, Lb);
-    }
-    // resolution as in the slice kernel, for both sources of the lane
-    int nexact = 0;
-    auto resolve = [&](const LaneBest& Lx, float x, float y, float z, bool vx,
-                       unsigned long long& keyx, bool& ambx) -> bool {
-      const float thr_h = winner_threshold(Lx.H);
-      const bool has = vx && Lx.A >= 0;
-      const bool two = has && Lx.S <= thr_h;
-      ambx = two && Lx.S2 <= thr_h;
-      keyx = ~0ull;
-      if (has && !ambx) {
-        keyx = exact_scan<true>(D.qorg, Lx.A * kBruteGroup, kBruteGroup, x, y, z, keyx);
-        nexact += kBruteGroup;
-        if (two) {
-          keyx = exact_scan<true>(D.qorg, Lx.B * kBruteGroup, kBruteGroup, x, y, z, keyx);
-          nexact += kBruteGroup;
-        }
-      }
-      return has;
-    };
-    unsigned long long ka, kb;
-    bool amba, ambb;
-    const bool hasa = resolve(La, ax, ay, az, va, ka, amba);
-    const bool hasb = resolve(Lb, bx, by, bz, vb, kb, ambb);
-    if (__any(amba || ambb)) {
-      // near-ties: the slice's clusters again, exactly, for those lanes
-      const float tha = winner_threshold(La.H), thb = winner_threshold(Lb.H);
-      for (int c = c0; c < c1; ++c) {
-        const float4 blo = load_global(D.clo, c), bhi = load_global(D.chi, c);
-        const bool na = amba && box_lb2(ax, ay, az, blo, bhi) * (1.0f - 0x1.0p-20f) <= tha;
-        const bool nb = ambb && box_lb2(bx, by, bz, blo, bhi) * (1.0f - 0x1.0p-20f) <= thb;
-        if (!__any(na || nb)) continue;
-        wave_lds_sync();
-        for (int t = 0; t < kRows; ++t)
-          s_tgt[64 * t + lane] = load_global(D.qorg, (size_t)c * kCluster + 64 * t + lane);
-        wave_lds_sync();
-        if (na) {
-          ka = exact_scan<false>(s_tgt, 0, kCluster, ax, ay, az, ka);
-          nexact += kCluster;
-        }
-        if (nb) {
-          kb = exact_scan<false>(s_tgt, 0, kCluster, bx, by, bz, kb);
-          nexact += kCluster;
-        }
-      }
-    }
-    if (hasa) atomicMin(&D.keys[sa], ka);
-    if (hasb) atomicMin(&D.keys[sb], kb);
-    int nv = (va ? 1 : 0) + (vb ? 1 : 0);
-    int ne = nexact;
-    for (int o = 32; o > 0; o >>= 1) {
-      nv += __shfl_xor(nv, o, 64);
-      ne += __shfl_xor(ne, o, 64);
-    }
-    if (lane == 0 && D.stats) {
-      unsigned long long* st = D.stats + (blockIdx.x % kQueues) * kStatStride;
-      atomicAdd(&st[0], (unsigned long long)(c1 - c0) * kCluster * (unsigned long long)nv);
-      atomicAdd(&st[1], (unsigned long long)ne);
-    }
+    brute_item(D, S, pi, c0, c1, s_tgt);
+  }
+}
+
+// Multi-slot engine, exhaustive method: the items of every searching pair
+// (brute_items per pair, prefixed by the planner), shared out statically.
+__global__ __launch_bounds__(64) void nn_brute_multi_kernel(const SlotDesc* __restrict__ descs,
+                                                            const SlotState* __restrict__ states,
+                                                            const WorkList* __restrict__ wl) {
+  __shared__ float4 s_tgt[kCluster];
+  const int total = wl->b_total;
+  const int na = wl->n_active;
+  for (int g = blockIdx.x; g < total; g += gridDim.x) {
+    const int a = find_slot(wl->b_base, na, g);
+    const int slot = __builtin_amdgcn_readfirstlane(wl->slot[a]);
+    const SlotDesc& D = descs[slot];
+    const SlotState& S = states[slot];
+    const int item = g - wl->b_base[a];
+    const int split = brute_split(D.ncl);
+    const int len = (D.ncl + split - 1) / split;
+    const int pi = item / split, k = item - pi * split;
+    const int c0 = k * len, c1 = min(D.ncl, c0 + len);
+    if (c0 >= c1) continue;
+    brute_item(D, S, pi, c0, c1, s_tgt);
   }
 }
 
@@ -909,6 +929,7 @@ void launch_nn(const SlotDesc* descs, const SlotState* states, WorkList* wl, int
                      states, wl);
   if (!single) hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl);
   hipLaunchKernelGGL(nn_slice_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
+  if (!single) hipLaunchKernelGGL(nn_brute_multi_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
 }
 
 }  // namespace icp

@@ -411,25 +411,33 @@ __global__ void fill_u64_kernel(unsigned long long* __restrict__ p, int n, unsig
 __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__ descs,
                                                     const SlotState* __restrict__ states,
                                                     WorkList* __restrict__ wl, int capacity) {
-  __shared__ int s_act[1024], s_nn[1024], s_epi[1024];
+  __shared__ int s_act[1024], s_nn[1024], s_epi[1024], s_b[1024];
   const int t = threadIdx.x;
-  int act = 0, nn = 0, ep = 0;
+  int act = 0, nn = 0, ep = 0, bi = 0;
   if (t < capacity && states[t].status == ST_RUNNING) {
+    const SlotDesc& D = descs[t];
     act = 1;
-    nn = (states[t].reuse || !states[t].cull) ? 0 : descs[t].ntile;
-    if (nn) {
-      descs[t].scount[0] = 0;
-      descs[t].scount[1] = 0;
+    // cluster method: cull items (tiles) when the candidate lists are rebuilt;
+    // exhaustive method: its own items whenever the pair searches
+    const bool search = !states[t].reuse;
+    if (D.method == NN_BRUTE) {
+      bi = search ? brute_items(D.ntile, D.ncl) : 0;
+    } else {
+      nn = (search && states[t].cull) ? D.ntile : 0;
+      if (nn) {
+        D.scount[0] = 0;
+        D.scount[1] = 0;
+      }
     }
-    ep = descs[t].nepi;
+    ep = D.nepi;
   }
-  s_act[t] = act; s_nn[t] = nn; s_epi[t] = ep;
+  s_act[t] = act; s_nn[t] = nn; s_epi[t] = ep; s_b[t] = bi;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
-    int a = 0, b = 0, c = 0;
-    if (t >= o) { a = s_act[t - o]; b = s_nn[t - o]; c = s_epi[t - o]; }
+    int a = 0, b = 0, c = 0, e = 0;
+    if (t >= o) { a = s_act[t - o]; b = s_nn[t - o]; c = s_epi[t - o]; e = s_b[t - o]; }
     __syncthreads();
-    s_act[t] += a; s_nn[t] += b; s_epi[t] += c;
+    s_act[t] += a; s_nn[t] += b; s_epi[t] += c; s_b[t] += e;
     __syncthreads();
   }
   if (t < kQueues) {
@@ -441,6 +449,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__
     wl->slot[pos] = t;
     wl->nn_base[pos] = s_nn[t] - nn;
     wl->epi_base[pos] = s_epi[t] - ep;
+    wl->b_base[pos] = s_b[t] - bi;
   }
   if (t == 1023) {
     wl->single = 0;
@@ -450,6 +459,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__
     wl->epi_total = s_epi[t];
     wl->nn_base[s_act[t]] = s_nn[t];
     wl->epi_base[s_act[t]] = s_epi[t];
+    wl->b_total = s_b[t];
+    wl->b_base[s_act[t]] = s_b[t];
   }
 }
 
