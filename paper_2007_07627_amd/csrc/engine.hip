@@ -561,6 +561,13 @@ struct Engine {
     return hipGetLastError() == hipSuccess;
   }
 
+  // Wait for the admission streams: after a failed admission, before the
+  // host sources of its uploads may be freed.
+  void drain() {
+    (void)hipStreamSynchronize(up);
+    (void)hipStreamSynchronize(side);
+  }
+
   // Make the slot RUNNING on the pass stream once its setup has completed.
   bool activate(int s) {
     hipEvent_t ev;
@@ -720,7 +727,7 @@ static icp_status run_sync(icp_ctx* ctx, OwnedRequest& r, icp_result* out, void*
     (void)hipEventDestroy(ev);
   }
   bool oom = false;
-  if (!E.admit(0, r, &oom)) { E.release(0); return ICP_ERR_DEVICE; }
+  if (!E.admit(0, r, &oom)) { E.drain(); E.release(0); return ICP_ERR_DEVICE; }
   if (oom) return ICP_ERR_OOM;
   if (!E.activate(0)) { E.release(0); return ICP_ERR_DEVICE; }
   const bool plain = !r.query && !r.eval && r.prm.engine == ICP_ENGINE_PLAIN;
@@ -873,7 +880,7 @@ static void scheduler(icp_ctx* ctx) {
         break;
       }
       if (!adm || !E.activate(s)) {
-        (void)hipStreamSynchronize(E.side);
+        E.drain();
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->state[req->ticket] = 4;
         E.release(s);
@@ -893,7 +900,7 @@ static void scheduler(icp_ctx* ctx) {
     if (ok) held.clear();
     if (ok && running > 0) E.collect_profile(R);
     if (!ok) {
-      (void)hipStreamSynchronize(E.side);
+      E.drain();
       std::lock_guard<std::mutex> lk(ctx->mu);
       ctx->failed = true;
       ctx->stop = true;
@@ -1186,7 +1193,7 @@ icp_status icp_nu_min_auto(icp_ctx* ctx, const float* Q, const float* Qn, int64_
   Engine& E = ctx->sync_eng;
   if (hipSetDevice(ctx->device) != hipSuccess) return ICP_ERR_DEVICE;
   bool oom = false;
-  if (!E.admit(0, r, &oom)) { E.release(0); return ICP_ERR_DEVICE; }
+  if (!E.admit(0, r, &oom)) { E.drain(); E.release(0); return ICP_ERR_DEVICE; }
   if (oom) return ICP_ERR_OOM;
   SlotState S;
   const bool ok = E.read_state(0, &S);
@@ -1210,7 +1217,7 @@ icp_status icp_estimate_normals(icp_ctx* ctx, const float* Q, int64_t N, float* 
   Engine& E = ctx->sync_eng;
   if (hipSetDevice(ctx->device) != hipSuccess) return ICP_ERR_DEVICE;
   bool oom = false;
-  if (!E.admit(0, r, &oom)) { E.release(0); return ICP_ERR_DEVICE; }
+  if (!E.admit(0, r, &oom)) { E.drain(); E.release(0); return ICP_ERR_DEVICE; }
   if (oom) return ICP_ERR_OOM;
   const Layout& L = E.hs[0].L;
   char* b = E.hs[0].mem;
