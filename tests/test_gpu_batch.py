@@ -59,6 +59,26 @@ def test_batch_equals_alone_bitwise(ctx):
         assert g["latency_ms"] > 0
 
 
+def test_batch_exhaustive_edge_shapes(ctx):
+    # exhaustive-method pairs in the multi-slot engine: odd tile counts (a tile
+    # pair whose second tile is missing or partial), single and ragged clusters;
+    # each must equal the pair registered alone (one-slot exhaustive kernel)
+    shapes = [(10, 10), (64, 200), (65, 129), (130, 4096), (3000, 20), (4097, 4096)]
+    announce(f"batch of exhaustive pairs {shapes} vs alone")
+    reqs = []
+    for i, (m, n) in enumerate(shapes):
+        d = synth.fast_icp_pair(synth.rng_for(41, i), n=max(m, n))
+        P = np.ascontiguousarray(d["P"][:m])
+        Q = np.ascontiguousarray(d["Q"][:n])
+        prm = B.icp_params_default(B.ICP_P2P_WELSCH, nu_min=1e-3, nn=B.ICP_NN_BRUTE)
+        reqs.append((P, Q, None, prm))
+    res = _wait(ctx, B.icp_batch_submit(ctx, reqs))
+    for (P, Q, Qn, prm), g in zip(reqs, res):
+        a = B.icp_register(ctx, P, Q, Qn, prm)
+        assert np.array_equal(g["T"], a["T"]), (len(P), len(Q))
+        assert g["nn_passes"] == a["nn_passes"] and g["energy"] == a["energy"]
+
+
 def test_batch_alone_vs_mix_and_oracle(ctx):
     reqs = _requests(6, seed_config=41)
     d0, r0 = reqs[0]
