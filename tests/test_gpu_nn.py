@@ -111,6 +111,20 @@ def test_nn_full_size_sampled(ctx, method):
     assert np.array_equal(gi[sel], oi) and np.array_equal(gd[sel], od)
 
 
+@pytest.mark.parametrize("m,n", [(200_000, 500_000), (1_000_000, 1_000_000)])
+def test_nn_height_field_full_size_sampled(ctx, m, n):
+    """The point-to-plane workload's size (200k sources, 500k targets) and the
+    largest served request (1M x 1M), height field with outliers, cluster
+    search in one call; the oracle checks a seeded sample of 1500 sources."""
+    d = synth.height_field_pair(synth.rng_for(3, 7), m=m, n=n)
+    announce(f"nn height field full-size sampled m={m} n={n}")
+    T = d["T_gt"]
+    gi, gd = B.icp_nn_query(ctx, d["P"], d["Q"], T, B.ICP_NN_CLUSTER)
+    sel = np.random.default_rng(1).choice(m, 1500, replace=False)
+    oi, od = oracle.nn_query(d["P"][sel], d["Q"], T)
+    assert np.array_equal(gi[sel], oi) and np.array_equal(gd[sel], od)
+
+
 @pytest.mark.parametrize("method", [B.ICP_NN_CLUSTER])
 def test_nn_scattered_tiles_long_ranges(ctx, method):
     """Sources scattered over a box much larger than the target surface make
