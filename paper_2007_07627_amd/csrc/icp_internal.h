@@ -195,7 +195,7 @@ struct WorkList {
 
 // Exhaustive method in the multi-slot engine: one item = a pair of 64-source
 // tiles against a range of about kBruteItemClusters clusters.
-constexpr int kBruteItemClusters = 32;
+constexpr int kBruteItemClusters = 8;
 __host__ __device__ inline int brute_split(int ncl) {
   return ncl > 0 ? (ncl + kBruteItemClusters - 1) / kBruteItemClusters : 1;
 }
