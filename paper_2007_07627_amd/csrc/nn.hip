@@ -719,7 +719,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
 // target read from LDS serves two pairs, which halves the LDS traffic per
 // pair. Items are (pair of tiles, cluster range) on a fixed grid of about
 // kBruteItems, shared out statically (they cost the same).
-constexpr int kBruteItems = 4096;
+constexpr int kBruteItems = 8192;
 
 // Folds one chunk into a lane's state (the bookkeeping of filter_chunk): m is
 // the chunk's minimum of h - pl . ql, v = 2 m + |pl|^2 with bounds lo, hi.
