@@ -41,13 +41,19 @@ def log(msg):
 
 
 def sources_digest():
-    """sha256 over the closest-point kernel sources (the counters in the
-    traffic summary hold only for the sources they were taken from)."""
+    """sha256 over the code of the closest-point kernel sources (the counters
+    in the traffic summary hold only for the code they were taken from): line
+    comments, trailing blanks and empty lines are left out, so that a change
+    of comments alone keeps the record valid."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            for line in f:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

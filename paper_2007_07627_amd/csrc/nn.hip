@@ -714,11 +714,13 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
 }
 
 // ------------------------------------------------------------------ exhaustive kernel
-// One-slot engine, exhaustive method: every target for every source, without
-// a cull pass. The wavefront holds two tiles (two sources per lane), so every
-// target read from LDS serves two pairs, which halves the LDS traffic per
-// pair. Items are (pair of tiles, cluster range) on a fixed grid of about
-// kBruteItems, shared out statically (they cost the same).
+// Exhaustive method: every target for every source, without a cull pass. The
+// wavefront holds two tiles (two sources per lane), so every target read from
+// LDS serves two pairs, which halves the LDS traffic per pair. Items are
+// (pair of tiles, cluster range), shared out statically (they cost the same):
+// in the one-slot engine on a fixed grid of about kBruteItems, in the
+// multi-slot engine brute_items per pair (about kBruteItemClusters clusters
+// per item).
 constexpr int kBruteItems = 8192;
 
 // Folds one chunk into a lane's state (the bookkeeping of filter_chunk): m is
