@@ -19,6 +19,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 
 P2P_L2, P2P_WELSCH, P2PL_WELSCH, P2PL_L2 = 0, 1, 2, 3
 FLAG_CONVERGED, FLAG_MAX_ITER, FLAG_ZERO_WEIGHT, FLAG_DEGENERATE, FLAG_AA_SINGULAR = 1, 2, 4, 8, 16
+# trace row reasons (column 2): stage start, iterate, safeguard revert, line-search trial
+ROW_STAGE, ROW_ITER, ROW_REVERT, ROW_TRIAL = 1, 2, 3, 4
 
 
 def build() -> str:

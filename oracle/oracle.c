@@ -701,6 +701,7 @@ typedef struct {
   int nn_passes, evaluations;
   double *trace;
   int trace_cap, trace_len;
+  int reason;      /* ORC_ROW_* of the next evaluation (recorded in the trace) */
   double *etrace;
   int etrace_cap, etrace_len;
 } orc_ctx;
@@ -726,7 +727,7 @@ static void ctx_record(orc_ctx *c, double E, double nu, int reused, const double
     double *row = c->trace + 20 * c->trace_len;
     row[0] = E;
     row[1] = nu;
-    row[2] = -1.0;
+    row[2] = c->reason;
     row[3] = reused;
     memcpy(row + 4, T, sizeof(double) * 16);
     c->trace_len++;
@@ -965,6 +966,7 @@ static void register_p2p(orc_ctx *c, const orc_params *prm, double nu0, orc_resu
     const int kstart = k - 1;
     double Eprev = INFINITY;
     res->stages++;
+    c->reason = ORC_ROW_STAGE;
     ev = eval_p2p(c, Tkm1, nu); /* re-weighting at the current transform */
     if (ev.flags & ORC_FLAG_ZERO_WEIGHT) {
       res->flags |= ORC_FLAG_ZERO_WEIGHT;
@@ -983,6 +985,7 @@ static void register_p2p(orc_ctx *c, const orc_params *prm, double nu0, orc_resu
         F[(k - 1) % HIST][a] = lp[a] - lq[a];
       }
     }
+    c->reason = ORC_ROW_ITER;
     ev = eval_p2p(c, Tk, nu);
     int is_aa = 0, converged = 0;
     while (k - kstart <= Inu) {
@@ -992,6 +995,7 @@ static void register_p2p(orc_ctx *c, const orc_params *prm, double nu0, orc_resu
       double E = ev.E;
       if (m > 0 && E >= Eprev) { /* safeguard: revert to the un-accelerated iterate */
         memcpy(Tk, Tp, sizeof Tk);
+        c->reason = ORC_ROW_REVERT;
         ev = eval_p2p(c, Tk, nu);
         E = ev.E;
         res->aa_rejected++;
@@ -1022,6 +1026,7 @@ static void register_p2p(orc_ctx *c, const orc_params *prm, double nu0, orc_resu
         is_aa = 1;
       }
       memcpy(Tk, Tn, sizeof Tk);
+      c->reason = ORC_ROW_ITER;
       ev = eval_p2p(c, Tk, nu);
       k++;
     }
@@ -1059,6 +1064,7 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
     const int kstart = k - 1;
     double Eprev = INFINITY;
     res->stages++;
+    c->reason = ORC_ROW_STAGE;
     orc_evalres ev = eval_p2pl(c, xkm1, nu);
     if (ev.flags & (ORC_FLAG_ZERO_WEIGHT | ORC_FLAG_DEGENERATE)) {
       res->flags |= ev.flags;
@@ -1072,6 +1078,7 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
       F[(k - 1) % HIST][a] = xstar[a] - xkm1[a];
     }
     memcpy(xk, xstar, sizeof xk);
+    c->reason = ORC_ROW_ITER;
     ev = eval_p2pl(c, xk, nu);
     Ecur = ev.E;
     int converged = 0, is_aa = 0;
@@ -1086,6 +1093,7 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
         for (int l = 1; l <= prm->max_line_search; ++l) {
           double xt[6];
           for (int a = 0; a < 6; ++a) xt[a] = xkm1[a] + tau * (xstar[a] - xkm1[a]);
+          c->reason = ORC_ROW_TRIAL;
           orc_evalres et = eval_p2pl(c, xt, nu);
           res->line_search_trials++;
           if (et.E < E) {
@@ -1137,6 +1145,7 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
       memcpy(xkm1, xk, sizeof xkm1);
       memcpy(xstar, xs_next, sizeof xstar);
       memcpy(xk, xn, sizeof xk);
+      c->reason = ORC_ROW_ITER;
       ev = eval_p2pl(c, xk, nu);
       Ecur = ev.E;
       k++;

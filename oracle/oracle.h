@@ -25,6 +25,9 @@ extern "C" {
  * eq. GNMapping with unit weights, one stage. */
 enum { ORC_P2P_L2 = 0, ORC_P2P_WELSCH = 1, ORC_P2PL_WELSCH = 2, ORC_P2PL_L2 = 3 };
 
+/* why the registration evaluated a transform (trace rows) */
+enum { ORC_ROW_STAGE = 1, ORC_ROW_ITER = 2, ORC_ROW_REVERT = 3, ORC_ROW_TRIAL = 4 };
+
 enum {
   ORC_FLAG_CONVERGED = 1u,
   ORC_FLAG_MAX_ITER = 2u,
@@ -116,8 +119,11 @@ int orc_estimate_normals(const float *Q, int64_t N, float *normals);
 /* Full registration: Fast ICP (L2 + AA), Algorithm 1, Algorithm 2, and
  * classical point-to-plane ICP. Qn may be NULL except for the point-to-plane
  * modes. trace (optional) receives one
- * row of 20 doubles per evaluation [E, nu, -1, reused, T(16)], up to
+ * row of 20 doubles per evaluation [E, nu, reason, reused, T(16)], up to
  * trace_cap rows (the setup pass that only feeds the median is not a row);
+ * reason is ORC_ROW_STAGE (the stage's first evaluation, at T^(k-1)),
+ * ORC_ROW_ITER (an iterate T^(k)), ORC_ROW_REVERT (Algorithm 1's safeguard:
+ * the un-accelerated T') or ORC_ROW_TRIAL (an Algorithm 2 line-search trial);
  * etrace (optional) receives (stage, accepted energy)
  * for every inner iteration, up to etrace_cap pairs.
  * Returns 0 on success, -1 on invalid arguments. */

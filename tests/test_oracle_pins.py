@@ -164,7 +164,7 @@ def test_exp_matches_scipy_expm():
 
 def test_log_matches_scipy_logm_and_round_trips():
     rng = np.random.default_rng(7)
-    for ang in [0.0, 1e-8, 1e-4, 0.01, 0.5, 1.5, 3.0, math.pi - 1e-4]:
+    for ang in [0.0, 1e-8, 1e-4, 2e-3, 0.01, 0.05, 0.1, 0.15, 0.19, 0.25, 0.5, 1.5, 3.0, math.pi - 1e-4]:
         for _ in range(4):
             d = rng.normal(size=3)
             d = d / np.linalg.norm(d) * ang
@@ -175,6 +175,8 @@ def test_log_matches_scipy_logm_and_round_trips():
             if 0.01 <= ang <= 3.0:
                 L = np.real(scipy.linalg.logm(T))
                 assert np.abs(_twist_matrix(got) - L).max() < 1e-10
+                # the rotation angle itself, from the exact inverse of Rodrigues
+                assert abs(np.linalg.norm(got[:3]) - ang) <= 1e-14 * max(1.0, ang)
             assert np.abs(oracle.se3_exp(got) - T).max() < 1e-13
 
 
@@ -412,12 +414,203 @@ def test_fast_icp_matches_plain_icp_with_fewer_passes():
     assert pa <= pb
 
 
-def test_alg2_monotone_where_line_search_succeeds():
-    d = synth.height_field_pair(synth.rng_for(3, 1), m=2000, n=5000)
+def _alg2_iterations(tr):
+    """Split an Algorithm 2 trace into stages of iterations: per iteration the
+    iterate's row and the line-search trial rows that follow it."""
+    stages = []
+    for r in tr:
+        why = int(r[2])
+        if why == oracle.ROW_STAGE:
+            stages.append({"start": r, "its": []})
+        elif why == oracle.ROW_ITER:
+            stages[-1]["its"].append({"row": r, "trials": []})
+        elif why == oracle.ROW_TRIAL:
+            stages[-1]["its"][-1]["trials"].append(r)
+    return stages
+
+
+def _accepted(it):
+    """Energy and parameters Algorithm 2 keeps for an iteration: the iterate,
+    or the first trial that lowers the lowest energy seen."""
+    E, x = it["row"][0], oracle.se3_log(it["row"][4:])
+    for t in it["trials"]:
+        if t[0] < E:
+            E, x = t[0], oracle.se3_log(t[4:])
+    return E, x
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_alg2_monotone_where_line_search_succeeds(seed):
+    """Within a nu stage, an iteration whose iterate lowered the energy or
+    whose line search found a lower energy than the previous iteration's ends
+    below it (Alg. 2, Sec. 5); only a failed line search may leave it higher."""
+    d = synth.height_field_pair(synth.rng_for(3, 400 + seed), m=1500, n=3000)
     r = oracle.register(d["P"], d["Q"], d["Qn"], mode=oracle.P2PL_WELSCH, anderson_m=6,
-                        nu_min=d["nu_min"], etrace_cap=5000)
+                        nu_min=d["nu_min"], trace_cap=5000, etrace_cap=5000)
     assert r["flags"] & (oracle.FLAG_CONVERGED | oracle.FLAG_MAX_ITER)
     assert metrics.rmse(d["T_gt"], r["T"], d["P"]) < 2e-3
+    succeeded = failed = 0
+    for st in _alg2_iterations(r["trace"]):
+        prev = None
+        for it in st["its"]:
+            E, _ = _accepted(it)
+            if prev is not None:
+                ok = it["row"][0] < prev or any(t[0] < prev for t in it["trials"])
+                if ok:
+                    assert E < prev
+                    succeeded += 1 if it["trials"] else 0
+                else:
+                    failed += 1
+            prev = E
+    assert succeeded > 0 and failed > 0
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_alg2_line_search_halves_tau_from_the_previous_iterate(seed):
+    """Alg. 2: trial = T^(k-1) + tau (T*^(k) - T^(k-1)) with tau = 1, 1/2, 1/4...
+    So consecutive trial differences halve, and the point the trials converge
+    to (2 x_2 - x_1) is the previous iteration's accepted parameters, not the
+    rejected iterate."""
+    d = synth.height_field_pair(synth.rng_for(3, 400 + seed), m=1500, n=3000)
+    r = oracle.register(d["P"], d["Q"], d["Qn"], mode=oracle.P2PL_WELSCH, anderson_m=6,
+                        nu_min=d["nu_min"], trace_cap=5000)
+    runs = 0
+    for st in _alg2_iterations(r["trace"]):
+        for j, it in enumerate(st["its"]):
+            tr = it["trials"]
+            if len(tr) < 3:
+                continue
+            x = [oracle.se3_log(t[4:]) for t in tr]
+            d12 = np.linalg.norm(x[0] - x[1])
+            if d12 < 1e-7:
+                continue
+            assert j > 0  # the first iteration of a stage never searches (E_prev = inf)
+            for l in range(1, len(x) - 1):
+                assert np.linalg.norm((x[l - 1] - x[l]) - 2.0 * (x[l] - x[l + 1])) <= 1e-6 * d12
+            anchor = 2.0 * x[1] - x[0]
+            _, prev_x = _accepted(st["its"][j - 1])
+            assert np.linalg.norm(anchor - prev_x) <= 1e-6 * d12
+            assert np.linalg.norm(anchor - oracle.se3_log(it["row"][4:])) > 0.1 * d12
+            runs += 1
+    assert runs >= 3
+
+
+def _brute_residuals(P, Q, Qn=None):
+    """Closest points by a numpy FP64 distance matrix (independent of the
+    oracle's FP32 scan), residuals at T0 = I: squared distances, or
+    point-to-plane distances with the closest target's normal."""
+    P64, Q64 = np.asarray(P, np.float64), np.asarray(Q, np.float64)
+    d2 = ((P64[:, None, :] - Q64[None, :, :]) ** 2).sum(-1)
+    j = d2.argmin(1)
+    if Qn is None:
+        return d2[np.arange(len(P)), j]
+    return ((P64 - Q64[j]) * np.asarray(Qn, np.float64)[j]).sum(1)
+
+
+def test_nu_max_is_three_medians_point_to_point():
+    """Sec. 4.3: nu_max = 3 x the median closest-point distance at T0."""
+    d = synth.partial_sphere_pair(synth.rng_for(2, 410), m=601, n=800)
+    r = oracle.register(d["P"], d["Q"], mode=oracle.P2P_WELSCH, anderson_m=5, nu_min=d["nu_min"],
+                        trace_cap=5000)
+    ref = 3.0 * math.sqrt(np.sort(_brute_residuals(d["P"], d["Q"]))[601 // 2])
+    assert int(r["trace"][0, 2]) == oracle.ROW_STAGE
+    assert abs(r["trace"][0, 1] - ref) <= 1e-6 * ref
+
+
+def test_nu_max_is_three_median_plane_distances():
+    """Sec. 5: nu_max = 3 x the median |point-to-plane distance| at T0."""
+    d = synth.height_field_pair(synth.rng_for(3, 410), m=601, n=900)
+    r = oracle.register(d["P"], d["Q"], d["Qn"], mode=oracle.P2PL_WELSCH, anderson_m=6,
+                        nu_min=d["nu_min"], trace_cap=5000)
+    ref = 3.0 * np.sort(np.abs(_brute_residuals(d["P"], d["Q"], d["Qn"])))[601 // 2]
+    assert abs(r["trace"][0, 1] - ref) <= 1e-6 * ref
+
+
+@pytest.mark.parametrize("mode", [oracle.P2P_WELSCH, oracle.P2PL_WELSCH])
+def test_nu_schedule_halves_per_stage_down_to_nu_min(mode):
+    """Alg. 1 / Alg. 2: each stage starts with nu = max(nu / 2, nu_min), the
+    last stage runs at nu_min, and every evaluation of a stage uses its nu."""
+    if mode == oracle.P2PL_WELSCH:
+        d = synth.height_field_pair(synth.rng_for(3, 411), m=1200, n=2500)
+        r = oracle.register(d["P"], d["Q"], d["Qn"], mode=mode, anderson_m=6, nu_min=d["nu_min"],
+                            trace_cap=5000)
+    else:
+        d = synth.partial_sphere_pair(synth.rng_for(2, 411), m=1200, n=1500)
+        r = oracle.register(d["P"], d["Q"], mode=mode, anderson_m=5, nu_min=d["nu_min"], trace_cap=5000)
+    tr = r["trace"]
+    starts = np.flatnonzero(tr[:, 2] == oracle.ROW_STAGE)
+    nus = tr[starts, 1]
+    assert len(nus) == r["stages"] >= 4
+    for a, b in zip(nus[:-1], nus[1:]):
+        assert b == max(a / 2.0, d["nu_min"])
+    assert nus[-1] == d["nu_min"] == r["nu_final"] and nus[-2] > d["nu_min"]
+    for s0, s1 in zip(starts, list(starts[1:]) + [len(tr)]):
+        assert (tr[s0:s1, 1] == tr[s0, 1]).all()
+
+
+def test_alg2_stage_caps_six_plus_stage_up_to_ten():
+    """Sec. 5: I_nu = 6 for the first stage, one more per stage, at most 10.
+    With a threshold no step can meet, every stage runs to its cap."""
+    d = synth.height_field_pair(synth.rng_for(3, 412), m=1000, n=2000)
+    r = oracle.register(d["P"], d["Q"], d["Qn"], mode=oracle.P2PL_WELSCH, anderson_m=6,
+                        nu_min=d["nu_min"], eps=1e-300, etrace_cap=5000)
+    st = r["etrace"][:, 0].astype(int)
+    counts = np.bincount(st)
+    assert len(counts) == r["stages"] >= 6
+    assert counts.tolist() == [min(6 + s, 10) for s in range(len(counts))]
+    assert r["flags"] & oracle.FLAG_MAX_ITER
+
+
+def test_alg1_stage_cap_counts_inner_iterations():
+    """Alg. 1 with I_nu = 7 and a threshold no step can meet: seven inner
+    iterations per stage in every stage."""
+    d = synth.partial_sphere_pair(synth.rng_for(2, 412), m=800, n=1000)
+    r = oracle.register(d["P"], d["Q"], mode=oracle.P2P_WELSCH, anderson_m=5, nu_min=d["nu_min"],
+                        eps=1e-300, iter_first=7, iter_cap=7, etrace_cap=5000)
+    counts = np.bincount(r["etrace"][:, 0].astype(int))
+    assert len(counts) == r["stages"] >= 4 and (counts == 7).all()
+
+
+@pytest.mark.parametrize("seed", [33, 34])
+def test_welsch_point_to_plane_step_is_weighted_least_squares(seed):
+    """One Welsch point-to-plane map application at T (eq. ProxyPointToPlane-
+    Alignment, eq. GNSystem): with B_i the signed plane distances on the
+    closest points at T, the energy is sum psi_nu(B_i) = sum 1 - exp(-B_i^2 /
+    (2 nu^2)) (eq. welsch), and the update is the Gauss-Newton step of
+    sum gamma_i B_i(xi)^2 with the weights gamma_i = exp(-B_i^2 / (2 nu^2))
+    frozen at T. Computed here another way: numpy closest points, scipy expm,
+    a central-difference Jacobian and numpy lstsq on sqrt(gamma)-scaled rows."""
+    rng = np.random.default_rng(seed)
+    Q = rng.normal(size=(400, 3)).astype(np.float32)
+    Qn = rng.normal(size=(400, 3))
+    Qn = (Qn / np.linalg.norm(Qn, axis=1, keepdims=True)).astype(np.float32)
+    P = (rng.normal(size=(150, 3)) * 0.9).astype(np.float32)
+    xi = rng.normal(scale=0.05, size=6)
+    T = _expm_twist(xi)
+    Pt = (P.astype(np.float64) @ T[:3, :3].T + T[:3, 3]).astype(np.float32).astype(np.float64)
+    d2 = ((Pt[:, None, :] - Q[None, :, :].astype(np.float64)) ** 2).sum(-1)
+    j = d2.argmin(1)
+    srt = np.sort(d2, 1)
+    assert (srt[:, 1] - srt[:, 0] > 1e-6 * srt[:, 1]).all()  # no near-ties
+    q, n, p = Q[j].astype(np.float64), Qn[j].astype(np.float64), P.astype(np.float64)
+
+    def B(x):
+        Tx = _expm_twist(x)
+        return ((p @ Tx[:3, :3].T + Tx[:3, 3] - q) * n).sum(1)
+
+    b0 = B(xi)
+    nu = float(np.median(np.abs(b0)))  # weights spread over (0, 1]
+    g = np.exp(-b0 ** 2 / (2 * nu * nu))
+    assert g.min() < 0.2 and g.max() > 0.9
+    E, Tn, fl = oracle.eval_map(P, Q, Qn, oracle.P2PL_WELSCH, T, nu)
+    assert fl == 0
+    Eref = (1.0 - np.exp(-b0 ** 2 / (2 * nu * nu))).sum()
+    assert abs(E - Eref) <= 1e-12 * Eref
+    h = 1e-6
+    J = np.stack([(B(xi + h * e) - B(xi - h * e)) / (2 * h) for e in np.eye(6)], 1)
+    w = np.sqrt(g)
+    step = np.linalg.lstsq(J * w[:, None], b0 * w, rcond=None)[0]
+    assert np.abs(Tn - _expm_twist(xi - step)).max() < 1e-8
 
 
 def test_welsch_large_nu_reduces_to_l2():
