@@ -56,8 +56,10 @@ typedef enum {
  * bit-exact result: the FP32 transformed point p' = fl32(T p) (FP64 fused
  * order), d2 = fma(dz,dz, fma(dy,dy, dx*dx)) with FP32 differences, minimum
  * d2, ties to the lowest target index. BRUTE scans every target; CLUSTER
- * prunes with a Morton-ordered cluster index (a uniform 1024^3 cell grid over
- * the target's bounding box); AUTO picks by size. */
+ * prunes with a Hilbert-ordered cluster index (Hilbert keys of a 1024^3 cell
+ * grid over the target's bounding box, 128 targets per cluster); AUTO picks
+ * by size. The batch engine searches a BRUTE pair above about 2^37 source x
+ * target pairs per pass with CLUSTER instead (the result is the same). */
 typedef enum { ICP_NN_AUTO = 0, ICP_NN_BRUTE = 1, ICP_NN_CLUSTER = 2 } icp_nn_method;
 
 /* How icp_register drives the iterations: GRAPH keeps the per-pair state on
@@ -161,14 +163,20 @@ icp_status icp_eval(icp_ctx *ctx, const float *P, int64_t M, const float *Q, con
                     int64_t N, icp_mode mode, const double T[16], double nu,
                     double *energy_out, double T_out[16], unsigned *flags_out);
 
-/* icp_register that also records one row of 20 doubles per pass into the
- * caller's host array trace_out (capacity trace_cap rows): the pass's energy
- * (sum of psi_nu, eq. welsch, or sum of squares for L2), its nu (0 for L2),
- * the solver position that requested it, 1 if the closest-point search was
- * reused at an unchanged transform, and the 16 entries of the evaluated
- * transform. *trace_len receives the number of rows written (passes beyond
- * the capacity are not recorded). For convergence plots (energy against
- * iteration, Sec. 4.2) and for replaying the evaluated transforms. */
+/* icp_register that also records one row of ICP_TRACE_ROW (36) doubles per
+ * pass into the caller's host array trace_out (capacity trace_cap rows):
+ * [0] the pass's energy (sum of psi_nu, eq. welsch, or sum of squares for L2),
+ * [1] its nu (0 for L2), [2] the solver position that requested it (0 first
+ * pass, 1 stage start at T^(k-1), 2 iterate T^(k), 3 safeguard revert to T',
+ * 4 line-search trial), [3] 1 if the closest-point search was reused at an
+ * unchanged transform, [4..19] the evaluated transform (row-major 4 x 4),
+ * [20..35] the un-accelerated update computed from this evaluation: T' of
+ * eq. WelschAlignment (point-to-point; T itself when every weight is zero)
+ * or the Gauss-Newton parameters xi* of eq. GNMapping in [20..25]
+ * (point-to-plane). *trace_len receives the number of rows written (passes
+ * beyond the capacity are not recorded). For convergence plots (energy
+ * against iteration, Sec. 4.2) and for replaying a registration step by step. */
+#define ICP_TRACE_ROW 36
 icp_status icp_register_trace(icp_ctx *ctx, const float *P, int64_t M, const float *Q,
                               const float *Qn, int64_t N, const icp_params *params,
                               icp_result *out, double *trace_out, int trace_cap,

@@ -20,6 +20,7 @@ ICP_NN_AUTO, ICP_NN_BRUTE, ICP_NN_CLUSTER = 0, 1, 2
 ICP_ENGINE_GRAPH, ICP_ENGINE_PLAIN = 0, 1
 ICP_FLAG_CONVERGED, ICP_FLAG_MAX_ITER, ICP_FLAG_ZERO_WEIGHT = 1, 2, 4
 ICP_FLAG_DEGENERATE, ICP_FLAG_AA_SINGULAR = 8, 16
+ICP_TRACE_ROW = 36
 
 EXPORTED = ["icp_create", "icp_destroy", "icp_params_default", "icp_params_classical", "icp_register", "icp_register_trace",
             "icp_eval", "icp_trace_items",
@@ -178,12 +179,13 @@ def icp_register(ctx, P, Q, Qn=None, params: icp_params | None = None, raw=False
 
 
 def icp_register_trace(ctx, P, Q, Qn=None, params: icp_params | None = None, cap: int = 100000):
-    """Registration plus the per-pass trace: rows [E, nu, state, reuse, T(16)]."""
+    """Registration plus the per-pass trace: rows [E, nu, state, reuse, T(16),
+    update(16)] (ICP_TRACE_ROW doubles)."""
     P, Q = _f32(P), _f32(Q)
     Qn = None if Qn is None else _f32(Qn)
     params = params or icp_params_default()
     r = icp_result()
-    tr = np.zeros((cap, 20))
+    tr = np.zeros((cap, ICP_TRACE_ROW))
     n = C.c_int(0)
     rc = lib().icp_register_trace(ctx, _ptr(P), P.shape[0], _ptr(Q), _ptr(Qn), Q.shape[0],
                                   C.byref(params), C.byref(r), tr.ctypes.data, cap, C.byref(n))

@@ -549,6 +549,8 @@ struct Engine {
     icp_nn_method meth = r.query ? r.qmethod : r.prm.nn;
     if (meth == ICP_NN_AUTO) meth = ((double)L.M * L.N <= 64.0e6) ? ICP_NN_BRUTE : ICP_NN_CLUSTER;
     D.method = meth == ICP_NN_BRUTE ? NN_BRUTE : NN_CLUSTER;
+    if (!single && D.method == NN_BRUTE && brute_items64(L.ntile, L.ncl) > kMaxBruteItemsPerPair)
+      D.method = NN_CLUSTER;
     if (single) brute = D.method == NN_BRUTE;
     D.mode = S.mode;
     HIP_OK(hipMemcpyAsync(d_desc + s, &D, offsetof(SlotDesc, rho_max), hipMemcpyHostToDevice, up));
@@ -620,6 +622,7 @@ struct icp_ctx {
   int passes_per_replay = 4;
   int max_slots = 256;
   int running = 0;
+  int admitting = 0;    // popped from the queue, not yet running or finished
   std::vector<int> last_items;  // per NN work item of the last traced registration's last pass
 };
 
@@ -867,11 +870,13 @@ static void scheduler(icp_ctx* ctx) {
         if (s < 0) break;
         req = std::move(ctx->queue.front());
         ctx->queue.pop_front();
+        ctx->admitting++;
       }
       bool oom = false;
       const bool adm = E.admit(s, *req, &oom, false);
       if (adm && oom) {
         std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->admitting--;
         if (ctx->running == 0) {
           ctx->state[req->ticket] = 3;  // can never fit the budget
         } else {
@@ -882,6 +887,7 @@ static void scheduler(icp_ctx* ctx) {
       if (!adm || !E.activate(s)) {
         E.drain();
         std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->admitting--;
         ctx->state[req->ticket] = 4;
         E.release(s);
         ok = false;
@@ -890,6 +896,7 @@ static void scheduler(icp_ctx* ctx) {
       held.push_back(std::move(req));
       std::lock_guard<std::mutex> lk(ctx->mu);
       ctx->state[held.back()->ticket] = 1;
+      ctx->admitting--;
       ctx->running++;
     }
     // 3) completion flags after the replay (and after the boots of new slots)
@@ -1323,6 +1330,7 @@ icp_status icp_batch_submit(icp_ctx* ctx, const icp_request* reqs, int n, uint64
       ctx->reserved--;
       if (!r) {
         ctx->state[tickets_out[i]] = 3;
+        ctx->cv_done.notify_all();
         return;
       }
       r->M = q.M; r->N = q.N; r->prm = q.params;
@@ -1380,7 +1388,13 @@ icp_status icp_profile_read(icp_ctx* ctx, icp_profile_stats* out) {
 icp_status icp_batch_wait_all(icp_ctx* ctx) {
   if (!ctx) return ICP_ERR_INVALID_ARG;
   std::unique_lock<std::mutex> lk(ctx->mu);
-  ctx->cv_done.wait(lk, [&] { return ctx->failed || (ctx->queue.empty() && ctx->running == 0); });
+  // a request is pending while it is queued, being copied by a submission
+  // (reserved), between its pop from the queue and its activation or
+  // rejection (admitting), or running
+  ctx->cv_done.wait(lk, [&] {
+    return ctx->failed ||
+           (ctx->queue.empty() && ctx->reserved == 0 && ctx->admitting == 0 && ctx->running == 0);
+  });
   return ctx->failed ? ICP_ERR_DEVICE : ICP_OK;
 }
 

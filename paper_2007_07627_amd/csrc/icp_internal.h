@@ -98,7 +98,7 @@ struct SlotDesc {
   float* d2_out;
   unsigned long long* stats;  // kQueues lines of kStatStride: [0] pairs through the
                               // filter, [1] pairs scanned exactly (summed on the host)
-  double* trace;              // optional per-pass rows [E, nu, sm, reuse, T(16)]
+  double* trace;              // optional per-pass rows [E, nu, sm, reuse, T(16), prop(16)]
   int* item_stats;            // optional, last pass: per NN work item
                               // [cycles, clusters filtered, candidates, flags]
   int trace_cap;
@@ -199,8 +199,15 @@ constexpr int kBruteItemClusters = 8;
 __host__ __device__ inline int brute_split(int ncl) {
   return ncl > 0 ? (ncl + kBruteItemClusters - 1) / kBruteItemClusters : 1;
 }
+__host__ __device__ inline long long brute_items64(int ntile, int ncl) {
+  return (long long)((ntile + 1) / 2) * (long long)brute_split(ncl);
+}
+// Items of one pair in the multi-slot engine are capped so that the planner's
+// int prefix over kMaxSlots pairs cannot overflow (1024 x 2^20 < 2^31); a pair
+// beyond the cap is searched with the cluster method, whose result is the same.
+constexpr long long kMaxBruteItemsPerPair = 1ll << 20;
 __host__ __device__ inline int brute_items(int ntile, int ncl) {
-  return ((ntile + 1) / 2) * brute_split(ncl);
+  return (int)brute_items64(ntile, ncl);
 }
 
 // Element i of a device array through a global-address-space pointer. The
@@ -231,6 +238,7 @@ __device__ __forceinline__ int queue_item(int* q, int round) {
 }
 
 constexpr int kMaxSlots = 1024;
-constexpr int kTraceRow = 20;
+// trace row: [E, nu, solver position, reuse, T_eval (16), proposal (16)]
+constexpr int kTraceRow = 36;
 
 }  // namespace icp

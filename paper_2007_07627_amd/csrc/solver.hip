@@ -58,9 +58,12 @@ __device__ inline Coef coeffs(double t) {
     k.A = 1.0 - t2 / 6.0 + t4 / 120.0 - t6 / 5040.0 + t8 / 362880.0 - t10 / 39916800.0;
     k.B = 0.5 - t2 / 24.0 + t4 / 720.0 - t6 / 40320.0 + t8 / 3628800.0 - t10 / 479001600.0;
     k.C = 1.0 / 6.0 - t2 / 120.0 + t4 / 5040.0 - t6 / 362880.0 + t8 / 39916800.0 - t10 / 6227020800.0;
-    k.Ad = -1.0 / 3.0 + t2 / 30.0 - t4 / 840.0 + t6 / 45360.0 - t8 / 3991680.0;
-    k.Bd = -1.0 / 12.0 + t2 / 180.0 - t4 / 6720.0 + t6 / 453600.0 - t8 / 47900160.0;
-    k.Cd = -1.0 / 60.0 + t2 / 1260.0 - t4 / 60480.0 + t6 / 4989600.0 - t8 / 622702080.0;
+    // derivative series sum_k (-1)^k 2k t^(2k-2) / (2k+1)!, (2k+2)!, (2k+3)!
+    // through k = 6 (the first omitted term is below 1e-17 relative at 0.3)
+    k.Ad = -1.0 / 3.0 + t2 / 30.0 - t4 / 840.0 + t6 / 45360.0 - t8 / 3991680.0 + t10 / 518918400.0;
+    k.Bd = -1.0 / 12.0 + t2 / 180.0 - t4 / 6720.0 + t6 / 453600.0 - t8 / 47900160.0 + t10 / 7264857600.0;
+    k.Cd = -1.0 / 60.0 + t2 / 1260.0 - t4 / 60480.0 + t6 / 4989600.0 - t8 / 622702080.0 +
+           t10 / 108972864000.0;
   } else {
     const double s = sin(t), c = cos(t), h = sin(0.5 * t);
     const double omc = 2.0 * h * h;  // 1 - cos t
@@ -104,11 +107,12 @@ __device__ void twist_log(const double T[16], double xi[6]) {
   const double th = atan2(sn, cs);
   double d[3];
   if (th < 3.0) {
-    // theta / (2 sin theta): series below 0.2
+    // theta / (2 sin theta): the quotient itself is accurate down to tiny
+    // angles (no cancellation); below 1e-4 its series, whose first omitted
+    // term 7 theta^4 / 720 is below 1e-18
     double f;
-    if (th < 0.2) {
-      const double t2 = th * th;
-      f = 0.5 + t2 / 12.0 + 7.0 * t2 * t2 / 720.0 + 31.0 * t2 * t2 * t2 / 30240.0;
+    if (th < 1e-4) {
+      f = 0.5 + th * th / 12.0;
     } else {
       f = th / (2.0 * sin(th));
     }
@@ -678,10 +682,11 @@ __device__ inline void cpy(double* d, const double* s, int n) {
 
 // ------------------------------------------------------------------ Algorithm 1
 
-__device__ void step_p2p(SlotState& S, const double* mom) {
+__device__ void step_p2p(SlotState& S, const double* mom, double* trace_prop) {
   const double E = mom[0];
   double Tprop[16];
   const unsigned pf = align_p2p(mom, S.cP, S.cQ, S.Vq, Tprop);
+  if (trace_prop) cpy(trace_prop, (pf & F_ZERO_WEIGHT) ? S.Teval : Tprop, 16);
   const int m = S.m;
   int sm = S.sm;
   if (sm == SM_INIT) {
@@ -772,9 +777,9 @@ __device__ void step_p2p(SlotState& S, const double* mom) {
       cpy(Tn, S.Tp, 16);
       S.is_aa = 0;
     } else {
-      // log Tk is kept from when Tk was set: the G entry of an un-accelerated
-      // iterate, or the mixed parameters themselves (exp then log returns
-      // them up to rounding while the angle stays below pi)
+      // F^(k) = G^(k) - log T^(k) with log T^(k) taken from the transform
+      // itself (Algorithm 1): the logarithm of the iterate is re-taken after
+      // the exponential of the mixed parameters, not carried over from them
       double lp[6], xa[6];
       twist_log(S.Tp, lp);
       for (int a = 0; a < 6; ++a) {
@@ -784,8 +789,7 @@ __device__ void step_p2p(SlotState& S, const double* mom) {
       const int mk = (S.k - S.kstart) < m ? (S.k - S.kstart) : m;
       if (anderson(S, S.k, mk, 0, xa)) S.flags |= F_AA_SINGULAR;
       twist_exp(xa, Tn);
-      if (xa[0] * xa[0] + xa[1] * xa[1] + xa[2] * xa[2] < 9.0) cpy(S.lk, xa, 6);
-      else twist_log(Tn, S.lk);
+      twist_log(Tn, S.lk);
       S.is_aa = 1;
     }
     cpy(S.Tk, Tn, 16);
@@ -810,11 +814,15 @@ stage_end:
 
 // ------------------------------------------------------------------ Algorithm 2
 
-__device__ void step_p2pl(SlotState& S, const double* mom) {
+__device__ void step_p2pl(SlotState& S, const double* mom, double* trace_prop) {
   const double E = mom[0];
   double xprop[6];
   const double* xeval = S.last_key;  // parameters of this evaluation
   const unsigned pf = gn_p2pl(mom, xeval, xprop);
+  if (trace_prop) {
+    cpy(trace_prop, xprop, 6);
+    for (int i = 6; i < 16; ++i) trace_prop[i] = 0.0;
+  }
   int sm = S.sm;
   if (sm == SM_INIT) {
     if (S.nu_auto) {
@@ -1153,6 +1161,7 @@ __global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__
 // One pass of the state machine for a slot (lane 0 of the solver wavefront).
 __device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc) {
   S.phases++;
+  double* prop = nullptr;  // the trace row's un-accelerated update, written by the step
   if (D.trace && S.trace_len < D.trace_cap) {
     double* row = D.trace + (size_t)S.trace_len * kTraceRow;
     row[0] = acc[0];
@@ -1160,6 +1169,8 @@ __device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc) 
     row[2] = S.sm;
     row[3] = S.reuse;
     for (int i = 0; i < 16; ++i) row[4 + i] = S.Teval[i];
+    prop = row + 20;
+    for (int i = 0; i < 16; ++i) prop[i] = 0.0;
     S.trace_len++;
   }
   if (S.sm == SM_QUERY) {
@@ -1179,9 +1190,9 @@ __device__ void solver_step(const SlotDesc& D, SlotState& S, const double* acc) 
     S.nu = S.nu_eval;
     finish(S, T, acc[0]);
   } else if (mode_plane(D.mode)) {
-    step_p2pl(S, acc);
+    step_p2pl(S, acc, prop);
   } else {
-    step_p2p(S, acc);
+    step_p2p(S, acc, prop);
   }
 }
 

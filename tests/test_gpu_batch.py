@@ -147,3 +147,58 @@ def test_requests_join_in_flight(ctx):
     for (d, (P, Q, Qn, prm)), g in zip(second, res2):
         a = B.icp_register(ctx, P, Q, Qn, prm)
         assert np.array_equal(g["T"], a["T"])
+
+
+def _oracle_reproducible_requests(count, seed_config, lo=3000, hi=8000):
+    """Pairs whose trajectories the oracle reproduces (Algorithm 1 without
+    mixing, Algorithm 2 with m = 6), so that a batched result can be held to
+    the end-point tolerance against the oracle's own registration."""
+    out = []
+    for d in synth.batch_pairs(count=count, lo=lo, hi=hi, seed_config=seed_config):
+        if d["mode"] == 2:
+            prm = B.icp_params_default(B.ICP_P2PL_WELSCH, anderson_m=6, nu_min=d["nu_min"])
+            out.append((d, (d["P"], d["Q"], d["Qn"], prm), dict(mode=2, anderson_m=6)))
+        else:
+            prm = B.icp_params_default(B.ICP_P2P_WELSCH, anderson_m=0, nu_min=d["nu_min"])
+            out.append((d, (d["P"], d["Q"], None, prm), dict(mode=1, anderson_m=0)))
+    return out
+
+
+def test_batched_and_served_against_oracle(ctx):
+    """Batched pairs, and pairs admitted while others run, end within 1e-5 rad
+    and 1e-5 diag of the oracle's registration of the same pair."""
+    first = _oracle_reproducible_requests(6, seed_config=47)
+    late = _oracle_reproducible_requests(3, seed_config=48)
+    announce("batched and in-flight pairs vs oracle")
+    t1 = B.icp_batch_submit(ctx, [r for _, r, _ in first])
+    time.sleep(0.005)
+    t2 = B.icp_batch_submit(ctx, [r for _, r, _ in late])
+    res = _wait(ctx, t1) + _wait(ctx, t2)
+    modes = set()
+    for (d, (P, Q, Qn, prm), okw), g in zip(first + late, res):
+        o = oracle.register(P, Q, Qn, nu_min=d["nu_min"], **okw)
+        rot = metrics.rotation_error_rad(g["T"], o["T"])
+        tr = metrics.translation_error(g["T"], o["T"])
+        print(f"mode {okw['mode']} M={len(P)} N={len(Q)}: rot {rot:.2e} tr {tr:.2e}", flush=True)
+        assert rot <= 1e-5 and tr <= 1e-5 * d["diag"]
+        assert abs(g["energy"] - o["energy"]) <= 1e-6 * max(1.0, abs(o["energy"]))
+        modes.add(okw["mode"])
+    assert modes == {1, 2}
+
+
+def test_wait_all_returns_after_every_result():
+    """icp_batch_wait_all blocks until every request has a result: right after
+    it returns, no ticket reports NOT_READY."""
+    h = B.icp_create(0, 1 << 30)
+    try:
+        B.icp_batch_config(h, 2, 8)
+        for rnd in range(3):
+            reqs = _requests(24, lo=500, hi=2000, seed_config=49 + rnd)
+            announce(f"wait_all round {rnd}")
+            tickets = B.icp_batch_submit(h, [r for _, r in reqs])
+            B.icp_batch_wait_all(h)
+            for t in tickets:
+                rc, _ = B.icp_poll(h, t)
+                assert rc == B.ICP_OK, B.icp_status_str(rc)
+    finally:
+        B.icp_destroy(h)

@@ -99,23 +99,42 @@ def test_nn_empty_and_invalid(ctx):
     assert rc == B.ICP_ERR_INVALID_ARG
 
 
+_FULL_CACHE = {}
+
+
+def _oracle_full(key, P, Q, T):
+    if key not in _FULL_CACHE:
+        _FULL_CACHE[key] = oracle.nn_query(P, Q, T)
+    return _FULL_CACHE[key]
+
+
 @pytest.mark.parametrize("method", METHODS)
-def test_nn_full_size_sampled(ctx, method):
-    """Config-2 scale (M = N = 100k) in one call; the oracle checks a seeded
-    sample of 3000 sources."""
+def test_nn_full_size_all_sources(ctx, method):
+    """Config-2 scale (M = N = 100k) in one call: every source against the
+    oracle's exhaustive scan, bit for bit."""
     d = synth.partial_sphere_pair(synth.rng_for(2, 0))
-    announce(f"nn full-size sampled method={method}")
+    announce(f"nn full-size all sources 100k x 100k method={method}")
     gi, gd = B.icp_nn_query(ctx, d["P"], d["Q"], d["T_gt"], method)
-    sel = np.random.default_rng(0).choice(len(d["P"]), 3000, replace=False)
-    oi, od = oracle.nn_query(d["P"][sel], d["Q"], d["T_gt"])
-    assert np.array_equal(gi[sel], oi) and np.array_equal(gd[sel], od)
+    oi, od = _oracle_full("sphere100k", d["P"], d["Q"], d["T_gt"])
+    assert np.array_equal(gi, oi) and np.array_equal(gd, od)
 
 
-@pytest.mark.parametrize("m,n", [(200_000, 500_000), (1_000_000, 1_000_000)])
-def test_nn_height_field_full_size_sampled(ctx, m, n):
-    """The point-to-plane workload's size (200k sources, 500k targets) and the
-    largest served request (1M x 1M), height field with outliers, cluster
-    search in one call; the oracle checks a seeded sample of 1500 sources."""
+def test_nn_height_field_200k_500k_all_sources(ctx):
+    """The point-to-plane workload's size (200k sources, 500k targets, height
+    field with outliers), cluster search in one call: every source against the
+    oracle's exhaustive scan (1e11 pairs)."""
+    d = synth.height_field_pair(synth.rng_for(3, 7), m=200_000, n=500_000)
+    announce("nn height field full-size all sources 200k x 500k")
+    T = d["T_gt"]
+    gi, gd = B.icp_nn_query(ctx, d["P"], d["Q"], T, B.ICP_NN_CLUSTER)
+    oi, od = oracle.nn_query(d["P"], d["Q"], T)
+    assert np.array_equal(gi, oi) and np.array_equal(gd, od)
+
+
+def test_nn_height_field_1m_sampled(ctx):
+    """The largest served request (1M x 1M): the oracle checks a seeded sample
+    of 1500 sources (its exhaustive scan of all of them would take minutes)."""
+    m = n = 1_000_000
     d = synth.height_field_pair(synth.rng_for(3, 7), m=m, n=n)
     announce(f"nn height field full-size sampled m={m} n={n}")
     T = d["T_gt"]

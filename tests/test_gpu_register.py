@@ -40,20 +40,6 @@ def test_fast_icp_config1(ctx, seed):
     assert metrics.rmse(d["T_gt"], g["T"], d["P"]) < 5e-3 * d["diag"]
 
 
-def _oracle_self_stable(d, mode, **kw):
-    """The oracle run twice with the source order permuted (same mathematics,
-    different FP64 summation order). Anderson mixing with the safeguard can
-    amplify rounding into a different end point; only when the oracle
-    reproduces itself is a 1e-5 rad bar meaningful against any other
-    implementation."""
-    a = oracle.register(d["P"], d["Q"], d.get("Qn") if mode == 2 else None, mode=mode, **kw)
-    perm = np.random.default_rng(1).permutation(len(d["P"]))
-    b = oracle.register(d["P"][perm], d["Q"], d.get("Qn") if mode == 2 else None, mode=mode, **kw)
-    stable = (metrics.rotation_error_rad(a["T"], b["T"]) <= 1e-7 and
-              metrics.translation_error(a["T"], b["T"]) <= 1e-7 * d["diag"])
-    return a, stable
-
-
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("nn", [B.ICP_NN_BRUTE, B.ICP_NN_CLUSTER])
 def test_robust_p2p_plain_mm(ctx, seed, nn):
@@ -66,26 +52,6 @@ def test_robust_p2p_plain_mm(ctx, seed, nn):
     o = oracle.register(d["P"], d["Q"], mode=1, anderson_m=0, nu_min=d["nu_min"])
     _compare(g, o, d["diag"], f"p2p-mm{seed}")
     assert g["nn_passes"] == o["nn_passes"] and g["iterations"] == o["iterations"]
-
-
-@pytest.mark.parametrize("seed", [0, 2, 3])
-def test_robust_p2p_anderson(ctx, seed):
-    """Algorithm 1 with m = 5: the first passes follow the oracle's trajectory
-    closely; the end point must match wherever the oracle reproduces itself."""
-    d = synth.partial_sphere_pair(synth.rng_for(2, 100 + seed), m=4000, n=5000)
-    announce(f"register robust-p2p m=5 seed={seed}")
-    kw = dict(anderson_m=5, nu_min=d["nu_min"], eps=1e-9)
-    prm = B.icp_params_default(B.ICP_P2P_WELSCH, **kw)
-    g = B.icp_register_trace(ctx, d["P"], d["Q"], None, prm, cap=20000)
-    o = oracle.register(d["P"], d["Q"], mode=1, trace_cap=20000, **kw)
-    gt, ot = g["trace"][1:], o["trace"]  # GPU row 0 is the median setup pass
-    for i in range(6):
-        assert np.abs(gt[i, 4:] - ot[i, 4:]).max() < 1e-9, i
-        assert abs(gt[i, 0] - ot[i, 0]) <= 1e-9 * abs(ot[i, 0]), i
-    _, stable = _oracle_self_stable(d, 1, **kw)
-    print(f"seed {seed}: oracle self-stable {stable}", flush=True)
-    if stable:
-        _compare(g, o, d["diag"], f"p2p-aa{seed}")
 
 
 @pytest.mark.parametrize("mode", [B.ICP_P2P_L2, B.ICP_P2P_WELSCH, B.ICP_P2PL_WELSCH])
@@ -103,7 +69,7 @@ def test_map_evaluation_along_oracle_trajectory(ctx, mode):
     pick = np.unique(np.linspace(0, len(rows) - 1, 12).astype(int))
     announce(f"eval-map mode={mode} rows={len(rows)}")
     for i in pick:
-        T = rows[i, 4:].reshape(4, 4)
+        T = rows[i, 4:20].reshape(4, 4)
         nu = rows[i, 1]
         Eg, Tg, fg = B.icp_eval(ctx, d["P"], d["Q"], d["Qn"], mode, T, nu)
         Eo, To, fo = oracle.eval_map(d["P"], d["Q"], d["Qn"], mode, T, nu)
