@@ -208,6 +208,30 @@ icp_status icp_nn_query_dev(icp_ctx *ctx, const float *P_dev, int64_t M, const f
                             int64_t N, const double T[16], icp_nn_method method,
                             int32_t *idx_out_dev, float *d2_out_dev, void *stream);
 
+/* For callers that cannot allocate device memory or synchronise with the
+ * host -- code under HIP graph capture, serving loops that forbid allocation
+ * -- the closest-point query of icp_nn_query_dev without a context: no
+ * allocation of any kind, no host synchronisation, no memset or host-copy
+ * nodes; every step (setup of the cluster index, search, outputs) is a kernel
+ * launched on `stream` (NULL = the null stream), and the call returns once
+ * they are enqueued, so the outputs are ready when the stream reaches that
+ * point. Same result as icp_nn_query_dev, bit for bit.
+ * Working memory: one fixed device array of ICP_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * per GPU, held until the process ends; about 100 bytes per source plus 60
+ * per target (plus the sort buffers) must fit it, which holds M = N up to
+ * about 400000; larger requests return ICP_ERR_OOM without launching
+ * anything. Every call on a GPU uses that GPU's one array: calls that overlap
+ * on one GPU (other streams, other threads) race and must be serialised by
+ * the caller; consecutive calls on one stream are ordered. The array keeps
+ * the last call's contents; everything a call reads is rewritten by it first.
+ * Device: the current HIP device. Inputs/outputs: device pointers as in
+ * icp_nn_query_dev. Errors: ICP_ERR_INVALID_ARG as icp_nn_query_dev,
+ * ICP_ERR_OOM beyond the array, ICP_ERR_DEVICE on a launch failure. */
+icp_status icp_nn_query_dev_noalloc(const float *P_dev, int64_t M, const float *Q_dev, int64_t N,
+                                    const double T[16], icp_nn_method method,
+                                    int32_t *idx_out_dev, float *d2_out_dev, void *stream);
+#define ICP_NOALLOC_SCRATCH_BYTES (64u << 20)
+
 /* Automatic nu_min of a target set (Sec. 4.3 for point-to-point, Sec. 5 for
  * point-to-plane; rationale in App. C), the value a registration uses when
  * its params.nu_min <= 0: for every target its six nearest other targets

@@ -25,7 +25,7 @@ ICP_TRACE_ROW = 36
 EXPORTED = ["icp_create", "icp_destroy", "icp_params_default", "icp_params_classical", "icp_register", "icp_register_trace",
             "icp_eval", "icp_trace_items",
             "icp_register_dev",
-            "icp_nn_query", "icp_nn_query_dev", "icp_nu_min_auto", "icp_estimate_normals", "icp_batch_submit", "icp_poll",
+            "icp_nn_query", "icp_nn_query_dev", "icp_nn_query_dev_noalloc", "icp_nu_min_auto", "icp_estimate_normals", "icp_batch_submit", "icp_poll",
             "icp_batch_wait_all", "icp_batch_config", "icp_profile", "icp_profile_read",
             "icp_status_str"]
 
@@ -89,6 +89,7 @@ def lib():
                                        C.POINTER(icp_result), vp]
         L.icp_nn_query.argtypes = [vp, vp, i64, vp, i64, vp, i32, vp, vp]
         L.icp_nn_query_dev.argtypes = [vp, vp, i64, vp, i64, vp, i32, vp, vp, vp]
+        L.icp_nn_query_dev_noalloc.argtypes = [vp, i64, vp, i64, vp, i32, vp, vp, vp]
         L.icp_batch_submit.argtypes = [vp, C.POINTER(icp_request), i32, C.POINTER(C.c_uint64)]
         L.icp_poll.argtypes = [vp, C.c_uint64, C.POINTER(icp_result)]
         L.icp_nu_min_auto.argtypes = [vp, vp, vp, C.c_int64, i32, C.POINTER(C.c_double)]
@@ -274,6 +275,18 @@ def icp_nn_query_dev(ctx, P_t, Q_t, T, method, idx_t, d2_t, stream=None):
     rc = lib().icp_nn_query_dev(ctx, P_t.data_ptr(), P_t.shape[0], Q_t.data_ptr(), Q_t.shape[0],
                                 T.ctypes.data, method, idx_t.data_ptr(), d2_t.data_ptr(), st)
     _check(rc, "icp_nn_query_dev")
+
+
+def icp_nn_query_dev_noalloc(P_t, Q_t, T, method, idx_t, d2_t, stream=None, raw=False):
+    """Allocation-free closest-point query on the current device (no context):
+    enqueued on `stream`, outputs ready when the stream reaches that point."""
+    T = np.ascontiguousarray(np.asarray(T, np.float64).reshape(4, 4))
+    st = None if stream is None else int(stream.cuda_stream)
+    rc = lib().icp_nn_query_dev_noalloc(P_t.data_ptr(), P_t.shape[0], Q_t.data_ptr(), Q_t.shape[0],
+                                        T.ctypes.data, method, idx_t.data_ptr(), d2_t.data_ptr(), st)
+    if raw:
+        return rc
+    _check(rc, "icp_nn_query_dev_noalloc")
 
 
 def icp_batch_submit(ctx, requests):

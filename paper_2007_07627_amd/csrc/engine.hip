@@ -595,6 +595,81 @@ struct Engine {
   }
 };
 
+// ------------------------------------------------------------------ allocation-free query
+
+// Working memory of icp_nn_query_dev_noalloc: one query slot (descriptor,
+// state, work list, completion flag and the slot's arrays) in a fixed device
+// array, one copy per GPU, held until the process ends. Host code reaches it
+// only through the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t kNoAllocDesc = 0;
+constexpr size_t kNoAllocState = kNoAllocDesc + round256(sizeof(SlotDesc));
+constexpr size_t kNoAllocWl = kNoAllocState + round256(sizeof(SlotState));
+constexpr size_t kNoAllocDone = kNoAllocWl + round256(sizeof(WorkList));
+constexpr size_t kNoAllocSlot = kNoAllocDone + 256;
+
+struct NoAllocDevice {
+  bool ready = false;
+  unsigned char* ptr = nullptr;  // device address of `scratch` on this GPU
+  int nn_grid = 4096, epi_grid = 1024;
+};
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+
+// Address of the scratch array on the current device (looked up once per
+// device with that device current), or nullptr.
+static NoAllocDevice* noalloc_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  NoAllocDevice& d = g_noalloc[dev];
+  if (!d.ready) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    d.ptr = static_cast<unsigned char*>(p);
+    d.nn_grid = cus * 16;
+    d.epi_grid = cus * 4;
+    d.ready = true;
+  }
+  return &d;
+}
+
+struct QueryT { double T[16]; };
+
+// Descriptor, state and work list of a fresh query slot, written on the
+// device (no host copy, so the sequence can be captured into a graph and
+// replayed with other inputs). The descriptor's rho_max and verlet are
+// written afterwards by the cluster build.
+__global__ __launch_bounds__(256) void noalloc_init_kernel(SlotDesc* __restrict__ desc,
+                                                           SlotState* __restrict__ state,
+                                                           WorkList* __restrict__ wl,
+                                                           int* __restrict__ done, SlotDesc D,
+                                                           QueryT T) {
+  unsigned long long* sw = reinterpret_cast<unsigned long long*>(state);
+  for (size_t i = threadIdx.x; i < sizeof(SlotState) / 8; i += blockDim.x) sw[i] = 0ull;
+  int* ww = reinterpret_cast<int*>(wl);
+  for (size_t i = threadIdx.x; i < sizeof(WorkList) / 4; i += blockDim.x) ww[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    D.rho_max = 0.0f;
+    D.verlet = 0.0f;
+    *desc = D;
+    state->status = ST_SETUP;
+    state->mode = P2P_L2;
+    state->sm = SM_QUERY;
+    state->k = 1;
+    for (int i = 0; i < 16; ++i) state->Tkm1[i] = T.T[i];
+    done[0] = 0;
+  }
+}
+
 }  // namespace icp
 
 using namespace icp;
@@ -1260,6 +1335,90 @@ icp_status icp_nn_query_dev(icp_ctx* ctx, const float* P_dev, int64_t M, const f
   std::lock_guard<std::mutex> g(ctx->sync_mu);
   icp_result res;
   return run_sync(ctx, r, &res, stream, nullptr, nullptr);
+}
+
+icp_status icp_nn_query_dev_noalloc(const float* P_dev, int64_t M, const float* Q_dev, int64_t N,
+                                    const double T[16], icp_nn_method method, int32_t* idx_out_dev,
+                                    float* d2_out_dev, void* stream) {
+  if (!T || method < ICP_NN_AUTO || method > ICP_NN_CLUSTER) return ICP_ERR_INVALID_ARG;
+  if (M < 0 || N <= 0 || M > (1 << 28) || N > (1 << 28) || !Q_dev) return ICP_ERR_INVALID_ARG;
+  if (M == 0) return ICP_OK;
+  if (!P_dev || !idx_out_dev || !d2_out_dev) return ICP_ERR_INVALID_ARG;
+  if (!rigid_ok(T)) return ICP_ERR_INVALID_ARG;
+  Layout L;
+  L.plan(M, N, false, false, 0);
+  if (kNoAllocSlot + L.total > kNoAllocBytes) return ICP_ERR_OOM;
+  NoAllocDevice* nd = noalloc_device();
+  if (!nd) return ICP_ERR_DEVICE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  unsigned char* base = nd->ptr;
+  SlotDesc* desc = reinterpret_cast<SlotDesc*>(base + kNoAllocDesc);
+  SlotState* state = reinterpret_cast<SlotState*>(base + kNoAllocState);
+  WorkList* wl = reinterpret_cast<WorkList*>(base + kNoAllocWl);
+  int* done = reinterpret_cast<int*>(base + kNoAllocDone);
+  char* b = reinterpret_cast<char*>(base + kNoAllocSlot);
+  auto F = [&](size_t o) { return reinterpret_cast<float*>(b + o); };
+  auto F4 = [&](size_t o) { return reinterpret_cast<float4*>(b + o); };
+  unsigned* sort_scratch = reinterpret_cast<unsigned*>(b + L.o_scratch);
+  char* st_base = reinterpret_cast<char*>(state);
+  float* bbQ = reinterpret_cast<float*>(st_base + offsetof(SlotState, bbQ));
+  float* bbP = reinterpret_cast<float*>(st_base + offsetof(SlotState, bbP));
+  double* cQ = reinterpret_cast<double*>(st_base + offsetof(SlotState, cQ));
+  double* cP = reinterpret_cast<double*>(st_base + offsetof(SlotState, cP));
+  float* rho = reinterpret_cast<float*>(reinterpret_cast<char*>(desc) + offsetof(SlotDesc, rho_max));
+  SlotDesc D;
+  std::memset(&D, 0, sizeof D);
+  D.px = F(L.o_px); D.py = F(L.o_py); D.pz = F(L.o_pz);
+  D.perm = reinterpret_cast<int*>(b + L.o_perm);
+  D.tsph = reinterpret_cast<double4*>(b + L.o_tsph);
+  D.qx = F(L.o_qx); D.qy = F(L.o_qy); D.qz = F(L.o_qz);
+  D.qloc = F4(L.o_qloc); D.qorg = F4(L.o_qorg); D.ccen = F4(L.o_ccen);
+  D.clo = F4(L.o_clo); D.chi = F4(L.o_chi); D.slo = F4(L.o_slo); D.shi = F4(L.o_shi);
+  D.kbox = F4(L.o_kbox);
+  D.keys = reinterpret_cast<unsigned long long*>(b + L.o_keys);
+  D.clist = reinterpret_cast<int*>(b + L.o_clist);
+  D.squeue = reinterpret_cast<int4*>(b + L.o_squeue);
+  D.scount = reinterpret_cast<int*>(b + L.o_scount);
+  D.nnidx = reinterpret_cast<int32_t*>(b + L.o_nnidx);
+  D.nnd2 = F(L.o_nnd2);
+  D.part = reinterpret_cast<double*>(b + L.o_part);
+  D.medkey = reinterpret_cast<double*>(b + L.o_med);
+  D.idx_out = idx_out_dev;
+  D.d2_out = d2_out_dev;
+  D.stats = reinterpret_cast<unsigned long long*>(b + L.o_stats);
+  D.M = L.M; D.N = L.N; D.ntile = L.ntile; D.ncl = L.ncl; D.nsup = L.nsup; D.nepi = L.nepi;
+  if (method == ICP_NN_AUTO) method = ((double)L.M * L.N <= 64.0e6) ? ICP_NN_BRUTE : ICP_NN_CLUSTER;
+  D.method = method == ICP_NN_BRUTE ? NN_BRUTE : NN_CLUSTER;
+  D.mode = P2P_L2;
+  QueryT qt;
+  std::memcpy(qt.T, T, sizeof qt.T);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(noalloc_init_kernel, dim3(1), dim3(256), 0, st, desc, state, wl, done, D, qt);
+  // the setup of icp_nn_query_dev (Engine::admit) with device inputs, on the caller's stream
+  launch_aos_to_soa(Q_dev, L.N, F(L.o_qx), F(L.o_qy), F(L.o_qz), st);
+  launch_aos_to_soa(P_dev, L.M, F(L.o_pox), F(L.o_poy), F(L.o_poz), st);
+  launch_bbox(F(L.o_qx), F(L.o_qy), F(L.o_qz), L.N, bbQ, cQ, st);
+  unsigned* order = nullptr;
+  launch_hilbert_order(F(L.o_qx), F(L.o_qy), F(L.o_qz), L.N, bbQ, sort_scratch, &order, st);
+  launch_build_clusters(F(L.o_qx), F(L.o_qy), F(L.o_qz), order, L.N, L.ncl, F4(L.o_qloc), F4(L.o_qorg),
+                        F4(L.o_ccen), F4(L.o_clo), F4(L.o_chi), F4(L.o_kbox), st);
+  launch_build_super(F4(L.o_clo), F4(L.o_chi), F4(L.o_ccen), L.ncl, L.nsup, F4(L.o_slo), F4(L.o_shi),
+                     rho, st);
+  launch_bbox(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, cP, st);
+  launch_hilbert_order(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, sort_scratch, &order, st);
+  launch_build_tiles(F(L.o_pox), F(L.o_poy), F(L.o_poz), order, L.M, L.ntile, F(L.o_px), F(L.o_py),
+                     F(L.o_pz), reinterpret_cast<int*>(b + L.o_perm), reinterpret_cast<double4*>(b + L.o_tsph),
+                     st);
+  launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_keys), L.M, ~0ull, st);
+  launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_stats), kQueues * kStatStride, 0ull, st);
+  launch_fill_u64(reinterpret_cast<unsigned long long*>(b + L.o_nnidx), (L.M + 1) / 2, ~0ull, st);
+  // one pass of the one-slot engine: search, output epilogue, solver (marks the query done)
+  launch_boot(desc, state, 0, wl, true, st);
+  if (D.method == NN_BRUTE) launch_brute(desc, state, nd->nn_grid, st);
+  else launch_nn(desc, state, wl, nd->nn_grid, true, st);
+  launch_epi(desc, state, wl, nd->epi_grid, true, st);
+  launch_solver(desc, state, 1, done, wl, true, st);
+  return hipGetLastError() == hipSuccess ? ICP_OK : ICP_ERR_DEVICE;
 }
 
 icp_status icp_batch_config(icp_ctx* ctx, int passes_per_replay, int max_slots) {
