@@ -181,34 +181,38 @@ def log_uniform_int(rng, lo, hi):
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
 
 
+def batch_pair(i, lo=2000, hi=200_000, seed_config=4):
+    """Pair i of an uneven batch: M, N log-uniform in [lo, hi]; generator (full
+    resample vs. partial overlap) and mode (point-to-point vs. point-to-plane)
+    by independent seeded coins."""
+    rng = rng_for(seed_config, i)
+    m = log_uniform_int(rng, lo, hi)
+    n = log_uniform_int(rng, lo, hi)
+    partial = rng.uniform() < 0.5
+    plane = rng.uniform() < 0.5
+    if partial:
+        d = partial_sphere_pair(rng, m=m, n=n)
+    else:
+        d = resampled_sphere_pair(rng, m=m, n=n)
+    d["mode"] = 2 if plane else 1
+    return d
+
+
 def batch_pairs(count=256, lo=2000, hi=200_000, seed_config=4):
-    """Uneven batch: M, N log-uniform in [lo, hi]; generator (full resample vs.
-    partial overlap) and mode (point-to-point vs. point-to-plane) by independent
-    seeded coins."""
-    out = []
-    for i in range(count):
-        rng = rng_for(seed_config, i)
-        m = log_uniform_int(rng, lo, hi)
-        n = log_uniform_int(rng, lo, hi)
-        partial = rng.uniform() < 0.5
-        plane = rng.uniform() < 0.5
-        if partial:
-            d = partial_sphere_pair(rng, m=m, n=n)
-        else:
-            d = resampled_sphere_pair(rng, m=m, n=n)
-        d["mode"] = 2 if plane else 1
-        out.append(d)
-    return out
+    """The first `count` pairs of an uneven batch (batch_pair)."""
+    return [batch_pair(i, lo, hi, seed_config) for i in range(count)]
+
+
+def served_request(i, lo=1000, hi=1_000_000, seed_config=5):
+    """Height-field request i with M, N log-uniform in [lo, hi]."""
+    rng = rng_for(seed_config, i)
+    m = log_uniform_int(rng, lo, hi)
+    n = log_uniform_int(rng, lo, hi)
+    d = height_field_pair(rng, m=m, n=n)
+    d["mode"] = 2
+    return d
 
 
 def served_requests(count, lo=1000, hi=1_000_000, seed_config=5, start=0):
-    """Height-field requests with M, N log-uniform in [lo, hi]."""
-    out = []
-    for i in range(start, start + count):
-        rng = rng_for(seed_config, i)
-        m = log_uniform_int(rng, lo, hi)
-        n = log_uniform_int(rng, lo, hi)
-        d = height_field_pair(rng, m=m, n=n)
-        d["mode"] = 2
-        out.append(d)
-    return out
+    """Height-field requests start .. start + count - 1 (served_request)."""
+    return [served_request(i, lo, hi, seed_config) for i in range(start, start + count)]
