@@ -202,11 +202,28 @@ def nn_roofline(prof, pairs, workload, note):
 
 # ------------------------------------------------------------------ batch-256 (headline)
 
+def tuning_used(B, ctx, shapes, batch):
+    """The autotuner's partition each (M, N, mode) uses in an engine kind:
+    distinct settings with their pair counts, and how many shapes had their
+    own tuned bucket."""
+    seen, found = {}, [0, 0, 0]
+    for M, N, mode in shapes:
+        t, f = B.icp_tuning_lookup(ctx, M, N, mode, B.ICP_NN_AUTO, batch)
+        key = json.dumps(t, sort_keys=True)
+        seen[key] = seen.get(key, 0) + 1
+        found[f] += 1
+    return {"arch": B.icp_device_arch(0), "table_entries": len(B.icp_tuning_entries(ctx)),
+            "pairs_with_own_bucket": found[2], "pairs_with_nearby_bucket": found[1],
+            "pairs_with_defaults": found[0],
+            "settings": [dict(json.loads(k), pairs=v) for k, v in sorted(seen.items(), key=lambda x: -x[1])]}
+
+
 def batch_bench(args, B, pairs):
     from paper_2007_07627_amd import metrics
     count = len(pairs)
     reqs = [_request(B, d) for d in pairs]
     ctx = B.icp_create(0, 32 << 30)
+    tuning = tuning_used(B, ctx, [(len(d["P"]), len(d["Q"]), 2 if d["mode"] == 2 else 1) for d in pairs], 1)
     B.icp_batch_config(ctx, args.passes_per_replay, min(1024, count))
     for w in range(args.warmup):
         _wait_tickets(B, ctx, B.icp_batch_submit(ctx, reqs))
@@ -293,6 +310,7 @@ def batch_bench(args, B, pairs):
                                    "rotation near 90 deg about z), another local minimum of the energy"},
         "roofline": nn_roofline(prof, float(sum(r["nn_pairs"] for r in res_prof)), "batch-256",
                                 "one profiled batch of the same 256 pairs; kernels timed per batch pass"),
+        "tuning": tuning,
     }
     return out, {"pairs": pairs, "passes": passes}
 
@@ -428,6 +446,7 @@ def single_pair_bench(args, B, torch, ds, prms, cfg, workload_name, steps, warmu
     Qns = [torch.from_numpy(d["Qn"]).to(dev) if int(p.mode) == 2 else None for d, p in zip(ds, prms)]
     ctx = B.icp_create(0, 16 << 30)
     stream = torch.cuda.current_stream()
+    tuning = tuning_used(B, ctx, [(len(d["P"]), len(d["Q"]), int(p.mode)) for d, p in zip(ds, prms)], 0)
 
     def run(engine, steps, profile=False):
         lat, res = [], []
@@ -470,6 +489,7 @@ def single_pair_bench(args, B, torch, ds, prms, cfg, workload_name, steps, warmu
         "effective_pairs_per_s": M * float(N) * passes * steps / wall,
         "roofline": nn_roofline(prof, float(sum(r["nn_pairs"] for r in res_prof)), workload_name,
                                 "a second run of the same registrations with per-pass kernel timing"),
+        "tuning": tuning,
     }
 
 

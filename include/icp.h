@@ -280,6 +280,90 @@ icp_status icp_batch_wait_all(icp_ctx *ctx);
  * concurrently resident pairs (1..1024). */
 icp_status icp_batch_config(icp_ctx *ctx, int passes_per_replay, int max_slots);
 
+/* Work partition of the closest-point search, chosen per size bucket by the
+ * autotuner. No value changes a result: the closest points (and so every
+ * registration) are the same bit for bit under any valid setting; only the
+ * time differs. */
+typedef struct {
+  int slice_min;        /* cluster search: candidate clusters per work slice at least, 1..64 (6) */
+  float list_margin;    /* cluster search: margin of the reusable candidate lists as a fraction
+                           of the median cluster radius, 0..1 (0.08) */
+  int brute_clusters;   /* exhaustive search in the batch engine: clusters per work item,
+                           1..4096 (8) */
+  int brute_items;      /* exhaustive search of a single pair: work items per pass, 64..2^20 (8192) */
+  int grid_per_cu;      /* synchronous calls: workgroups per compute unit of the persistent
+                           search kernels, 1..64 (16) */
+} icp_tuning;
+
+/* One entry of the tuning table: requests with floor(log2 M) == m_bucket and
+ * floor(log2 N) == n_bucket of this mode family (ICP_P2P_WELSCH stands for
+ * the point-to-point modes, ICP_P2PL_WELSCH for the point-to-plane ones) and
+ * search method (ICP_NN_BRUTE or ICP_NN_CLUSTER; AUTO resolves to BRUTE up to
+ * 64e6 source x target pairs), run by the engine kind `batch` (0: the
+ * synchronous calls, one pair on the GPU; 1: icp_batch_submit, pairs sharing
+ * the GPU -- a partition that shortens one pair's latency can cost
+ * throughput there). ms: the tuner's time for its test run (0 for an entry
+ * set by hand). */
+typedef struct {
+  int m_bucket, n_bucket, mode, method, batch;
+  icp_tuning tuning;
+  double ms;
+} icp_tuning_entry;
+
+/* The built-in partition (the values in parentheses above). */
+icp_status icp_tuning_default(icp_tuning *out);
+
+/* The partition a request of this shape uses in the given engine kind (0
+ * synchronous, 1 batch): the entry of its bucket, else the nearest tuned
+ * bucket of the same family, method and engine kind within two octaves
+ * (|dm| + |dn| <= 2), else the defaults. *found (may be NULL): 2 exact
+ * bucket, 1 nearby bucket, 0 defaults. */
+icp_status icp_tuning_lookup(icp_ctx *ctx, int64_t M, int64_t N, icp_mode mode,
+                             icp_nn_method method, int batch, icp_tuning *out, int *found);
+
+/* Add or replace the entry of a bucket (INVALID_ARG for values out of range). */
+icp_status icp_tuning_set(icp_ctx *ctx, const icp_tuning_entry *entry);
+
+/* Copy the table (up to cap entries) into out; *n receives its size. */
+icp_status icp_tuning_entries(icp_ctx *ctx, icp_tuning_entry *out, int cap, int *n);
+
+/* Search the partition for one bucket on the context's GPU: a synthetic
+ * bumpy-sphere pair of M sources and N targets (70% overlap, 10% outliers;
+ * radial normals for point-to-plane) is registered (at most 40 inner
+ * iterations) under each candidate setting, each timed as the best of two
+ * runs. batch = 0 (synchronous calls, the pair alone): cluster search
+ * slice_min {4, 6, 8, 12} x list_margin {0.04, 0.08, 0.16} x grid_per_cu
+ * {8, 16, 32}; exhaustive: brute_items {2048 .. 32768} x grid_per_cu
+ * {8, 16, 32}. batch = 1 (16 copies of the pair at once through the batch
+ * engine, fewer for large pairs: about 4e6 points in flight): cluster
+ * search slice_min x list_margin as above; exhaustive:
+ * brute_clusters {4, 8, 16, 32}. Every candidate must return the defaults'
+ * transform bit for bit (ICP_ERR_DEVICE otherwise: a library fault). The
+ * fastest is stored in the table and written to *best (may be NULL). Uses
+ * the engines for its duration (a few seconds at 100k points); do not run it
+ * while batch requests are being served. */
+icp_status icp_autotune(icp_ctx *ctx, int64_t M, int64_t N, icp_mode mode, icp_nn_method method,
+                        int batch, icp_tuning_entry *best);
+
+/* Architecture name of a HIP device (gcnArchName up to the first ':', e.g.
+ * "gfx950") into out (capacity cap bytes, NUL-terminated). */
+icp_status icp_device_arch(int device, char *out, int cap);
+
+/* Tuning cache files (JSON: {"arch": "...", "entries": [{"m_bucket": ..,
+ * "n_bucket": .., "mode": .., "method": .., "batch": .., "slice_min": .., "list_margin":
+ * .., "brute_clusters": .., "brute_items": .., "grid_per_cu": .., "ms": ..},
+ * ...]}). Host-only: no device is needed. Write stores n entries under arch.
+ * Read fills out (capacity cap) with the entries of a file whose arch equals
+ * `arch` (*n = 0 for another arch; arch NULL accepts any);
+ * ICP_ERR_INVALID_ARG for a missing or malformed file or an entry out of
+ * range. icp_create loads the file named by the environment variable
+ * ICP_TUNING_CACHE, else tuning_<arch>.json beside the library, when it
+ * exists and holds this device's arch. */
+icp_status icp_tuning_file_write(const char *path, const char *arch, const icp_tuning_entry *entries,
+                                 int n);
+icp_status icp_tuning_file_read(const char *path, const char *arch, icp_tuning_entry *out, int cap,
+                                int *n);
+
 /* Enable (1) or disable (0) per-pass kernel timing; resets the counters.
  * Applies to passes launched afterwards. */
 icp_status icp_profile(icp_ctx *ctx, int enable);

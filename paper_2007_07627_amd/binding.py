@@ -27,6 +27,8 @@ EXPORTED = ["icp_create", "icp_destroy", "icp_params_default", "icp_params_class
             "icp_register_dev",
             "icp_nn_query", "icp_nn_query_dev", "icp_nn_query_dev_noalloc", "icp_nu_min_auto", "icp_estimate_normals", "icp_batch_submit", "icp_poll",
             "icp_batch_wait_all", "icp_batch_config", "icp_profile", "icp_profile_read",
+            "icp_tuning_default", "icp_tuning_lookup", "icp_tuning_set", "icp_tuning_entries",
+            "icp_autotune", "icp_device_arch", "icp_tuning_file_write", "icp_tuning_file_read",
             "icp_status_str"]
 
 
@@ -50,6 +52,16 @@ class icp_result(C.Structure):
 class icp_profile_stats(C.Structure):
     _fields_ = [("nn_ms", C.c_double), ("reduce_ms", C.c_double), ("solve_ms", C.c_double),
                 ("passes", C.c_longlong)]
+
+
+class icp_tuning(C.Structure):
+    _fields_ = [("slice_min", C.c_int), ("list_margin", C.c_float), ("brute_clusters", C.c_int),
+                ("brute_items", C.c_int), ("grid_per_cu", C.c_int)]
+
+
+class icp_tuning_entry(C.Structure):
+    _fields_ = [("m_bucket", C.c_int), ("n_bucket", C.c_int), ("mode", C.c_int), ("method", C.c_int),
+                ("batch", C.c_int), ("tuning", icp_tuning), ("ms", C.c_double)]
 
 
 class icp_request(C.Structure):
@@ -98,6 +110,15 @@ def lib():
         L.icp_batch_config.argtypes = [vp, i32, i32]
         L.icp_profile.argtypes = [vp, i32]
         L.icp_profile_read.argtypes = [vp, C.POINTER(icp_profile_stats)]
+        L.icp_tuning_default.argtypes = [C.POINTER(icp_tuning)]
+        L.icp_tuning_lookup.argtypes = [vp, i64, i64, i32, i32, i32, C.POINTER(icp_tuning), C.POINTER(C.c_int)]
+        L.icp_tuning_set.argtypes = [vp, C.POINTER(icp_tuning_entry)]
+        L.icp_tuning_entries.argtypes = [vp, C.POINTER(icp_tuning_entry), i32, C.POINTER(C.c_int)]
+        L.icp_autotune.argtypes = [vp, i64, i64, i32, i32, i32, C.POINTER(icp_tuning_entry)]
+        L.icp_device_arch.argtypes = [i32, C.c_char_p, i32]
+        L.icp_tuning_file_write.argtypes = [C.c_char_p, C.c_char_p, C.POINTER(icp_tuning_entry), i32]
+        L.icp_tuning_file_read.argtypes = [C.c_char_p, C.c_char_p, C.POINTER(icp_tuning_entry), i32,
+                                           C.POINTER(C.c_int)]
         L.icp_status_str.argtypes = [i32]
         L.icp_status_str.restype = C.c_char_p
         for n in EXPORTED:
@@ -321,6 +342,88 @@ def icp_batch_wait_all(ctx):
 
 def icp_batch_config(ctx, passes_per_replay: int, max_slots: int):
     _check(lib().icp_batch_config(ctx, passes_per_replay, max_slots), "icp_batch_config")
+
+
+def tuning_dict(t: icp_tuning) -> dict:
+    return {f: getattr(t, f) for f, _ in icp_tuning._fields_}
+
+
+def entry_dict(e: icp_tuning_entry) -> dict:
+    d = {f: getattr(e, f) for f in ("m_bucket", "n_bucket", "mode", "method", "batch", "ms")}
+    d["tuning"] = tuning_dict(e.tuning)
+    return d
+
+
+def make_entry(m_bucket, n_bucket, mode, method, ms=0.0, batch=0, **tuning) -> icp_tuning_entry:
+    e = icp_tuning_entry()
+    e.m_bucket, e.n_bucket, e.mode, e.method, e.ms, e.batch = m_bucket, n_bucket, mode, method, ms, batch
+    t = icp_tuning()
+    _check(lib().icp_tuning_default(C.byref(t)), "icp_tuning_default")
+    for k, v in tuning.items():
+        setattr(t, k, v)
+    e.tuning = t
+    return e
+
+
+def icp_tuning_default() -> dict:
+    t = icp_tuning()
+    _check(lib().icp_tuning_default(C.byref(t)), "icp_tuning_default")
+    return tuning_dict(t)
+
+
+def icp_tuning_lookup(ctx, M, N, mode, method, batch=0):
+    """(tuning dict, found: 2 exact bucket, 1 nearby, 0 defaults) for the
+    synchronous calls (batch=0) or the batch engine (batch=1)."""
+    t = icp_tuning()
+    f = C.c_int(0)
+    _check(lib().icp_tuning_lookup(ctx, M, N, mode, method, batch, C.byref(t), C.byref(f)),
+           "icp_tuning_lookup")
+    return tuning_dict(t), f.value
+
+
+def icp_tuning_set(ctx, entry: icp_tuning_entry, raw=False):
+    rc = lib().icp_tuning_set(ctx, C.byref(entry))
+    if raw:
+        return rc
+    _check(rc, "icp_tuning_set")
+
+
+def icp_tuning_entries(ctx, cap=4096):
+    arr = (icp_tuning_entry * cap)()
+    n = C.c_int(0)
+    _check(lib().icp_tuning_entries(ctx, arr, cap, C.byref(n)), "icp_tuning_entries")
+    return [arr[i] for i in range(min(cap, n.value))]
+
+
+def icp_autotune(ctx, M, N, mode, method, batch=0) -> icp_tuning_entry:
+    e = icp_tuning_entry()
+    _check(lib().icp_autotune(ctx, M, N, mode, method, batch, C.byref(e)), "icp_autotune")
+    return e
+
+
+def icp_device_arch(device=0) -> str:
+    buf = C.create_string_buffer(64)
+    _check(lib().icp_device_arch(device, buf, 64), "icp_device_arch")
+    return buf.value.decode()
+
+
+def icp_tuning_file_write(path, arch, entries, raw=False):
+    arr = (icp_tuning_entry * max(1, len(entries)))(*entries)
+    rc = lib().icp_tuning_file_write(path.encode(), arch.encode(), arr, len(entries))
+    if raw:
+        return rc
+    _check(rc, "icp_tuning_file_write")
+
+
+def icp_tuning_file_read(path, arch=None, cap=4096, raw=False):
+    arr = (icp_tuning_entry * cap)()
+    n = C.c_int(0)
+    rc = lib().icp_tuning_file_read(path.encode(), None if arch is None else arch.encode(), arr, cap,
+                                    C.byref(n))
+    if raw:
+        return rc, [arr[i] for i in range(min(cap, n.value))]
+    _check(rc, "icp_tuning_file_read")
+    return [arr[i] for i in range(min(cap, n.value))]
 
 
 def icp_profile(ctx, enable: bool):

@@ -4,11 +4,14 @@
 // requests with continuous admission. Exposes the C ABI of include/icp.h.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -16,6 +19,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -46,7 +50,7 @@ void launch_hilbert_order(const float*, const float*, const float*, int, const f
 void launch_build_clusters(const float*, const float*, const float*, const unsigned*, int, int,
                            float4*, float4*, float4*, float4*, float4*, float4*, hipStream_t);
 void launch_build_super(const float4*, const float4*, const float4*, int, int, float4*, float4*,
-                        float*, hipStream_t);
+                        float*, float, hipStream_t);
 void launch_build_tiles(const float*, const float*, const float*, const unsigned*, int, int, float*,
                         float*, float*, int*, double4*, hipStream_t);
 void launch_fill_u64(unsigned long long*, int, unsigned long long, hipStream_t);
@@ -205,9 +209,19 @@ struct OwnedRequest {
   int32_t* idx_dev_out = nullptr;  // device outputs for a dev query
   float* d2_dev_out = nullptr;
   int trace_cap = 0;               // per-pass trace rows kept on the device
+  icp_tuning tune{kSliceMinDefault, kVerletFracDefault, kBruteClustersDefault, kBruteItemsDefault,
+                  kGridPerCuDefault};    // work partition of this request (no effect on results)
+  bool tune_fixed = false;         // tune set by the caller (autotuner), not looked up
   uint64_t ticket = 0;
   Clock::time_point t_submit;
 };
+
+// The search method a request runs: AUTO takes the exhaustive scan up to
+// 64e6 source x target pairs.
+static icp_nn_method resolve_method(int64_t M, int64_t N, icp_nn_method m) {
+  if (m == ICP_NN_AUTO) return ((double)M * (double)N <= 64.0e6) ? ICP_NN_BRUTE : ICP_NN_CLUSTER;
+  return m;
+}
 
 // nu_min <= 0 selects the automatic rule for the Welsch modes.
 static bool auto_nu_min(const icp_params* p) { return !mode_l2(p->mode) && !(p->nu_min > 0.0); }
@@ -276,6 +290,8 @@ struct Engine {
   bool gprof = false;
   bool gbrute = false;
   int nn_grid = 4096, epi_grid = 1024;
+  int cus = 256;
+  int gnn_grid = 0;          // search grid the captured graph was built with
   Arena* arena = nullptr;
   // profiling: timing events around the kernels of every pass
   bool prof = false;
@@ -312,8 +328,9 @@ struct Engine {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
       cus = prop.multiProcessorCount;
-    nn_grid = cus * 16;
+    nn_grid = cus * kGridPerCuDefault;
     epi_grid = cus * 4;
+    this->cus = cus;
     return true;
   }
 
@@ -396,7 +413,9 @@ struct Engine {
   }
 
   bool build_graph(int phases) {
-    if (gexec && gphases == phases && gcap == capacity && gprof == prof && gbrute == brute) return true;
+    if (gexec && gphases == phases && gcap == capacity && gprof == prof && gbrute == brute &&
+        gnn_grid == nn_grid)
+      return true;
     if (prof && !ensure_events(phases)) return false;
     if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
     if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
@@ -408,6 +427,7 @@ struct Engine {
     gcap = capacity;
     gprof = prof;
     gbrute = brute;
+    gnn_grid = nn_grid;
     return true;
   }
 
@@ -495,7 +515,7 @@ struct Engine {
     launch_build_clusters(F(L.o_qx), F(L.o_qy), F(L.o_qz), order, L.N, L.ncl, F4(L.o_qloc),
                           F4(L.o_qorg), F4(L.o_ccen), F4(L.o_clo), F4(L.o_chi), F4(L.o_kbox), ss);
     launch_build_super(F4(L.o_clo), F4(L.o_chi), F4(L.o_ccen), L.ncl, L.nsup, F4(L.o_slo),
-                       F4(L.o_shi), rho, ss);
+                       F4(L.o_shi), rho, r.tune.list_margin, ss);
     // automatic nu_min from the targets' six nearest neighbours, into the
     // state (scratch holds the per-target values until the source sort)
     if (r.numin_only || (!r.query && !r.eval && auto_nu_min(&r.prm))) {
@@ -549,9 +569,16 @@ struct Engine {
     icp_nn_method meth = r.query ? r.qmethod : r.prm.nn;
     if (meth == ICP_NN_AUTO) meth = ((double)L.M * L.N <= 64.0e6) ? ICP_NN_BRUTE : ICP_NN_CLUSTER;
     D.method = meth == ICP_NN_BRUTE ? NN_BRUTE : NN_CLUSTER;
-    if (!single && D.method == NN_BRUTE && brute_items64(L.ntile, L.ncl) > kMaxBruteItemsPerPair)
+    D.slice_min = r.tune.slice_min;
+    D.brute_clusters = r.tune.brute_clusters;
+    D.brute_items = r.tune.brute_items;
+    if (!single && D.method == NN_BRUTE &&
+        brute_items64(L.ntile, L.ncl, D.brute_clusters) > kMaxBruteItemsPerPair)
       D.method = NN_CLUSTER;
-    if (single) brute = D.method == NN_BRUTE;
+    if (single) {
+      brute = D.method == NN_BRUTE;
+      nn_grid = cus * r.tune.grid_per_cu;  // the one-slot engine's launch shape follows its pair
+    }
     D.mode = S.mode;
     HIP_OK(hipMemcpyAsync(d_desc + s, &D, offsetof(SlotDesc, rho_max), hipMemcpyHostToDevice, up));
     h.zero = 0;
@@ -698,6 +725,10 @@ struct icp_ctx {
   int max_slots = 256;
   int running = 0;
   int admitting = 0;    // popped from the queue, not yet running or finished
+  // work-partition table of the autotuner, per size bucket (tune_mu)
+  std::mutex tune_mu;
+  std::vector<icp_tuning_entry> tuning;
+  std::string arch;     // gcnArchName up to the first ':' (e.g. gfx950)
   std::vector<int> last_items;  // per NN work item of the last traced registration's last pass
 };
 
@@ -786,12 +817,72 @@ static icp_status check_params_sized(const icp_params* p, int64_t N) {
   return ICP_OK;
 }
 
+// ------------------------------------------------------------------ tuning table
+
+static int size_bucket(int64_t n) {
+  int b = 0;
+  while (b < 62 && (int64_t(1) << (b + 1)) <= n) ++b;
+  return b;
+}
+
+// Tuning entries are kept per mode family (point-to-point / point-to-plane)
+// and search method.
+static int mode_family(int mode) { return mode_plane(mode) ? ICP_P2PL_WELSCH : ICP_P2P_WELSCH; }
+
+static bool tuning_valid(const icp_tuning& t) {
+  return t.slice_min >= 1 && t.slice_min <= 64 && t.list_margin >= 0.0f && t.list_margin <= 1.0f &&
+         t.brute_clusters >= 1 && t.brute_clusters <= 4096 && t.brute_items >= 64 &&
+         t.brute_items <= (1 << 20) && t.grid_per_cu >= 1 && t.grid_per_cu <= 64;
+}
+
+static icp_tuning default_tuning() {
+  return icp_tuning{kSliceMinDefault, kVerletFracDefault, kBruteClustersDefault, kBruteItemsDefault,
+                    kGridPerCuDefault};
+}
+
+// The entry of the request's bucket; else the nearest tuned bucket of the same
+// family and method within two octaves (sum over M and N); else the defaults.
+// *found: 2 exact, 1 nearby, 0 default.
+static icp_tuning lookup_tuning(icp_ctx* ctx, int64_t M, int64_t N, int mode, icp_nn_method method,
+                                int batch, int* found) {
+  const int mb = size_bucket(M), nb = size_bucket(N), fam = mode_family(mode);
+  method = resolve_method(M, N, method);
+  std::lock_guard<std::mutex> g(ctx->tune_mu);
+  int best = -1, bestd = 3;
+  for (size_t i = 0; i < ctx->tuning.size(); ++i) {
+    const icp_tuning_entry& e = ctx->tuning[i];
+    if (e.mode != fam || e.method != (int)method || e.batch != batch) continue;
+    const int dd = std::abs(e.m_bucket - mb) + std::abs(e.n_bucket - nb);
+    if (dd < bestd) { bestd = dd; best = (int)i; }
+  }
+  if (found) *found = best < 0 ? 0 : (bestd == 0 ? 2 : 1);
+  return best < 0 ? default_tuning() : ctx->tuning[best].tuning;
+}
+
+static void put_tuning(icp_ctx* ctx, icp_tuning_entry e) {
+  e.mode = mode_family(e.mode);
+  std::lock_guard<std::mutex> g(ctx->tune_mu);
+  for (auto& x : ctx->tuning)
+    if (x.m_bucket == e.m_bucket && x.n_bucket == e.n_bucket && x.mode == e.mode && x.method == e.method &&
+        x.batch == e.batch) {
+      x = e;
+      return;
+    }
+  ctx->tuning.push_back(e);
+}
+
+static void tune_request(icp_ctx* ctx, OwnedRequest& r, int batch) {
+  const int mode = r.query ? (int)ICP_P2P_L2 : (int)r.prm.mode;
+  r.tune = lookup_tuning(ctx, r.M, r.N, mode, r.query ? r.qmethod : r.prm.nn, batch, nullptr);
+}
+
 // Run one slot of the synchronous engine to completion.
 static icp_status run_sync(icp_ctx* ctx, OwnedRequest& r, icp_result* out, void* ustream,
                            int32_t* host_idx, float* host_d2, double* host_trace = nullptr,
                            int* trace_len = nullptr, std::vector<int>* item_stats_out = nullptr) {
   Engine& E = ctx->sync_eng;
   const auto t0 = Clock::now();
+  if (!r.tune_fixed) tune_request(ctx, r, 0);
   hipStream_t us = reinterpret_cast<hipStream_t>(ustream);
   if (hipSetDevice(ctx->device) != hipSuccess) return ICP_ERR_DEVICE;
   // order after the caller's stream
@@ -1089,6 +1180,29 @@ icp_status icp_params_classical(icp_mode mode, icp_params* out) {
   return ICP_OK;
 }
 
+// The tuning cache of icp_create: $ICP_TUNING_CACHE, else tuning_<arch>.json
+// in the directory of this library. A missing or unreadable file leaves the
+// defaults.
+static void load_tuning_cache(icp_ctx* c) {
+  if (c->arch.empty()) return;
+  std::string path;
+  if (const char* env = std::getenv("ICP_TUNING_CACHE")) {
+    path = env;
+  } else {
+    Dl_info info;
+    if (dladdr(reinterpret_cast<void*>(&load_tuning_cache), &info) && info.dli_fname) {
+      path = info.dli_fname;
+      const size_t sl = path.find_last_of('/');
+      path = (sl == std::string::npos ? std::string(".") : path.substr(0, sl)) + "/tuning_" + c->arch + ".json";
+    }
+  }
+  if (path.empty()) return;
+  std::vector<icp_tuning_entry> e(4096);
+  int n = 0;
+  if (icp_tuning_file_read(path.c_str(), c->arch.c_str(), e.data(), (int)e.size(), &n) != ICP_OK) return;
+  for (int i = 0; i < n; ++i) put_tuning(c, e[i]);
+}
+
 icp_status icp_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
   if (!out) return ICP_ERR_INVALID_ARG;
   *out = nullptr;
@@ -1107,6 +1221,9 @@ icp_status icp_create(int device, size_t hbm_budget_bytes, icp_ctx** out) {
     delete c;
     return ICP_ERR_DEVICE;
   }
+  char arch[64];
+  if (icp_device_arch(device, arch, sizeof arch) == ICP_OK) c->arch = arch;
+  load_tuning_cache(c);
   *out = c;
   return ICP_OK;
 }
@@ -1390,6 +1507,9 @@ icp_status icp_nn_query_dev_noalloc(const float* P_dev, int64_t M, const float* 
   if (method == ICP_NN_AUTO) method = ((double)L.M * L.N <= 64.0e6) ? ICP_NN_BRUTE : ICP_NN_CLUSTER;
   D.method = method == ICP_NN_BRUTE ? NN_BRUTE : NN_CLUSTER;
   D.mode = P2P_L2;
+  D.slice_min = kSliceMinDefault;
+  D.brute_clusters = kBruteClustersDefault;
+  D.brute_items = kBruteItemsDefault;
   QueryT qt;
   std::memcpy(qt.T, T, sizeof qt.T);
   (void)hipGetLastError();
@@ -1403,7 +1523,7 @@ icp_status icp_nn_query_dev_noalloc(const float* P_dev, int64_t M, const float* 
   launch_build_clusters(F(L.o_qx), F(L.o_qy), F(L.o_qz), order, L.N, L.ncl, F4(L.o_qloc), F4(L.o_qorg),
                         F4(L.o_ccen), F4(L.o_clo), F4(L.o_chi), F4(L.o_kbox), st);
   launch_build_super(F4(L.o_clo), F4(L.o_chi), F4(L.o_ccen), L.ncl, L.nsup, F4(L.o_slo), F4(L.o_shi),
-                     rho, st);
+                     rho, kVerletFracDefault, st);
   launch_bbox(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, cP, st);
   launch_hilbert_order(F(L.o_pox), F(L.o_poy), F(L.o_poz), L.M, bbP, sort_scratch, &order, st);
   launch_build_tiles(F(L.o_pox), F(L.o_poy), F(L.o_poz), order, L.M, L.ntile, F(L.o_px), F(L.o_py),
@@ -1493,6 +1613,7 @@ icp_status icp_batch_submit(icp_ctx* ctx, const icp_request* reqs, int n, uint64
         return;
       }
       r->M = q.M; r->N = q.N; r->prm = q.params;
+      tune_request(ctx, *r, 1);
       r->t_submit = now;
       r->ticket = tickets_out[i];
       ctx->queue.push_back(std::move(r));
@@ -1541,6 +1662,332 @@ icp_status icp_profile_read(icp_ctx* ctx, icp_profile_stats* out) {
     out->solve_ms += E->prof_ms[2];
     out->passes += E->prof_passes;
   }
+  return ICP_OK;
+}
+
+icp_status icp_tuning_default(icp_tuning* out) {
+  if (!out) return ICP_ERR_INVALID_ARG;
+  *out = default_tuning();
+  return ICP_OK;
+}
+
+icp_status icp_tuning_lookup(icp_ctx* ctx, int64_t M, int64_t N, icp_mode mode, icp_nn_method method,
+                             int batch, icp_tuning* out, int* found) {
+  if (!ctx || !out || M <= 0 || N <= 0 || mode < ICP_P2P_L2 || mode > ICP_P2PL_L2 ||
+      method < ICP_NN_AUTO || method > ICP_NN_CLUSTER || (batch != 0 && batch != 1))
+    return ICP_ERR_INVALID_ARG;
+  *out = lookup_tuning(ctx, M, N, mode, method, batch, found);
+  return ICP_OK;
+}
+
+icp_status icp_tuning_set(icp_ctx* ctx, const icp_tuning_entry* e) {
+  if (!ctx || !e || e->m_bucket < 0 || e->m_bucket > 62 || e->n_bucket < 0 || e->n_bucket > 62 ||
+      e->mode < ICP_P2P_L2 || e->mode > ICP_P2PL_L2 ||
+      (e->method != ICP_NN_BRUTE && e->method != ICP_NN_CLUSTER) || (e->batch != 0 && e->batch != 1) ||
+      !tuning_valid(e->tuning))
+    return ICP_ERR_INVALID_ARG;
+  put_tuning(ctx, *e);
+  return ICP_OK;
+}
+
+icp_status icp_tuning_entries(icp_ctx* ctx, icp_tuning_entry* out, int cap, int* n) {
+  if (!ctx || !n || cap < 0 || (cap > 0 && !out)) return ICP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(ctx->tune_mu);
+  *n = (int)ctx->tuning.size();
+  for (int i = 0; i < std::min(cap, *n); ++i) out[i] = ctx->tuning[i];
+  return ICP_OK;
+}
+
+icp_status icp_device_arch(int device, char* out, int cap) {
+  if (!out || cap < 2) return ICP_ERR_INVALID_ARG;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return ICP_ERR_DEVICE;
+  std::string a(prop.gcnArchName);
+  a = a.substr(0, a.find(':'));
+  if ((int)a.size() + 1 > cap) return ICP_ERR_INVALID_ARG;
+  std::memcpy(out, a.c_str(), a.size() + 1);
+  return ICP_OK;
+}
+
+icp_status icp_tuning_file_write(const char* path, const char* arch, const icp_tuning_entry* e, int n) {
+  if (!path || !arch || n < 0 || (n > 0 && !e)) return ICP_ERR_INVALID_ARG;
+  for (const char* p = arch; *p; ++p)
+    if (*p == '"' || *p == '\\' || (unsigned char)*p < 32) return ICP_ERR_INVALID_ARG;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return ICP_ERR_INVALID_ARG;
+  std::fprintf(f, "{\"arch\": \"%s\", \"entries\": [", arch);
+  for (int i = 0; i < n; ++i) {
+    const icp_tuning_entry& x = e[i];
+    std::fprintf(f,
+                 "%s\n  {\"m_bucket\": %d, \"n_bucket\": %d, \"mode\": %d, \"method\": %d, \"batch\": %d, "
+                 "\"slice_min\": %d, \"list_margin\": %.9g, \"brute_clusters\": %d, "
+                 "\"brute_items\": %d, \"grid_per_cu\": %d, \"ms\": %.6g}",
+                 i ? "," : "", x.m_bucket, x.n_bucket, x.mode, x.method, x.batch, x.tuning.slice_min,
+                 (double)x.tuning.list_margin, x.tuning.brute_clusters, x.tuning.brute_items,
+                 x.tuning.grid_per_cu, x.ms);
+  }
+  std::fprintf(f, "\n]}\n");
+  return std::fclose(f) == 0 ? ICP_OK : ICP_ERR_INVALID_ARG;
+}
+
+// A small reader for the format above: the "arch" string, then every object
+// of the "entries" array as "key": number pairs.
+icp_status icp_tuning_file_read(const char* path, const char* arch, icp_tuning_entry* out, int cap,
+                                int* n) {
+  if (!path || !n || cap < 0 || (cap > 0 && !out)) return ICP_ERR_INVALID_ARG;
+  *n = 0;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return ICP_ERR_INVALID_ARG;
+  std::string txt;
+  char buf[4096];
+  for (size_t k; (k = std::fread(buf, 1, sizeof buf, f)) > 0;) txt.append(buf, k);
+  std::fclose(f);
+  size_t p = txt.find("\"arch\"");
+  if (p == std::string::npos) return ICP_ERR_INVALID_ARG;
+  p = txt.find('"', txt.find(':', p));
+  const size_t q = p == std::string::npos ? p : txt.find('"', p + 1);
+  if (q == std::string::npos) return ICP_ERR_INVALID_ARG;
+  const std::string farch = txt.substr(p + 1, q - p - 1);
+  size_t at = txt.find("\"entries\"");
+  if (at == std::string::npos || (at = txt.find('[', at)) == std::string::npos) return ICP_ERR_INVALID_ARG;
+  const size_t end = txt.find(']', at);
+  if (end == std::string::npos) return ICP_ERR_INVALID_ARG;
+  std::vector<icp_tuning_entry> got;
+  for (size_t o = txt.find('{', at); o != std::string::npos && o < end; o = txt.find('{', o + 1)) {
+    const size_t c = txt.find('}', o);
+    if (c == std::string::npos || c > end) return ICP_ERR_INVALID_ARG;
+    const std::string obj = txt.substr(o + 1, c - o - 1);
+    auto num = [&](const char* key, double* v) -> bool {
+      const std::string k = std::string("\"") + key + "\"";
+      const size_t kp = obj.find(k);
+      if (kp == std::string::npos) return false;
+      const size_t cp = obj.find(':', kp + k.size());
+      if (cp == std::string::npos) return false;
+      const char* s0 = obj.c_str() + cp + 1;
+      char* e0 = nullptr;
+      *v = std::strtod(s0, &e0);
+      return e0 != s0 && std::isfinite(*v);
+    };
+    double v[11];
+    const char* keys[11] = {"m_bucket", "n_bucket", "mode", "method", "batch", "slice_min", "list_margin",
+                            "brute_clusters", "brute_items", "grid_per_cu", "ms"};
+    for (int k = 0; k < 11; ++k)
+      if (!num(keys[k], &v[k])) return ICP_ERR_INVALID_ARG;
+    icp_tuning_entry x;
+    x.m_bucket = (int)v[0]; x.n_bucket = (int)v[1]; x.mode = (int)v[2]; x.method = (int)v[3];
+    x.batch = (int)v[4];
+    x.tuning.slice_min = (int)v[5];
+    x.tuning.list_margin = (float)v[6];
+    x.tuning.brute_clusters = (int)v[7];
+    x.tuning.brute_items = (int)v[8];
+    x.tuning.grid_per_cu = (int)v[9];
+    x.ms = v[10];
+    if (x.m_bucket < 0 || x.m_bucket > 62 || x.n_bucket < 0 || x.n_bucket > 62 || x.mode < 0 || x.mode > 3 ||
+        (x.method != ICP_NN_BRUTE && x.method != ICP_NN_CLUSTER) || (x.batch != 0 && x.batch != 1) ||
+        !tuning_valid(x.tuning))
+      return ICP_ERR_INVALID_ARG;
+    got.push_back(x);
+    o = c;
+  }
+  if (arch && farch != arch) return ICP_OK;  // another architecture's table: nothing for this one
+  *n = (int)got.size();
+  for (int i = 0; i < std::min(cap, *n); ++i) out[i] = got[i];
+  return ICP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ autotuner
+
+// Test pair of the tuner: a bumpy sphere r = 1 + 0.1 sin(3 theta) sin(4 phi),
+// targets on u_z >= -7/13, sources independently on u_z <= 7/13 moved by 20
+// degrees and a small translation, noise 2e-3 diag, 10% uniform outliers;
+// radial normals. Its own xorshift generator (timing input only).
+namespace {
+struct TuneRng {
+  uint64_t s;
+  uint64_t next() { s ^= s << 13; s ^= s >> 7; s ^= s << 17; return s; }
+  double uni() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
+  double gauss() {
+    const double u1 = std::max(uni(), 1e-300), u2 = uni();
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+  }
+};
+
+void bumpy(TuneRng& g, int64_t n, double zlo, double zhi, std::vector<float>& pts, std::vector<float>* nrm) {
+  pts.resize(3 * n);
+  if (nrm) nrm->resize(3 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double z = zlo + (zhi - zlo) * g.uni(), ph = 6.283185307179586 * g.uni();
+    const double st = std::sqrt(std::max(0.0, 1.0 - z * z)), th = std::acos(z);
+    const double u[3] = {st * std::cos(ph), st * std::sin(ph), z};
+    const double r = 1.0 + 0.1 * std::sin(3.0 * th) * std::sin(4.0 * ph);
+    for (int a = 0; a < 3; ++a) {
+      pts[3 * i + a] = (float)(r * u[a]);
+      if (nrm) (*nrm)[3 * i + a] = (float)u[a];
+    }
+  }
+}
+
+void tune_pair(int64_t M, int64_t N, std::vector<float>& P, std::vector<float>& Q, std::vector<float>& Qn,
+               double* diag) {
+  TuneRng g{0x9e3779b97f4a7c15ull ^ (uint64_t)(M * 1000003 + N)};
+  bumpy(g, N, -7.0 / 13.0, 1.0, Q, &Qn);
+  float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
+  for (int64_t i = 0; i < N; ++i)
+    for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], Q[3 * i + a]); hi[a] = std::max(hi[a], Q[3 * i + a]); }
+  *diag = std::sqrt(double(hi[0] - lo[0]) * (hi[0] - lo[0]) + double(hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                    double(hi[2] - lo[2]) * (hi[2] - lo[2]));
+  bumpy(g, M, -1.0, 7.0 / 13.0, P, nullptr);
+  const double ang = 20.0 * 3.141592653589793 / 180.0, k[3] = {0.2672612, 0.5345225, 0.8017837};
+  const double c = std::cos(ang), s = std::sin(ang);
+  const double R[9] = {c + k[0] * k[0] * (1 - c), k[0] * k[1] * (1 - c) - k[2] * s, k[0] * k[2] * (1 - c) + k[1] * s,
+                       k[1] * k[0] * (1 - c) + k[2] * s, c + k[1] * k[1] * (1 - c), k[1] * k[2] * (1 - c) - k[0] * s,
+                       k[2] * k[0] * (1 - c) - k[1] * s, k[2] * k[1] * (1 - c) + k[0] * s, c + k[2] * k[2] * (1 - c)};
+  const double t[3] = {0.05, -0.03, 0.02}, sig = 2e-3 * *diag;
+  float plo[3] = {1e30f, 1e30f, 1e30f}, phi[3] = {-1e30f, -1e30f, -1e30f};
+  for (int64_t i = 0; i < M; ++i) {
+    double x[3];
+    for (int a = 0; a < 3; ++a) x[a] = P[3 * i + a] + sig * g.gauss();
+    for (int a = 0; a < 3; ++a) {
+      P[3 * i + a] = (float)(R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2] + t[a]);
+      plo[a] = std::min(plo[a], P[3 * i + a]);
+      phi[a] = std::max(phi[a], P[3 * i + a]);
+    }
+  }
+  for (int64_t i = 0; i < M; ++i)
+    if (g.uni() < 0.1)
+      for (int a = 0; a < 3; ++a) P[3 * i + a] = (float)(plo[a] + (phi[a] - plo[a]) * g.uni());
+}
+}  // namespace
+
+extern "C" {
+
+icp_status icp_autotune(icp_ctx* ctx, int64_t M, int64_t N, icp_mode mode, icp_nn_method method,
+                        int batch, icp_tuning_entry* best_out) {
+  if (!ctx || check_sizes(M, N) != ICP_OK || mode < ICP_P2P_L2 || mode > ICP_P2PL_L2 ||
+      method < ICP_NN_AUTO || method > ICP_NN_CLUSTER || (batch != 0 && batch != 1))
+    return ICP_ERR_INVALID_ARG;
+  method = resolve_method(M, N, method);
+  const bool plane = mode_plane(mode);
+  std::vector<float> P, Q, Qn;
+  double diag = 1.0;
+  tune_pair(M, N, P, Q, Qn, &diag);
+  icp_params prm;
+  icp_params_default(mode, &prm);
+  prm.nu_min = mode_l2(mode) ? 0.0 : (plane ? 1e-3 : 1e-3 * diag);
+  prm.max_total_iter = 40;
+  prm.nn = method;
+  prm.engine = ICP_ENGINE_GRAPH;
+  const icp_tuning d0 = default_tuning();
+  std::vector<icp_tuning> cands{d0};
+  for (int grid : {8, 16, 32}) {
+    if (batch && grid != d0.grid_per_cu) continue;  // the batch engine's grid is not per pair
+    if (method == ICP_NN_CLUSTER) {
+      for (int sm : {4, 6, 8, 12})
+        for (float mg : {0.04f, 0.08f, 0.16f}) {
+          icp_tuning t = d0;
+          t.slice_min = sm; t.list_margin = mg; t.grid_per_cu = grid;
+          cands.push_back(t);
+        }
+    } else if (!batch) {
+      for (int bi : {2048, 4096, 8192, 16384, 32768}) {
+        icp_tuning t = d0;
+        t.brute_items = bi; t.grid_per_cu = grid;
+        cands.push_back(t);
+      }
+    } else {
+      for (int cpi : {4, 8, 16, 32}) {
+        icp_tuning t = d0;
+        t.brute_clusters = cpi;
+        cands.push_back(t);
+      }
+    }
+  }
+  icp_tuning_entry e;
+  e.m_bucket = size_bucket(M);
+  e.n_bucket = size_bucket(N);
+  e.mode = mode_family(mode);
+  e.method = method;
+  e.batch = batch;
+  e.tuning = d0;
+  e.ms = 0.0;
+  // reference result of the defaults (the pair alone)
+  icp_result ref{};
+  {
+    std::lock_guard<std::mutex> g(ctx->sync_mu);
+    OwnedRequest r;
+    r.P = P; r.Q = Q;
+    if (plane) r.Qn = Qn;
+    r.M = M; r.N = N; r.prm = prm;
+    r.tune = d0;
+    r.tune_fixed = true;
+    const icp_status rc = run_sync(ctx, r, &ref, nullptr, nullptr, nullptr);
+    if (rc != ICP_OK) return rc;
+  }
+  double best_ms = 1e300;
+  icp_tuning best = d0;
+  // copies in flight for the batch kind: 16, fewer for large pairs (about
+  // 4e6 points in flight)
+  const int copies = (int)std::max<int64_t>(2, std::min<int64_t>(16, 4000000 / (M + N)));
+  std::vector<icp_request> reqs(batch ? copies : 0);
+  for (auto& q : reqs) {
+    q.P = P.data(); q.M = M; q.Q = Q.data(); q.Qn = plane ? Qn.data() : nullptr; q.N = N; q.params = prm;
+  }
+  // the table entry of this bucket while the batch candidates run (restored below)
+  std::vector<icp_tuning_entry> saved;
+  {
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    saved = ctx->tuning;
+  }
+  icp_status status = ICP_OK;
+  for (size_t ci = 0; ci < cands.size() && status == ICP_OK; ++ci) {
+    double ms = 1e300;
+    for (int rep = 0; rep < 3 && status == ICP_OK; ++rep) {
+      if (!batch) {
+        std::lock_guard<std::mutex> g(ctx->sync_mu);
+        OwnedRequest r;
+        r.P = P; r.Q = Q;
+        if (plane) r.Qn = Qn;
+        r.M = M; r.N = N; r.prm = prm;
+        r.tune = cands[ci];
+        r.tune_fixed = true;
+        icp_result res{};
+        status = run_sync(ctx, r, &res, nullptr, nullptr, nullptr);
+        if (status == ICP_OK && (std::memcmp(res.T, ref.T, sizeof ref.T) != 0 || res.nn_passes != ref.nn_passes))
+          status = ICP_ERR_DEVICE;  // a partition must never change the result
+        if (rep > 0) ms = std::min(ms, res.latency_ms);
+      } else {
+        icp_tuning_entry t = e;
+        t.tuning = cands[ci];
+        put_tuning(ctx, t);
+        std::vector<uint64_t> tk(reqs.size());
+        const auto t0 = Clock::now();
+        status = icp_batch_submit(ctx, reqs.data(), (int)reqs.size(), tk.data());
+        if (status == ICP_OK) status = icp_batch_wait_all(ctx);
+        const double el = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+        for (uint64_t k : tk) {
+          icp_result res{};
+          const icp_status pr = icp_poll(ctx, k, &res);
+          if (status == ICP_OK && pr != ICP_OK) status = pr;
+          if (status == ICP_OK &&
+              (std::memcmp(res.T, ref.T, sizeof ref.T) != 0 || res.nn_passes != ref.nn_passes))
+            status = ICP_ERR_DEVICE;
+        }
+        if (rep > 0) ms = std::min(ms, el);
+      }
+    }
+    if (status == ICP_OK && ms < best_ms) { best_ms = ms; best = cands[ci]; }
+  }
+  if (status != ICP_OK) {
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    ctx->tuning = saved;
+    return status;
+  }
+  e.tuning = best;
+  e.ms = best_ms;
+  put_tuning(ctx, e);
+  if (best_out) *best_out = e;
   return ICP_OK;
 }
 

@@ -27,8 +27,13 @@ constexpr int kMaxSlices = 64;   // slices per tile in cluster mode
 // drawing the slices beyond kMaxSlices from a per-pair budget of kExtraSlices.
 constexpr int kMaxLongSlices = 1024;
 constexpr int kExtraSlices = 8192;
-constexpr int kSliceMin = 6;     // clusters per slice at least (cluster mode)
-constexpr float kVerletFrac = 0.08f;  // candidate-list margin / median cluster radius
+// Defaults of the tunable work partition (each slot carries its own values,
+// chosen per size bucket by the autotuner; none of them changes a result).
+constexpr int kSliceMinDefault = 6;      // clusters per slice at least (cluster mode)
+constexpr float kVerletFracDefault = 0.08f;  // candidate-list margin / median cluster radius
+constexpr int kBruteClustersDefault = 8;     // clusters per exhaustive item (multi-slot engine)
+constexpr int kBruteItemsDefault = 8192;     // exhaustive items per pass (one-slot engine)
+constexpr int kGridPerCuDefault = 16;        // workgroups per CU of the persistent search kernels
 
 // tile record flags (cull kernel -> slice kernel)
 enum TileFlags { TI_WARM = 1, TI_LIST = 2, TI_RANGE = 4, TI_LANETEST = 8 };
@@ -105,6 +110,9 @@ struct SlotDesc {
   int M, N, ntile, ncl, nsup, nepi;
   int method;                 // NN_BRUTE or NN_CLUSTER
   int mode;
+  int slice_min;              // clusters per slice at least (cluster search)
+  int brute_clusters;         // clusters per exhaustive item (multi-slot engine)
+  int brute_items;            // exhaustive items per pass (one-slot engine)
   float rho_max;              // max cluster radius (upper bound)
   float verlet;               // candidate-list margin: lists built with this
                               // slack stay valid while no source moves farther
@@ -194,20 +202,19 @@ struct WorkList {
 };
 
 // Exhaustive method in the multi-slot engine: one item = a pair of 64-source
-// tiles against a range of about kBruteItemClusters clusters.
-constexpr int kBruteItemClusters = 8;
-__host__ __device__ inline int brute_split(int ncl) {
-  return ncl > 0 ? (ncl + kBruteItemClusters - 1) / kBruteItemClusters : 1;
+// tiles against a range of about cpi clusters (the slot's brute_clusters).
+__host__ __device__ inline int brute_split(int ncl, int cpi) {
+  return ncl > 0 ? (ncl + cpi - 1) / cpi : 1;
 }
-__host__ __device__ inline long long brute_items64(int ntile, int ncl) {
-  return (long long)((ntile + 1) / 2) * (long long)brute_split(ncl);
+__host__ __device__ inline long long brute_items64(int ntile, int ncl, int cpi) {
+  return (long long)((ntile + 1) / 2) * (long long)brute_split(ncl, cpi);
 }
 // Items of one pair in the multi-slot engine are capped so that the planner's
 // int prefix over kMaxSlots pairs cannot overflow (1024 x 2^20 < 2^31); a pair
 // beyond the cap is searched with the cluster method, whose result is the same.
 constexpr long long kMaxBruteItemsPerPair = 1ll << 20;
-__host__ __device__ inline int brute_items(int ntile, int ncl) {
-  return (int)brute_items64(ntile, ncl);
+__host__ __device__ inline int brute_items(int ntile, int ncl, int cpi) {
+  return (int)brute_items64(ntile, ncl, cpi);
 }
 
 // Element i of a device array through a global-address-space pointer. The

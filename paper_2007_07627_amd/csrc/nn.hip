@@ -455,18 +455,19 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
       }
     }
     __syncthreads();
-    // slices of at least kSliceMin candidates, at most kMaxSlices per tile
-    int len = max(kSliceMin, (n + kMaxSlices - 1) / kMaxSlices);
+    // slices of at least slice_min candidates, at most kMaxSlices per tile
+    const int smin = D.slice_min;
+    int len = max(smin, (n + kMaxSlices - 1) / kMaxSlices);
     int nsl = max(1, (n + len - 1) / len);
     // each slice record carries everything the slice kernel needs, so that
     // its first loads do not wait on a tile record
     if (wv == 0) {
       int base = 0;
       if (lane == 0) {
-        if (len > kSliceMin) {
+        if (len > smin) {
           // a long candidate sequence (rare) is cut into shorter slices while
           // the pair's budget of extra slices lasts: its slices would set the tail
-          const int l2 = max(kSliceMin, (n + kMaxLongSlices - 1) / kMaxLongSlices);
+          const int l2 = max(smin, (n + kMaxLongSlices - 1) / kMaxLongSlices);
           const int n2 = (n + l2 - 1) / l2;
           if (n2 > nsl && atomicAdd(D.scount + 1, n2 - kMaxSlices) + (n2 - kMaxSlices) <= kExtraSlices) {
             len = l2;
@@ -591,10 +592,30 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     lane_point_from(D, S.Teval, valid, spx, spy, spz, prev, ptx, pty, ptz, W);
     // The next cluster's targets are loaded into registers while the current
     // one, staged in LDS, is filtered.
+    // every lane's warm bound: a cluster beyond it for every lane is beyond
+    // winner_threshold(min(H, W)) too, so the test at filter time would skip
+    // it; testing the batch's boxes first keeps such clusters out of the
+    // load pipeline (their 2 KB would otherwise be fetched and waited for)
+    const float thr_w = winner_threshold(W);
     for (int gb = 0; gb < nent; gb += 64) {
       if (gb > 0) batch(gb, myc, mcc, mlo, mhi);
       const int gn = min(64, nent - gb);
-      const unsigned long long live = __ballot(lane < gn && myc >= 0);
+      unsigned long long live = __ballot(lane < gn && myc >= 0);
+      if (lane_test && (flags & TI_WARM)) {
+        unsigned long long need = 0ull;
+        for (unsigned long long m = live; m; m &= m - 1ull) {
+          const int jj = __builtin_ctzll(m);
+          if (gb + jj < lead) {  // the nearest cluster is never box-tested
+            need |= 1ull << jj;
+            continue;
+          }
+          const float4 blo = make_float4(lane_f(mlo.x, jj), lane_f(mlo.y, jj), lane_f(mlo.z, jj), 0.f);
+          const float4 bhi = make_float4(lane_f(mhi.x, jj), lane_f(mhi.y, jj), lane_f(mhi.z, jj), 0.f);
+          const float lb2 = box_lb2(ptx, pty, ptz, blo, bhi);
+          if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr_w)) need |= 1ull << jj;
+        }
+        live = need;
+      }
       if (live == 0ull) continue;
       int j = __builtin_ctzll(live);
       int c = __builtin_amdgcn_readlane(myc, j);
@@ -718,10 +739,9 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
 // wavefront holds two tiles (two sources per lane), so every target read from
 // LDS serves two pairs, which halves the LDS traffic per pair. Items are
 // (pair of tiles, cluster range), shared out statically (they cost the same):
-// in the one-slot engine on a fixed grid of about kBruteItems, in the
-// multi-slot engine brute_items per pair (about kBruteItemClusters clusters
-// per item).
-constexpr int kBruteItems = 8192;
+// in the one-slot engine on a fixed grid of about the slot's brute_items, in
+// the multi-slot engine brute_items() per pair (about the slot's
+// brute_clusters clusters per item).
 
 // Folds one chunk into a lane's state (the bookkeeping of filter_chunk): m is
 // the chunk's minimum of h - pl . ql, v = 2 m + |pl|^2 with bounds lo, hi.
@@ -887,7 +907,7 @@ __global__ __launch_bounds__(64) void nn_brute_kernel(const SlotDesc* __restrict
   if (S.status != ST_RUNNING || S.reuse) return;
   const int ncl = D.ncl;
   const int npair = (D.ntile + 1) / 2;
-  const int split = min(ncl, max(1, (kBruteItems + npair - 1) / npair));
+  const int split = min(ncl, max(1, (D.brute_items + npair - 1) / npair));
   const int len = (ncl + split - 1) / split;
   const int nitems = npair * split;
   for (int g = blockIdx.x; g < nitems; g += gridDim.x) {
@@ -912,7 +932,7 @@ __global__ __launch_bounds__(64) void nn_brute_multi_kernel(const SlotDesc* __re
     const SlotDesc& D = descs[slot];
     const SlotState& S = states[slot];
     const int item = g - wl->b_base[a];
-    const int split = brute_split(D.ncl);
+    const int split = brute_split(D.ncl, D.brute_clusters);
     const int len = (D.ncl + split - 1) / split;
     const int pi = item / split, k = item - pi * split;
     const int c0 = k * len, c1 = min(D.ncl, c0 + len);

@@ -325,7 +325,8 @@ __global__ __launch_bounds__(64) void build_super_kernel(const float4* __restric
                                                          const float4* __restrict__ ccen, int ncl,
                                                          int nsup, float4* __restrict__ slo,
                                                          float4* __restrict__ shi,
-                                                         float* __restrict__ rho_out) {
+                                                         float* __restrict__ rho_out,
+                                                         float verlet_frac) {
   float rmax = 0.0f;
   for (int s = threadIdx.x; s < nsup; s += 64) {
     float4 lo = make_float4(__builtin_inff(), __builtin_inff(), __builtin_inff(), 0.f);
@@ -340,8 +341,8 @@ __global__ __launch_bounds__(64) void build_super_kernel(const float4* __restric
   }
   for (int o = 32; o > 0; o >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, o, 64));
   // Median cluster radius from a histogram with four bins per octave; the
-  // candidate-list margin is a fixed fraction of it (about half the sample
-  // spacing of a surface cluster).
+  // candidate-list margin is a fraction of it (by default about half the
+  // sample spacing of a surface cluster).
   __shared__ int hist[256];
   for (int b = threadIdx.x; b < 256; b += 64) hist[b] = 0;
   __syncthreads();
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(64) void build_super_kernel(const float4* __restric
     }
     const float rmed = exp2f((b + 1) * 0.25f - 48.0f);  // upper edge of the median bin
     rho_out[0] = rmax;
-    rho_out[1] = kVerletFrac * rmed;
+    rho_out[1] = verlet_frac * rmed;
   }
 }
 
@@ -421,7 +422,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__
     // exhaustive method: its own items whenever the pair searches
     const bool search = !states[t].reuse;
     if (D.method == NN_BRUTE) {
-      bi = search ? brute_items(D.ntile, D.ncl) : 0;
+      bi = search ? brute_items(D.ntile, D.ncl, D.brute_clusters) : 0;
     } else {
       nn = (search && states[t].cull) ? D.ntile : 0;
       if (nn) {
@@ -513,9 +514,9 @@ void launch_build_clusters(const float* x, const float* y, const float* z, const
 }
 
 void launch_build_super(const float4* clo, const float4* chi, const float4* ccen, int ncl, int nsup,
-                        float4* slo, float4* shi, float* rho_out, hipStream_t st) {
+                        float4* slo, float4* shi, float* rho_out, float verlet_frac, hipStream_t st) {
   hipLaunchKernelGGL(build_super_kernel, dim3(1), dim3(64), 0, st, clo, chi, ccen, ncl, nsup, slo, shi,
-                     rho_out);
+                     rho_out, verlet_frac);
 }
 
 void launch_build_tiles(const float* x, const float* y, const float* z, const unsigned* order, int m,
