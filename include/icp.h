@@ -333,8 +333,8 @@ icp_status icp_tuning_entries(icp_ctx *ctx, icp_tuning_entry *out, int cap, int 
  * iterations) under each candidate setting, each timed as the best of two
  * runs. batch = 0 (synchronous calls, the pair alone): cluster search
  * slice_min {4, 6, 8, 12} x list_margin {0.04, 0.08, 0.16} x grid_per_cu
- * {8, 16, 32}; exhaustive: brute_items {2048 .. 32768} x grid_per_cu
- * {8, 16, 32}. batch = 1 (16 copies of the pair at once through the batch
+ * {8, 16, 32}; exhaustive: brute_items {2048, 4096, 8192, 12288, 16384,
+ * 24576, 32768} x grid_per_cu {8, 16, 32}. batch = 1 (16 copies of the pair at once through the batch
  * engine, fewer for large pairs: about 4e6 points in flight): cluster
  * search slice_min x list_margin as above; exhaustive:
  * brute_clusters {4, 8, 16, 32}. Every candidate must return the defaults'

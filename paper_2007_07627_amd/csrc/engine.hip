@@ -1891,7 +1891,7 @@ icp_status icp_autotune(icp_ctx* ctx, int64_t M, int64_t N, icp_mode mode, icp_n
           cands.push_back(t);
         }
     } else if (!batch) {
-      for (int bi : {2048, 4096, 8192, 16384, 32768}) {
+      for (int bi : {2048, 4096, 8192, 12288, 16384, 24576, 32768}) {
         icp_tuning t = d0;
         t.brute_items = bi; t.grid_per_cu = grid;
         cands.push_back(t);

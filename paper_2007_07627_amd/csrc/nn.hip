@@ -765,23 +765,27 @@ __device__ __forceinline__ void lane_best_update(LaneBest& L, float m, float pp,
 
 // One cluster staged in LDS against two sources per lane. The bookkeeping runs
 // per group of kBruteGroup targets (the rescan of a winning group covers all
-// of it), and the targets are read in runs of eight so that at most eight
-// reads are in flight.
-constexpr int kBruteGroup = 32;
+// of it); the targets are read in runs of eight, so that at most eight reads
+// are in flight, and each run is folded into the group's minimum with
+// three-way minima (32 for the 64 values of a source, the fewest that reduce
+// 64 values with them).
+constexpr int kBruteGroup = 64;
 constexpr int kGroupsPerCluster = kCluster / kBruteGroup;
 __device__ __forceinline__ void filter_cluster_pair(const float4* __restrict__ tg, int c,
                                                     const float (&pa)[3], const float (&pb)[3],
                                                     float rho_c, LaneBest& La, LaneBest& Lb) {
   const float ppa = __builtin_fmaf(pa[2], pa[2], __builtin_fmaf(pa[1], pa[1], pa[0] * pa[0]));
   const float ppb = __builtin_fmaf(pb[2], pb[2], __builtin_fmaf(pb[1], pb[1], pb[0] * pb[0]));
-  const float ta = sqrtf(ppa) + rho_c, tb = sqrtf(ppb) + rho_c;
+  // the hardware square root (within a few units in the last place) suffices:
+  // the bound below carries a 1e-4 relative margin
+  const float ta = __builtin_amdgcn_sqrtf(ppa) + rho_c, tb = __builtin_amdgcn_sqrtf(ppb) + rho_c;
   const float da = 0x1.0p-22f * 7.0f * 1.0001f * ta * ta;
   const float db = 0x1.0p-22f * 7.0f * 1.0001f * tb * tb;
 #pragma unroll 1
   for (int ch = 0; ch < kGroupsPerCluster; ++ch) {
     const float4* qc = tg + ch * kBruteGroup;
     constexpr int kRuns = kBruteGroup / 8;
-    float ma[kRuns], mb[kRuns];
+    float ma = 0.0f, mb = 0.0f;
 #pragma unroll
     for (int h = 0; h < kRuns; ++h) {
       float a[8], b[8];
@@ -791,16 +795,21 @@ __device__ __forceinline__ void filter_cluster_pair(const float4* __restrict__ t
         a[j] = __builtin_fmaf(-pa[0], q.x, __builtin_fmaf(-pa[1], q.y, __builtin_fmaf(-pa[2], q.z, q.w)));
         b[j] = __builtin_fmaf(-pb[0], q.x, __builtin_fmaf(-pb[1], q.y, __builtin_fmaf(-pb[2], q.z, q.w)));
       }
-      ma[h] = fminf(fminf(fminf(a[0], a[1]), a[2]), fminf(fminf(a[3], a[4]), a[5]));
-      ma[h] = fminf(fminf(ma[h], a[6]), a[7]);
-      mb[h] = fminf(fminf(fminf(b[0], b[1]), b[2]), fminf(fminf(b[3], b[4]), b[5]));
-      mb[h] = fminf(fminf(mb[h], b[6]), b[7]);
+      if (h == 0) {
+        ma = fminf(fminf(fminf(fminf(a[0], a[1]), a[2]), fminf(fminf(a[3], a[4]), a[5])), fminf(a[6], a[7]));
+        mb = fminf(fminf(fminf(fminf(b[0], b[1]), b[2]), fminf(fminf(b[3], b[4]), b[5])), fminf(b[6], b[7]));
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          ma = fminf(fminf(ma, a[j]), a[j + 1]);
+          mb = fminf(fminf(mb, b[j]), b[j + 1]);
+        }
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
-    static_assert(kBruteGroup == 32, "the group minimum below combines four runs");
     const int id = c * kGroupsPerCluster + ch;
-    lane_best_update(La, fminf(fminf(ma[0], ma[1]), fminf(ma[2], ma[3])), ppa, da, id);
-    lane_best_update(Lb, fminf(fminf(mb[0], mb[1]), fminf(mb[2], mb[3])), ppb, db, id);
+    lane_best_update(La, ma, ppa, da, id);
+    lane_best_update(Lb, mb, ppb, db, id);
   }
 }
 
