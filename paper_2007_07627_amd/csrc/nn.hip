@@ -103,6 +103,22 @@ __device__ __forceinline__ unsigned long long exact_scan(const float4* qorg, int
 }
 
 
+// The same lower bound with fused multiply-adds (fewer roundings). Callers
+// compare it against a threshold raised by 2^-19 for its rounding: lb2 <=
+// thr (1 + 2^-19) holds whenever lb2 (1 - 2^-20) <= thr does.
+__device__ __forceinline__ float box_lb2_fma(float px, float py, float pz, float4 lo, float4 hi) {
+  const float dx = fmaxf(fmaxf(lo.x - px, px - hi.x), 0.0f);
+  const float dy = fmaxf(fmaxf(lo.y - py, py - hi.y), 0.0f);
+  const float dz = fmaxf(fmaxf(lo.z - pz, pz - hi.z), 0.0f);
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
+// Some lane of `lanes` (a ballot of the lanes that take part) has `need`: the
+// vote as one 64-bit ballot, kept in scalar registers.
+__device__ __forceinline__ bool wave_any_of(bool need, unsigned long long lanes) {
+  return (__builtin_amdgcn_ballot_w64(need) & lanes) != 0ull;
+}
+
 __device__ __forceinline__ float box_ub2(float px, float py, float pz, float4 lo, float4 hi) {
   const float dx = fmaxf(fabsf(px - lo.x), fabsf(px - hi.x));
   const float dy = fmaxf(fabsf(py - lo.y), fabsf(py - hi.y));
@@ -178,19 +194,21 @@ template <bool kPrune>
 __device__ __forceinline__ int filter_cluster(const float4* __restrict__ tg,
                                                const float4* __restrict__ bx, int c, float plx,
                                                float ply, float plz, float rho_c, float px,
-                                               float py, float pz, bool valid, float W,
+                                               float py, float pz, unsigned long long vmask, float W,
                                                LaneBest& L) {
   const float npx = -plx, npy = -ply, npz = -plz;
   const float pp = __builtin_fmaf(plz, plz, __builtin_fmaf(ply, ply, plx * plx));
-  const float t = sqrtf(pp) + rho_c;
+  // the hardware square root (within a few units in the last place) suffices:
+  // the bound below carries a 1e-4 relative margin
+  const float t = __builtin_amdgcn_sqrtf(pp) + rho_c;
   const float delta = 0x1.0p-22f * 7.0f * 1.0001f * t * t;
   if (kPrune) {
-    const float thr = winner_threshold(fminf(L.H, W));
+    const float thr = winner_threshold(fminf(L.H, W)) * (1.0f + 0x1.0p-19f);
     unsigned mask = 0;
 #pragma unroll
     for (int ch = 0; ch < kChunksPerCluster; ++ch) {
-      const float lb2 = box_lb2(px, py, pz, bx[2 * ch], bx[2 * ch + 1]);
-      if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr)) mask |= 1u << ch;
+      const float lb2 = box_lb2_fma(px, py, pz, bx[2 * ch], bx[2 * ch + 1]);
+      if (wave_any_of(lb2 <= thr, vmask)) mask |= 1u << ch;
     }
     const int n = __builtin_popcount(mask);
     for (; mask; mask &= mask - 1u) {
@@ -596,7 +614,8 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     // winner_threshold(min(H, W)) too, so the test at filter time would skip
     // it; testing the batch's boxes first keeps such clusters out of the
     // load pipeline (their 2 KB would otherwise be fetched and waited for)
-    const float thr_w = winner_threshold(W);
+    const float thr_w = winner_threshold(W) * (1.0f + 0x1.0p-19f);
+    const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
     for (int gb = 0; gb < nent; gb += 64) {
       if (gb > 0) batch(gb, myc, mcc, mlo, mhi);
       const int gn = min(64, nent - gb);
@@ -611,8 +630,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
           }
           const float4 blo = make_float4(lane_f(mlo.x, jj), lane_f(mlo.y, jj), lane_f(mlo.z, jj), 0.f);
           const float4 bhi = make_float4(lane_f(mhi.x, jj), lane_f(mhi.y, jj), lane_f(mhi.z, jj), 0.f);
-          const float lb2 = box_lb2(ptx, pty, ptz, blo, bhi);
-          if (__any(valid && lb2 * (1.0f - 0x1.0p-20f) <= thr_w)) need |= 1ull << jj;
+          if (wave_any_of(box_lb2_fma(ptx, pty, ptz, blo, bhi) <= thr_w, vmask)) need |= 1ull << jj;
         }
         live = need;
       }
@@ -646,18 +664,19 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
           // every target of the cluster is at exact squared distance >= lb2
           const float4 blo = make_float4(lane_f(mlo.x, j), lane_f(mlo.y, j), lane_f(mlo.z, j), 0.f);
           const float4 bhi = make_float4(lane_f(mhi.x, j), lane_f(mhi.y, j), lane_f(mhi.z, j), 0.f);
-          const float lb2 = box_lb2(ptx, pty, ptz, blo, bhi);
-          run = __any(valid && lb2 * (1.0f - 0x1.0p-20f) <= winner_threshold(fminf(L.H, W)));
+          run = wave_any_of(box_lb2_fma(ptx, pty, ptz, blo, bhi) <=
+                                winner_threshold(fminf(L.H, W)) * (1.0f + 0x1.0p-19f),
+                            vmask);
         }
         if (run) {
           const float plx = ptx - lane_f(mcc.x, j), ply = pty - lane_f(mcc.y, j),
                       plz = ptz - lane_f(mcc.z, j);
           if (lane_test)
             nproc += filter_cluster<true>(s_tgt, s_box, c, plx, ply, plz, lane_f(mcc.w, j), ptx,
-                                          pty, ptz, valid, W, L);
+                                          pty, ptz, vmask, W, L);
           else
             nproc += filter_cluster<false>(s_tgt, s_box, c, plx, ply, plz, lane_f(mcc.w, j), ptx,
-                                           pty, ptz, valid, W, L);
+                                           pty, ptz, vmask, W, L);
         }
         if (cn < 0) break;
         j = jn;
