@@ -305,9 +305,11 @@ def batch_bench(args, B, pairs):
                            "pairs_rotated_over_10deg_from_truth": int(far.sum()),
                            "mean_excluding_those": float(rm[~far].mean()) if (~far).any() else None,
                            "far_pairs": far_pairs,
-                           "note": "the bumpy sphere is symmetric under a 90 deg turn about z; a pair "
-                                   "started far from the truth can settle in a turned basin (error "
-                                   "rotation near 90 deg about z), another local minimum of the energy"},
+                           "note": "pairs start up to 45 deg from the truth; some settle in another "
+                                   "local minimum of their energy: the bumpy sphere is symmetric under a "
+                                   "90 deg turn about z (error rotation near 90 deg about z), and "
+                                   "point-to-plane trajectories can wander into other minima; the oracle "
+                                   "lands in such minima too (tests replay these trajectories step by step)"},
         "roofline": nn_roofline(prof, float(sum(r["nn_pairs"] for r in res_prof)), "batch-256",
                                 "one profiled batch of the same 256 pairs; kernels timed per batch pass"),
         "tuning": tuning,

@@ -173,7 +173,10 @@ icp_status icp_eval(icp_ctx *ctx, const float *P, int64_t M, const float *Q, con
  * [20..35] the un-accelerated update computed from this evaluation: T' of
  * eq. WelschAlignment (point-to-point; T itself when every weight is zero)
  * or the Gauss-Newton parameters xi* of eq. GNMapping in [20..25]
- * (point-to-plane). *trace_len receives the number of rows written (passes
+ * (point-to-plane), followed there by the parameters xi of the evaluation
+ * itself in [26..31] (exp xi is the transform in [4..19]; the iterate of
+ * Algorithm 2 lives in R^6 and may rotate by more than pi, where log T is
+ * another point of R^6) and zeros. *trace_len receives the number of rows written (passes
  * beyond the capacity are not recorded). For convergence plots (energy
  * against iteration, Sec. 4.2) and for replaying a registration step by step. */
 #define ICP_TRACE_ROW 36

@@ -83,6 +83,9 @@ def lib():
         L.orc_eval.argtypes = [f32p, C.c_int64, f32p, C.c_void_p, C.c_int64, C.c_int, f64p,
                                C.c_double, C.POINTER(C.c_double), f64p, C.POINTER(C.c_uint)]
         L.orc_eval.restype = C.c_int
+        L.orc_eval_xi.argtypes = [f32p, C.c_int64, f32p, C.c_void_p, C.c_int64, C.c_int, f64p,
+                                  C.c_double, C.POINTER(C.c_double), f64p, C.POINTER(C.c_uint)]
+        L.orc_eval_xi.restype = C.c_int
         L.orc_nu_min_auto.argtypes = [f32p, C.c_void_p, C.c_int64, C.c_int, C.POINTER(C.c_double),
                                       C.c_void_p]
         L.orc_nu_min_auto.restype = C.c_int
@@ -221,6 +224,22 @@ def eval_map(P, Q, Qn, mode, T, nu=0.0):
     if rc != 0:
         raise ValueError("oracle: invalid eval arguments")
     return E.value, Tn.reshape(4, 4), fl.value
+
+
+def eval_map_xi(P, Q, Qn, mode, xi, nu=0.0):
+    """Algorithm 2's map at the parameters xi (point-to-plane modes):
+    (energy at exp(xi), Gauss-Newton candidate xi* linearised at xi, flags)."""
+    P = _f32(P).reshape(-1, 3)
+    Q = _f32(Q).reshape(-1, 3)
+    Qn = _f32(Qn).reshape(-1, 3)
+    E = C.c_double(0.0)
+    xo = np.zeros(6)
+    fl = C.c_uint(0)
+    rc = lib().orc_eval_xi(P, P.shape[0], Q, Qn.ctypes.data, Q.shape[0], mode, _f64(xi).reshape(6),
+                           float(nu), C.byref(E), xo, C.byref(fl))
+    if rc != 0:
+        raise ValueError("oracle: invalid eval arguments")
+    return E.value, xo, fl.value
 
 
 def default_params(mode):

@@ -1167,21 +1167,32 @@ static void register_p2pl(orc_ctx *c, const orc_params *prm, double nu0, orc_res
   res->nu_final = L2 ? 0.0 : nu;
 }
 
-/* One un-accelerated map application at T (see the header). */
-int orc_eval(const float *P, int64_t M, const float *Q, const float *Qn, int64_t N, int mode,
-             const double T[16], double nu, double *E, double Tout[16], unsigned *flags) {
+/* Scratch of one map application; freed by eval_ctx_free. */
+static int eval_ctx_init(orc_ctx *c, const float *P, int64_t M, const float *Q, const float *Qn,
+                         int64_t N, int mode, double nu) {
   if (!P || !Q || M <= 0 || N <= 0 || mode < 0 || mode > 3) return -1;
   if (mode_plane(mode) && !Qn) return -1;
   if (!mode_l2(mode) && !(nu > 0)) return -1;
+  memset(c, 0, sizeof *c);
+  c->P = P; c->Q = Q; c->Qn = Qn; c->M = M; c->N = N; c->mode = mode;
+  c->Pt = (float *)malloc(sizeof(float) * 3 * (size_t)M);
+  c->idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)M);
+  c->d2f = (float *)malloc(sizeof(float) * (size_t)M);
+  c->Qh = (float *)malloc(sizeof(float) * 3 * (size_t)M);
+  c->res = (double *)malloc(sizeof(double) * (size_t)M);
+  c->w = (double *)malloc(sizeof(double) * (size_t)M);
+  return 0;
+}
+
+static void eval_ctx_free(orc_ctx *c) {
+  free(c->Pt); free(c->idx); free(c->d2f); free(c->Qh); free(c->res); free(c->w);
+}
+
+/* One un-accelerated map application at T (see the header). */
+int orc_eval(const float *P, int64_t M, const float *Q, const float *Qn, int64_t N, int mode,
+             const double T[16], double nu, double *E, double Tout[16], unsigned *flags) {
   orc_ctx c;
-  memset(&c, 0, sizeof c);
-  c.P = P; c.Q = Q; c.Qn = Qn; c.M = M; c.N = N; c.mode = mode;
-  c.Pt = (float *)malloc(sizeof(float) * 3 * (size_t)M);
-  c.idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)M);
-  c.d2f = (float *)malloc(sizeof(float) * (size_t)M);
-  c.Qh = (float *)malloc(sizeof(float) * 3 * (size_t)M);
-  c.res = (double *)malloc(sizeof(double) * (size_t)M);
-  c.w = (double *)malloc(sizeof(double) * (size_t)M);
+  if (eval_ctx_init(&c, P, M, Q, Qn, N, mode, nu)) return -1;
   orc_evalres ev;
   if (mode_plane(mode)) {
     double xi[6];
@@ -1195,7 +1206,21 @@ int orc_eval(const float *P, int64_t M, const float *Q, const float *Qn, int64_t
   }
   *E = ev.E;
   *flags = ev.flags;
-  free(c.Pt); free(c.idx); free(c.d2f); free(c.Qh); free(c.res); free(c.w);
+  eval_ctx_free(&c);
+  return 0;
+}
+
+/* Algorithm 2's map at the parameters themselves (see the header). */
+int orc_eval_xi(const float *P, int64_t M, const float *Q, const float *Qn, int64_t N, int mode,
+                const double xi[6], double nu, double *E, double xi_out[6], unsigned *flags) {
+  if (!mode_plane(mode)) return -1;
+  orc_ctx c;
+  if (eval_ctx_init(&c, P, M, Q, Qn, N, mode, nu)) return -1;
+  orc_evalres ev = eval_p2pl(&c, xi, nu);
+  memcpy(xi_out, ev.prop, sizeof(double) * 6);
+  *E = ev.E;
+  *flags = ev.flags;
+  eval_ctx_free(&c);
   return 0;
 }
 

@@ -138,6 +138,14 @@ int orc_register(const float *P, int64_t M, const float *Q, const float *Qn,
 int orc_eval(const float *P, int64_t M, const float *Q, const float *Qn, int64_t N, int mode,
              const double T[16], double nu, double *E, double Tout[16], unsigned *flags);
 
+/* Algorithm 2's map evaluated at the parameters xi themselves (point-to-plane
+ * modes only): the energy at exp(xi) and the Gauss-Newton candidate xi* of
+ * eq. GNMapping, linearised at xi. The iterate of Algorithm 2 lives in R^6
+ * and may rotate by more than pi, where log(exp(xi)) is another point of R^6
+ * with another linearisation; orc_eval goes through log T. Returns 0 / -1. */
+int orc_eval_xi(const float *P, int64_t M, const float *Q, const float *Qn, int64_t N, int mode,
+                const double xi[6], double nu, double *E, double xi_out[6], unsigned *flags);
+
 void orc_params_default(int mode, orc_params *out);
 
 /* The comparison methods of Sec. 6 with the termination the paper gives them

@@ -821,7 +821,8 @@ __device__ void step_p2pl(SlotState& S, const double* mom, double* trace_prop) {
   const unsigned pf = gn_p2pl(mom, xeval, xprop);
   if (trace_prop) {
     cpy(trace_prop, xprop, 6);
-    for (int i = 6; i < 16; ++i) trace_prop[i] = 0.0;
+    cpy(trace_prop + 6, xeval, 6);
+    for (int i = 12; i < 16; ++i) trace_prop[i] = 0.0;
   }
   int sm = S.sm;
   if (sm == SM_INIT) {

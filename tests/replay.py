@@ -27,7 +27,9 @@ near-tie of the compared quantities, and counted.
 Rows may also carry the recorder's un-accelerated update (columns 20..35:
 T' for point-to-point, xi* in 20..25 for point-to-plane). It is then checked
 against the oracle's update at the same transform, and the replay mixes the
-recorded updates.
+recorded updates. Point-to-plane rows also carry the evaluated parameters xi
+(26..31): Algorithm 2 iterates in R^6, where an iterate may rotate by more than
+pi and log T is then a different point; the oracle's map is applied at xi.
 
 Anderson extrapolation is ill-conditioned when its columns are nearly
 parallel: the least-squares coefficients then move far for last-bit changes
@@ -98,17 +100,21 @@ class Replay:
     def mode_l2(self):
         return self.mode in (oracle.P2P_L2, oracle.P2PL_L2)
 
-    def _eval(self, row, T, nu):
+    def _eval(self, row, T, nu, xi=None):
         """Oracle map at T: (E, update, flags); the update is T' (4 x 4) for
-        point-to-point, xi* (6) for point-to-plane, the recorder's own when the
+        point-to-point, xi* (6) for point-to-plane (linearised at the
+        parameters xi when given, else at log T), the recorder's own when the
         row carries it (after checking it against the oracle's)."""
-        E, Tn, fl = oracle.eval_map(self.P, self.Q, self.Qn, self.mode, T, nu)
+        plane = self.mode in (oracle.P2PL_WELSCH, oracle.P2PL_L2)
+        if plane and xi is not None:
+            E, upd, fl = oracle.eval_map_xi(self.P, self.Q, self.Qn, self.mode, xi, nu)
+        else:
+            E, Tn, fl = oracle.eval_map(self.P, self.Q, self.Qn, self.mode, T, nu)
+            upd = oracle.se3_log(Tn) if plane else Tn
         d = abs(E - row[0]) / max(1.0, abs(E))
         self.max_e = max(self.max_e, d)
         if d > self.e_rtol:
             raise ReplayError(f"row {self.i - 1}: energy {row[0]!r} vs oracle {E!r}")
-        plane = self.mode in (oracle.P2PL_WELSCH, oracle.P2PL_L2)
-        upd = oracle.se3_log(Tn) if plane else Tn
         if len(row) >= 36:
             rec = row[20:26].copy() if plane else row[20:36].reshape(4, 4).copy()
             du = float(np.abs(rec - upd).max())
@@ -243,8 +249,9 @@ class Replay:
 
         def ev(xi_pred, sm, what, tol=None):
             row, T = self._next(None if xi_pred is None else oracle.se3_exp(xi_pred), nu, sm, what, tol)
-            E, xs, fl = self._eval(row, T, nu)
-            return oracle.se3_log(T), E, xs, fl
+            xi = self._row_xi(row, T, xi_pred, tol)
+            E, xs, fl = self._eval(row, T, nu, xi)
+            return xi, E, xs, fl
 
         while True:
             Inu = self._cap(stage)
@@ -306,6 +313,23 @@ class Replay:
             k += 1
             stage += 1
             xkm1 = xk
+
+    def _row_xi(self, row, T, xi_pred, tol):
+        """The parameters of a point-to-plane evaluation: the recorded ones
+        (columns 26..31) when the row carries them, checked to give the
+        recorded transform and to lie on the replay's branch (an iterate that
+        has rotated by more than pi is not log T), else log T."""
+        if len(row) < 36:
+            return oracle.se3_log(T)
+        xi = row[26:32].copy()
+        de = float(np.abs(oracle.se3_exp(xi) - T).max())
+        if de > 1e-12:
+            raise ReplayError(f"row {self.i - 1}: exp of the recorded parameters is {de:.3e} off its transform")
+        if xi_pred is not None:
+            dx = float(np.abs(xi - xi_pred).max())
+            if dx > max(1e-6, 10.0 * (tol or 0.0)):
+                raise ReplayError(f"row {self.i - 1}: parameters differ from the replay's by {dx:.3e}")
+        return xi
 
     def summary(self):
         return (f"{self.checked} evaluations replayed, {self.decisions} decisions ({self.ties} near-ties), "

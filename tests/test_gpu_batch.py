@@ -202,3 +202,48 @@ def test_wait_all_returns_after_every_result():
                 assert rc == B.ICP_OK, B.icp_status_str(rc)
     finally:
         B.icp_destroy(h)
+
+
+def test_batch_accuracy_distribution(ctx):
+    """The uneven batch's per-pair accuracy: the first 48 pairs of the batch
+    workload registered together; most land within 1e-2 of the bbox diagonal
+    of the ground truth (the rest in other local minima of their energy, see
+    the next test), the median within 2e-3."""
+    pairs = synth.batch_pairs(count=48)
+    reqs = []
+    for d in pairs:
+        if d["mode"] == 2:
+            prm = B.icp_params_default(B.ICP_P2PL_WELSCH, anderson_m=6, nu_min=d["nu_min"])
+            reqs.append((d["P"], d["Q"], d["Qn"], prm))
+        else:
+            reqs.append((d["P"], d["Q"], None, B.icp_params_default(B.ICP_P2P_WELSCH, nu_min=d["nu_min"])))
+    announce("batch accuracy distribution (48 pairs of the batch workload)")
+    res = _wait(ctx, B.icp_batch_submit(ctx, reqs), timeout=300.0)
+    rm = np.array([metrics.rmse(d["T_gt"], r["T"], d["P"]) / d["diag"] for d, r in zip(pairs, res)])
+    print("rmse/diag: median %.2e p90 %.2e max %.2e, %d of %d below 1e-2" %
+          (np.median(rm), np.percentile(rm, 90), rm.max(), (rm < 1e-2).sum(), len(rm)), flush=True)
+    assert np.median(rm) < 2e-3
+    assert (rm < 1e-2).mean() >= 0.85
+
+
+def test_batch_far_pair_is_the_algorithms_trajectory(ctx):
+    """Pair 176 of the batch workload (point-to-plane, 3128 x 11129) ends about
+    118 deg from the ground truth, and so does the oracle's registration of it:
+    a local minimum of the energy, not a fault. Its whole trajectory replays
+    through the oracle's map (Algorithm 2, Sec. 5), and the batched result
+    equals the pair registered alone."""
+    import replay
+    d = synth.batch_pair(176)
+    prm = B.icp_params_default(B.ICP_P2PL_WELSCH, anderson_m=6, nu_min=d["nu_min"])
+    announce("replay of a far batch pair")
+    g = B.icp_register_trace(ctx, d["P"], d["Q"], d["Qn"], prm, cap=20000)
+    rows = g["trace"][1:]  # the first row only feeds the median (nu_max rule)
+    rp = replay.Replay(d["P"], d["Q"], d["Qn"], oracle.P2PL_WELSCH, rows, m=6, eps=prm.eps,
+                       nu_min=prm.nu_min, iter_first=prm.iter_first, iter_inc=prm.iter_inc,
+                       iter_cap=prm.iter_cap, lmax=prm.max_line_search)
+    rp.run_alg2(rows[0, 1])
+    print(rp.summary(), flush=True)
+    assert rp.checked == len(rows) and rp.ties <= max(3, rp.decisions // 100)
+    assert np.degrees(metrics.rotation_error_rad(d["T_gt"], g["T"])) > 60.0
+    b = _wait(ctx, B.icp_batch_submit(ctx, [(d["P"], d["Q"], d["Qn"], prm)]))[0]
+    assert np.array_equal(b["T"], g["T"])

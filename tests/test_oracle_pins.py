@@ -613,6 +613,53 @@ def test_welsch_point_to_plane_step_is_weighted_least_squares(seed):
     assert np.abs(Tn - _expm_twist(xi - step)).max() < 1e-8
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gauss_newton_at_parameters_past_pi(seed):
+    """Algorithm 2 iterates on xi in R^6 (eq. GNMapping linearises
+    xi -> exp(xi) p at xi itself). At a rotation angle above pi, log(exp(xi))
+    is another point of R^6 (angle 2 pi - theta about the opposite axis) with
+    another Jacobian: the map evaluated at the parameters must be the
+    weighted least-squares step at xi (central differences through scipy
+    expm, numpy lstsq), while its energy equals the one at the transform."""
+    rng = np.random.default_rng(40 + seed)
+    Q = rng.normal(size=(400, 3)).astype(np.float32)
+    Qn = rng.normal(size=(400, 3))
+    Qn = (Qn / np.linalg.norm(Qn, axis=1, keepdims=True)).astype(np.float32)
+    P = (rng.normal(size=(150, 3)) * 0.9).astype(np.float32)
+    axis = rng.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    xi = np.r_[(math.pi + 0.5) * axis, rng.normal(scale=0.1, size=3)]
+    T = _expm_twist(xi)
+    xl = oracle.se3_log(T)
+    assert np.linalg.norm(xl[:3]) < math.pi and np.abs(_expm_twist(xl) - T).max() < 1e-12
+    Pt = (P.astype(np.float64) @ T[:3, :3].T + T[:3, 3]).astype(np.float32).astype(np.float64)
+    d2 = ((Pt[:, None, :] - Q[None, :, :].astype(np.float64)) ** 2).sum(-1)
+    j = d2.argmin(1)
+    q, n, p = Q[j].astype(np.float64), Qn[j].astype(np.float64), P.astype(np.float64)
+
+    def B(x):
+        Tx = _expm_twist(x)
+        return ((p @ Tx[:3, :3].T + Tx[:3, 3] - q) * n).sum(1)
+
+    b0 = B(xi)
+    nu = float(np.median(np.abs(b0)))
+    g = np.exp(-b0 ** 2 / (2 * nu * nu))
+    E, xs, fl = oracle.eval_map_xi(P, Q, Qn, oracle.P2PL_WELSCH, xi, nu)
+    assert fl == 0
+    assert abs(E - (1.0 - g).sum()) <= 1e-12 * E
+    h = 1e-6
+    J = np.stack([(B(xi + h * e) - B(xi - h * e)) / (2 * h) for e in np.eye(6)], 1)
+    w = np.sqrt(g)
+    step = np.linalg.lstsq(J * w[:, None], b0 * w, rcond=None)[0]
+    assert np.abs(xs - (xi - step)).max() < 1e-7
+    # through log T: the same energy, a step linearised elsewhere
+    E2, Tn2, _ = oracle.eval_map(P, Q, Qn, oracle.P2PL_WELSCH, T, nu)
+    assert abs(E2 - E) <= 1e-12 * E
+    E3, xs3, _ = oracle.eval_map_xi(P, Q, Qn, oracle.P2PL_WELSCH, xl, nu)
+    assert E3 == E2 and np.abs(_expm_twist(xs3) - Tn2).max() < 1e-12
+    assert np.abs(xs3 - xs).max() > 1.0
+
+
 def test_welsch_large_nu_reduces_to_l2():
     """nu -> infinity makes every Welsch weight 1: the robust alignment equals
     the L2 alignment (textbook special case)."""
