@@ -244,6 +244,26 @@ __device__ __forceinline__ int queue_item(int* q, int round) {
   return (int)gridDim.x + x + kQueues * atomicAdd(&q[x * kQueueStride], 1);
 }
 
+// Slice queue of the closest-point search. Items are queued tile by tile and
+// tiles follow the Hilbert order of the sources, so consecutive items need
+// nearby clusters. Sub-queue x (the workgroups on die x, blockIdx mod
+// kQueues == x) serves runs of kSliceRun consecutive items, runs x, x +
+// kQueues, x + 2 kQueues, ...: each die's L2 then sees a run's clusters
+// several times instead of every die fetching them for interleaved single
+// items, while the fine interleave of runs keeps the dies' shares of work
+// equal. Workgroup b takes position b / kQueues of its sub-queue without an
+// atomic, later positions come from counter x; positions map to items in
+// increasing order, so a sub-queue is used up at its first item >= total.
+constexpr int kSliceRun = 16;
+
+__device__ __forceinline__ int slice_queue_item(int* q, int total, int round) {
+  const int x = (int)(blockIdx.x % kQueues);
+  const int nb = ((int)gridDim.x - x + kQueues - 1) / kQueues;  // workgroups of die x
+  const int k = round == 0 ? (int)(blockIdx.x / kQueues) : nb + atomicAdd(&q[x * kQueueStride], 1);
+  const long long item = ((long long)(k / kSliceRun) * kQueues + x) * kSliceRun + (k % kSliceRun);
+  return item < total ? (int)item : total;
+}
+
 constexpr int kMaxSlots = 1024;
 // trace row: [E, nu, solver position, reuse, T_eval (16), proposal (16)]
 constexpr int kTraceRow = 36;

@@ -545,7 +545,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
       wl->s_from_scount ? ldg(descs[wl->slot[0]].scount, 0) : wl->s_total);
   for (int round = 0;; ++round) {
     int g = 0;
-    if (lane == 0) g = queue_item(wl->q_s, round);
+    if (lane == 0) g = slice_queue_item(wl->q_s, s_total, round);
     g = __builtin_amdgcn_readfirstlane(__shfl(g, 0, 64));
     if (g >= s_total) break;
     const int a = __builtin_amdgcn_readfirstlane(find_slot(wl->s_base, wl->n_active, g));
@@ -975,6 +975,8 @@ void launch_brute(const SlotDesc* descs, const SlotState* states, int grid, hipS
 
 void launch_nn(const SlotDesc* descs, const SlotState* states, WorkList* wl, int grid,
                bool single, hipStream_t st) {
+  // every sub-queue needs workgroups of its own (blockIdx mod kQueues)
+  grid = std::max(grid, kQueues * kCullWaves);
   hipLaunchKernelGGL(nn_cull_kernel, dim3(grid / kCullWaves), dim3(64 * kCullWaves), 0, st, descs,
                      states, wl);
   if (!single) hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl);

@@ -78,7 +78,7 @@ __device__ inline Coef coeffs(double t) {
 }
 
 // exp of the twist xi = (delta, u): R = I + A W + B W^2, t = (I + B W + C W^2) u.
-__device__ void twist_exp(const double xi[6], double T[16]) {
+__device__ __forceinline__ void twist_exp(const double xi[6], double T[16]) {
   const double th = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
   const Coef k = coeffs(th);
   double W[9], W2[9];
@@ -99,7 +99,7 @@ __device__ void twist_exp(const double xi[6], double T[16]) {
 
 // Principal logarithm (angle in [0, pi], Appendix A): the rotation vector from
 // the skew part (or, near pi, from the symmetric part), u = V^{-1} t.
-__device__ void twist_log(const double T[16], double xi[6]) {
+__device__ __forceinline__ void twist_log(const double T[16], double xi[6]) {
   const double R[9] = {T[0], T[1], T[2], T[4], T[5], T[6], T[8], T[9], T[10]};
   const double v[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};
   const double sn = 0.5 * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
@@ -120,17 +120,23 @@ __device__ void twist_log(const double T[16], double xi[6]) {
   } else {
     const double oc = 1.0 - cs;
     double S[9];
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
       for (int j = 0; j < 3; ++j)
         S[3 * i + j] = (0.5 * (R[3 * i + j] + R[3 * j + i]) - (i == j ? cs : 0.0)) / oc;
-    int kk = 0;
-    if (S[4] > S[0]) kk = 1;
-    if (S[8] > S[4 * kk]) kk = 2;
-    double a[3] = {S[3 * kk], S[3 * kk + 1], S[3 * kk + 2]};
+    // row kk of the largest diagonal entry (first on ties), gathered by
+    // selects so that S stays in registers
+    const bool k1 = S[4] > S[0];
+    const bool k2 = S[8] > (k1 ? S[4] : S[0]);
+    double a[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) a[j] = k2 ? S[6 + j] : (k1 ? S[3 + j] : S[j]);
     const double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
     a[0] /= na; a[1] /= na; a[2] /= na;
+    const double akk = k2 ? a[2] : (k1 ? a[1] : a[0]);
     const double sg = a[0] * v[0] + a[1] * v[1] + a[2] * v[2];
-    if (sg < 0.0 || (sg == 0.0 && a[kk] < 0.0)) { a[0] = -a[0]; a[1] = -a[1]; a[2] = -a[2]; }
+    if (sg < 0.0 || (sg == 0.0 && akk < 0.0)) { a[0] = -a[0]; a[1] = -a[1]; a[2] = -a[2]; }
     d[0] = th * a[0]; d[1] = th * a[1]; d[2] = th * a[2];
   }
   double g;
@@ -158,7 +164,7 @@ __device__ void twist_log(const double T[16], double xi[6]) {
 // K[0..26]  dR/d delta_j = A E_j + B (E_j W + W E_j) + Ad d_j W + Bd d_j W^2
 // K[27..35] dt/d delta (column j) = [B E_j + C (E_j W + W E_j) + Bd d_j W + Cd d_j W^2] u
 // K[36..44] dt/du = I + B W + C W^2
-__device__ void twist_derivs(const double xi[6], double K[45]) {
+__device__ __forceinline__ void twist_derivs(const double xi[6], double K[45]) {
   const double* d = xi;
   const double* u = xi + 3;
   const double th = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -399,13 +405,24 @@ __device__ void sym4_top(double A[16], double V[16], double q[4], double& l0, do
 #pragma unroll
       for (int r = p + 1; r < 4; ++r) jacobi_rot(A, V, p, r);
   }
+  // largest and second largest diagonal entries (first index on ties), by
+  // selects so that A and V stay in registers
   int b0 = 0;
-  for (int i = 1; i < 4; ++i) if (A[5 * i] > A[5 * b0]) b0 = i;
-  int b1 = b0 == 0 ? 1 : 0;
-  for (int i = 0; i < 4; ++i) if (i != b0 && A[5 * i] > A[5 * b1]) b1 = i;
-  l0 = A[5 * b0];
-  l1 = A[5 * b1];
-  for (int i = 0; i < 4; ++i) q[i] = V[4 * i + b0];
+  double v0 = A[0];
+#pragma unroll
+  for (int i = 1; i < 4; ++i) {
+    const bool g = A[5 * i] > v0;
+    v0 = g ? A[5 * i] : v0;
+    b0 = g ? i : b0;
+  }
+  double v1 = b0 == 0 ? A[5] : A[0];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v1 = (i != b0 && A[5 * i] > v1) ? A[5 * i] : v1;
+  l0 = v0;
+  l1 = v1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    q[i] = b0 == 0 ? V[4 * i] : b0 == 1 ? V[4 * i + 1] : b0 == 2 ? V[4 * i + 2] : V[4 * i + 3];
 #pragma unroll
   for (int i = 0; i < 4; ++i) V[4 * i] = q[i];
 }
@@ -457,37 +474,56 @@ __device__ unsigned align_p2p(const double* mom, const double cP[3], const doubl
 __device__ unsigned gn_p2pl(const double* mom, const double xi[6], double out[6]) {
   for (int a = 0; a < 6; ++a) out[a] = xi[a];
   if (!(mom[1] > 1e-300)) return F_ZERO_WEIGHT;
+  // every loop is unrolled, so that the small matrices stay in registers
   double A[36];
-  int t = 2;
+#pragma unroll
   for (int a = 0; a < 6; ++a)
-    for (int b = a; b < 6; ++b) { A[6 * a + b] = mom[t]; A[6 * b + a] = mom[t]; ++t; }
+#pragma unroll
+    for (int b = a; b < 6; ++b) {
+      const int t = 2 + 6 * a - a * (a - 1) / 2 + (b - a);  // upper triangle, row-major
+      A[6 * a + b] = mom[t];
+      A[6 * b + a] = mom[t];
+    }
   double dmax = 0.0;
+#pragma unroll
   for (int a = 0; a < 6; ++a) dmax = fmax(dmax, A[7 * a]);
   if (!(dmax > 0.0)) return F_DEGENERATE;
   double L[36];
+#pragma unroll
   for (int i = 0; i < 36; ++i) L[i] = 0.0;
+  bool deg = false;
+#pragma unroll
   for (int j = 0; j < 6; ++j) {
     double s = A[7 * j];
+#pragma unroll
     for (int k = 0; k < j; ++k) s -= L[6 * j + k] * L[6 * j + k];
-    if (!(s > 1e-14 * dmax)) return F_DEGENERATE;
-    L[7 * j] = sqrt(s);
+    if (!(s > 1e-14 * dmax)) deg = true;
+    L[7 * j] = deg ? 1.0 : sqrt(s);
+#pragma unroll
     for (int i = j + 1; i < 6; ++i) {
       double v = A[6 * i + j];
+#pragma unroll
       for (int k = 0; k < j; ++k) v -= L[6 * i + k] * L[6 * j + k];
       L[6 * i + j] = v / L[7 * j];
     }
   }
+  if (deg) return F_DEGENERATE;
   double y[6], x[6];
+#pragma unroll
   for (int i = 0; i < 6; ++i) {
     double v = mom[23 + i];
+#pragma unroll
     for (int k = 0; k < i; ++k) v -= L[6 * i + k] * y[k];
     y[i] = v / L[7 * i];
   }
+#pragma unroll
   for (int i = 5; i >= 0; --i) {
     double v = y[i];
+#pragma unroll
     for (int k = i + 1; k < 6; ++k) v -= L[6 * k + i] * x[k];
     x[i] = v / L[7 * i];
   }
+#pragma unroll
   for (int a = 0; a < 6; ++a) out[a] = xi[a] - x[a];
   return 0;
 }
@@ -628,7 +664,7 @@ __device__ void plan_lists(SlotState& S) {
     for (int i = 0; i < 16; ++i) S.Tref[i] = S.Teval[i];
 }
 
-__device__ void request_T(SlotState& S, const double T[16], double nu) {
+__device__ __forceinline__ void request_T(SlotState& S, const double T[16], double nu) {
   S.evaluations++;
   const bool same = S.have_last && same_bits(S.last_key, T, 16);
   S.reuse = same ? 1 : 0;
@@ -642,7 +678,7 @@ __device__ void request_T(SlotState& S, const double T[16], double nu) {
   set_nu(S, nu);
 }
 
-__device__ void request_xi(SlotState& S, const double xi[6], double nu) {
+__device__ __forceinline__ void request_xi(SlotState& S, const double xi[6], double nu) {
   S.evaluations++;
   const bool same = S.have_last && same_bits(S.last_key, xi, 6);
   S.reuse = same ? 1 : 0;

@@ -28,6 +28,15 @@ def fresh():
     B.icp_destroy(h)
 
 
+@pytest.fixture
+def empty(monkeypatch, tmp_path):
+    """A context whose tuning table starts empty (no cache file to load)."""
+    monkeypatch.setenv("ICP_TUNING_CACHE", str(tmp_path / "absent.json"))
+    h = B.icp_create(0, 4 << 30)
+    yield h
+    B.icp_destroy(h)
+
+
 def _set_all(ctx, M, N, mode, method, t):
     for fam in (B.ICP_P2P_WELSCH, B.ICP_P2PL_WELSCH):
         for batch in (0, 1):
@@ -82,7 +91,9 @@ def test_batch_exhaustive_items_do_not_change_results(fresh):
             assert rc == B.ICP_OK and np.array_equal(g["T"], a["T"]), cpi
 
 
-def test_lookup_rules_and_validation(fresh):
+def test_lookup_rules_and_validation(empty):
+    fresh = empty
+    assert B.icp_tuning_entries(fresh) == []
     d0 = B.icp_tuning_default()
     t, f = B.icp_tuning_lookup(fresh, 100_000, 100_000, B.ICP_P2P_WELSCH, B.ICP_NN_CLUSTER)
     assert f in (0, 1, 2)
@@ -106,7 +117,8 @@ def test_lookup_rules_and_validation(fresh):
                                                    (20_000, 20_000, B.ICP_P2P_WELSCH, B.ICP_NN_CLUSTER, 1),
                                                    (2048, 3000, B.ICP_P2PL_WELSCH, B.ICP_NN_BRUTE, 0),
                                                    (2048, 3000, B.ICP_P2PL_WELSCH, B.ICP_NN_BRUTE, 1)])
-def test_autotune_stores_a_winner(fresh, M, N, mode, method, batch):
+def test_autotune_stores_a_winner(empty, M, N, mode, method, batch):
+    fresh = empty
     announce(f"autotune M={M} N={N} mode={mode} method={method} batch={batch}")
     e = B.icp_autotune(fresh, M, N, mode, method, batch)
     assert e.m_bucket == _bucket(M) and e.n_bucket == _bucket(N) and e.method == method and e.ms > 0
