@@ -253,14 +253,16 @@ def batch_bench(args, B, pairs):
     # plain loop: the same pairs one at a time, host-synchronised passes
     lat_p, res_p = [], []
     t0 = time.perf_counter()
-    for P, Q, Qn, prm in reqs:
+    for P, Q, Qn, prm in ([] if args.no_plain else reqs):
         prm.engine = B.ICP_ENGINE_PLAIN
         t = time.perf_counter()
         res_p.append(B.icp_register(ctx, P, Q, Qn, prm))
         lat_p.append((time.perf_counter() - t) * 1e3)
         prm.engine = B.ICP_ENGINE_GRAPH
     wall_p = time.perf_counter() - t0
-    log(f"plain loop: {count} registrations in {wall_p:.2f} s")
+    if args.no_plain:
+        res_p, lat_p, wall_p = res0, [float("nan")], float("nan")
+    log(f"plain loop: {len(res_p)} registrations in {wall_p:.2f} s")
     B.icp_destroy(ctx)
     rm = np.array([metrics.rmse(d["T_gt"], r["T"], d["P"]) / d["diag"] for d, r in zip(pairs, res0)])
     rm_p = np.array([metrics.rmse(d["T_gt"], r["T"], d["P"]) / d["diag"] for d, r in zip(pairs, res_p)])
@@ -294,11 +296,12 @@ def batch_bench(args, B, pairs):
         "nn_queries_per_s": queries * args.steps / wall,
         "nn_passes_per_registration": float(passes.mean()),
         "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
-        "plain_loop": {"value": count / wall_p, "unit": "registrations/s", "p50_ms": _pct(lat_p, 50),
-                       "p99_ms": _pct(lat_p, 99), "nn_queries_per_s": queries / wall_p},
-        "speedup_vs_plain": value / (count / wall_p),
-        "equal_rmse": bool(np.array_equal(rm, rm_p)),
-        "bit_identical_to_plain": f"{same}/{count}",
+        "plain_loop": None if args.no_plain else {
+            "value": count / wall_p, "unit": "registrations/s", "p50_ms": _pct(lat_p, 50),
+            "p99_ms": _pct(lat_p, 99), "nn_queries_per_s": queries / wall_p},
+        "speedup_vs_plain": None if args.no_plain else value / (count / wall_p),
+        "equal_rmse": None if args.no_plain else bool(np.array_equal(rm, rm_p)),
+        "bit_identical_to_plain": None if args.no_plain else f"{same}/{count}",
         "rmse_over_diag": {"mean": float(rm.mean()), "median": float(np.median(rm)),
                            "p90": _pct(rm, 90), "max": float(rm.max()),
                            "pairs_below_1e-3": int((rm < 1e-3).sum()),
@@ -575,7 +578,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batch-256",
-                    choices=["batch-256", "robust-p2p-100k", "fast-icp-4096", "robust-p2pl-500k"])
+                    choices=["batch-256", "robust-p2p-100k", "fast-icp-4096", "robust-p2pl-500k",
+                             "nn-brute"])
     ap.add_argument("--batch-pairs", type=int, default=256)
     ap.add_argument("--passes-per-replay", type=int, default=4)
     ap.add_argument("--serve-requests", type=int, default=5000)
@@ -585,6 +589,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the batch's plain-loop comparator (counter runs: every dispatch is slow)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="headline only: no 100k x 100k pair, no exhaustive-kernel runs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -603,6 +609,9 @@ def main():
         pool = [] if args.no_serve else generate(_gen_served, args.serve_pool, args.workers)
         sphere = [] if args.no_secondary else generate(_gen_sphere, 4, args.workers)
         fast = [] if args.no_secondary else generate(_gen_fast, 256, args.workers)
+    elif args.workload == "nn-brute":
+        sphere = generate(_gen_sphere, 1, args.workers)
+        fast = generate(_gen_fast, 256, args.workers)
     else:
         gen = {"robust-p2p-100k": (_gen_sphere, 8), "fast-icp-4096": (_gen_fast, 1)}
         if args.workload == "robust-p2pl-500k":
@@ -618,6 +627,20 @@ def main():
     from paper_2007_07627_amd import binding as B
     if args.copy_calibration:
         copy_calibration(torch)
+
+    if args.workload == "nn-brute":
+        # the exhaustive closest-point kernels alone (one-slot at 100k x 100k,
+        # multi-slot over 256 pairs of 4096 x 4096)
+        one = brute_roofline(B, torch, sphere[0])
+        multi = brute_batch_roofline(B, fast)
+        out = {"metric": "exhaustive closest-point pairs/s", "value": one["pairs_per_s"], "unit": "pairs/s",
+               "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": one["ms_per_launch"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+               "data": DATA, "config": {"workload": "exhaustive closest point, 100k x 100k bumpy sphere "
+                                                    "pair; then 256 Fast ICP pairs of 4096 x 4096"},
+               "nn_brute_roofline": one, "nn_brute_batch_roofline": multi}
+        print(json.dumps(out), flush=True)
+        return
 
     if args.workload != "batch-256":
         prms, cfg = single_workload(args.workload, B, single)

@@ -293,8 +293,14 @@ struct Engine {
   int cus = 256;
   int gnn_grid = 0;          // search grid the captured graph was built with
   Arena* arena = nullptr;
-  // profiling: timing events around the kernels of every pass
+  // profiling: timing events around the kernels of every pass. `prof` is
+  // read and written only by the thread that enqueues this engine's passes
+  // (the caller under the context's sync lock for the one-slot engine; the
+  // scheduler, which copies `prof_req` at the start of each round under the
+  // context lock, for the batch engine), so that a round's passes and their
+  // collection agree even when profiling is switched meanwhile.
   bool prof = false;
+  bool prof_req = false;
   std::vector<hipEvent_t> pev;  // 4 per pass
   double prof_ms[3] = {0.0, 0.0, 0.0};  // closest point, reduction, median + solver
   long long prof_passes = 0;
@@ -1009,6 +1015,7 @@ static void scheduler(icp_ctx* ctx) {
       if (ctx->stop) return;
       R = ctx->passes_per_replay;
       running = ctx->running;
+      E.prof = E.prof_req;
       if (running == 0) E.capacity = ctx->max_slots;
     }
     bool ok = true;
@@ -1071,7 +1078,11 @@ static void scheduler(icp_ctx* ctx) {
                hipSuccess &&
            hipStreamSynchronize(E.st) == hipSuccess;
     if (ok) held.clear();
-    if (ok && running > 0) E.collect_profile(R);
+    if (ok && running > 0 && E.prof) {
+      // the sums are read and reset by other threads under the context lock
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      E.collect_profile(R);
+    }
     if (!ok) {
       E.drain();
       std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1643,8 +1654,9 @@ icp_status icp_profile(icp_ctx* ctx, int enable) {
   if (!ctx) return ICP_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> g(ctx->sync_mu);
   std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->sync_eng.prof = enable != 0;
+  ctx->batch_eng.prof_req = enable != 0;  // taken up by the scheduler's next round
   for (Engine* E : {&ctx->sync_eng, &ctx->batch_eng}) {
-    E->prof = enable != 0;
     E->prof_ms[0] = E->prof_ms[1] = E->prof_ms[2] = 0.0;
     E->prof_passes = 0;
   }
