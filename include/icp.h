@@ -270,6 +270,21 @@ icp_status icp_estimate_normals(icp_ctx *ctx, const float *Q, int64_t N, float *
  * start while the later ones are being copied. */
 icp_status icp_batch_submit(icp_ctx *ctx, const icp_request *reqs, int n, uint64_t *tickets_out);
 
+/* icp_batch_submit with device-resident inputs: every request's P, Q (and Qn
+ * for point-to-plane) are DEVICE pointers (AoS x,y,z FP32 in HBM of the
+ * context's device), read in place by the request's setup; nothing is copied
+ * through the host. The arrays must stay valid and unchanged until the
+ * request's result has been handed out by icp_poll (or icp_batch_wait_all has
+ * returned). `stream` (NULL = the null stream): the setups of these requests
+ * wait for the work enqueued on it before this call, so a caller may submit
+ * arrays its own kernels are still writing. Sizes and parameters are checked
+ * as for icp_batch_submit (ICP_ERR_INVALID_ARG, ICP_ERR_NO_NORMALS; nothing is
+ * queued then); coordinates are not read on the host, so non-finite values
+ * are not detected. Results are bit-identical to the same requests submitted
+ * with host arrays. */
+icp_status icp_batch_submit_dev(icp_ctx *ctx, const icp_request *reqs, int n, uint64_t *tickets_out,
+                                void *stream);
+
 /* ICP_OK and the result (handed out exactly once), ICP_ERR_NOT_READY while
  * pending, ICP_ERR_OOM (once) for a request that can never fit the HBM budget
  * or whose host copy could not be allocated, ICP_ERR_DEVICE after a HIP

@@ -25,7 +25,7 @@ ICP_TRACE_ROW = 36
 EXPORTED = ["icp_create", "icp_destroy", "icp_params_default", "icp_params_classical", "icp_register", "icp_register_trace",
             "icp_eval", "icp_trace_items",
             "icp_register_dev",
-            "icp_nn_query", "icp_nn_query_dev", "icp_nn_query_dev_noalloc", "icp_nu_min_auto", "icp_estimate_normals", "icp_batch_submit", "icp_poll",
+            "icp_nn_query", "icp_nn_query_dev", "icp_nn_query_dev_noalloc", "icp_nu_min_auto", "icp_estimate_normals", "icp_batch_submit", "icp_batch_submit_dev", "icp_poll",
             "icp_batch_wait_all", "icp_batch_config", "icp_profile", "icp_profile_read",
             "icp_tuning_default", "icp_tuning_lookup", "icp_tuning_set", "icp_tuning_entries",
             "icp_autotune", "icp_device_arch", "icp_tuning_file_write", "icp_tuning_file_read",
@@ -103,6 +103,7 @@ def lib():
         L.icp_nn_query_dev.argtypes = [vp, vp, i64, vp, i64, vp, i32, vp, vp, vp]
         L.icp_nn_query_dev_noalloc.argtypes = [vp, i64, vp, i64, vp, i32, vp, vp, vp]
         L.icp_batch_submit.argtypes = [vp, C.POINTER(icp_request), i32, C.POINTER(C.c_uint64)]
+        L.icp_batch_submit_dev.argtypes = [vp, C.POINTER(icp_request), i32, C.POINTER(C.c_uint64), vp]
         L.icp_poll.argtypes = [vp, C.c_uint64, C.POINTER(icp_result)]
         L.icp_nu_min_auto.argtypes = [vp, vp, vp, C.c_int64, i32, C.POINTER(C.c_double)]
         L.icp_estimate_normals.argtypes = [vp, vp, C.c_int64, vp]
@@ -326,6 +327,27 @@ def icp_batch_submit(ctx, requests):
         arr[i].params = prm
     t = (C.c_uint64 * len(requests))()
     _check(lib().icp_batch_submit(ctx, arr, len(requests), t), "icp_batch_submit")
+    return list(t)
+
+
+def icp_batch_submit_dev(ctx, requests, stream=None, raw=False):
+    """requests: iterable of (P_t, Q_t, Qn_t_or_None, icp_params) with torch
+    tensors in HBM (contiguous float32, shape (n, 3)), kept alive by the
+    caller until their results are polled. Returns tickets."""
+    arr = (icp_request * len(requests))()
+    for i, (P, Q, Qn, prm) in enumerate(requests):
+        arr[i].P = P.data_ptr()
+        arr[i].M = P.shape[0]
+        arr[i].Q = Q.data_ptr()
+        arr[i].Qn = None if Qn is None else Qn.data_ptr()
+        arr[i].N = Q.shape[0]
+        arr[i].params = prm
+    t = (C.c_uint64 * len(requests))()
+    st = None if stream is None else int(stream.cuda_stream)
+    rc = lib().icp_batch_submit_dev(ctx, arr, len(requests), t, st)
+    if raw:
+        return rc, list(t)
+    _check(rc, "icp_batch_submit_dev")
     return list(t)
 
 

@@ -194,6 +194,15 @@ struct HostSlot {
 
 // ------------------------------------------------------------------ requests
 
+// An event recorded on a caller's stream, shared by the requests of one
+// submission and destroyed with the last of them.
+struct ReadyEvent {
+  hipEvent_t ev = nullptr;
+  ~ReadyEvent() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
 struct OwnedRequest {
   std::vector<float> P, Q, Qn;  // host copies (batch path)
   const float* P_dev = nullptr;  // device AoS inputs (dev path)
@@ -212,6 +221,9 @@ struct OwnedRequest {
   icp_tuning tune{kSliceMinDefault, kVerletFracDefault, kBruteClustersDefault, kBruteItemsDefault,
                   kGridPerCuDefault};    // work partition of this request (no effect on results)
   bool tune_fixed = false;         // tune set by the caller (autotuner), not looked up
+  // device inputs of a batch submission: the caller's stream position at the
+  // submission, which the setup waits for before reading the arrays
+  std::shared_ptr<struct ReadyEvent> ready;
   uint64_t ticket = 0;
   Clock::time_point t_submit;
 };
@@ -510,6 +522,7 @@ struct Engine {
     if (!r.P_dev) HIP_OK(hipMemcpyAsync(F(L.o_clist), r.P.data(), 12ull * L.M, hipMemcpyHostToDevice, up));
     HIP_OK(hipEventRecord(up_done, up));
     HIP_OK(hipStreamWaitEvent(ss, up_done, 0));
+    if (r.ready) HIP_OK(hipStreamWaitEvent(ss, r.ready->ev, 0));
     // inputs -> SoA
     launch_aos_to_soa(srcQ, L.N, F(L.o_qx), F(L.o_qy), F(L.o_qz), ss);
     if (p2pl) launch_aos_to_soa(srcN, L.N, F(L.o_nx), F(L.o_ny), F(L.o_nz), ss);
@@ -590,7 +603,8 @@ struct Engine {
     h.zero = 0;
     HIP_OK(hipMemcpyAsync(d_done + s, &h.zero, sizeof(int), hipMemcpyHostToDevice, up));
     HIP_OK(hipEventRecord(up_done, up));
-    HIP_OK(hipStreamWaitEvent(ss, up_done, 0));  // the activation on `side` covers the uploads
+    HIP_OK(hipStreamWaitEvent(ss, up_done, 0));
+    if (r.ready) HIP_OK(hipStreamWaitEvent(ss, r.ready->ev, 0));  // the activation on `side` covers the uploads
     h_done[s] = 0;
     if (sync) HIP_OK(hipStreamSynchronize(ss));
     return hipGetLastError() == hipSuccess;
@@ -1631,6 +1645,59 @@ icp_status icp_batch_submit(icp_ctx* ctx, const icp_request* reqs, int n, uint64
     }
     ctx->cv.notify_all();
   });
+  return ICP_OK;
+}
+
+icp_status icp_batch_submit_dev(icp_ctx* ctx, const icp_request* reqs, int n, uint64_t* tickets_out,
+                                void* stream) {
+  if (!ctx || n < 0 || (n > 0 && (!reqs || !tickets_out))) return ICP_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    const icp_request& q = reqs[i];
+    if (!q.P || !q.Q) return ICP_ERR_INVALID_ARG;
+    icp_status st = check_sizes(q.M, q.N);
+    if (st == ICP_OK) st = check_params_sized(&q.params, q.N);
+    if (st == ICP_OK && mode_plane(q.params.mode) && !q.Qn) st = ICP_ERR_NO_NORMALS;
+    if (st != ICP_OK) return st;
+  }
+  if (n == 0) return ICP_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ICP_ERR_DEVICE;
+  auto ready = std::make_shared<ReadyEvent>();
+  if (hipEventCreateWithFlags(&ready->ev, hipEventDisableTiming) != hipSuccess) {
+    ready->ev = nullptr;
+    return ICP_ERR_DEVICE;
+  }
+  if (hipEventRecord(ready->ev, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return ICP_ERR_DEVICE;
+  const auto now = Clock::now();
+  std::vector<std::unique_ptr<OwnedRequest>> rs(n);
+  for (int i = 0; i < n; ++i) {
+    const icp_request& q = reqs[i];
+    auto r = std::make_unique<OwnedRequest>();
+    r->P_dev = q.P; r->Q_dev = q.Q;
+    r->Qn_dev = mode_plane(q.params.mode) ? q.Qn : nullptr;
+    r->M = q.M; r->N = q.N; r->prm = q.params;
+    r->ready = ready;
+    r->t_submit = now;
+    rs[i] = std::move(r);
+  }
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->failed) return ICP_ERR_DEVICE;
+    if (ctx->queue.size() + ctx->reserved + n > kQueueCap) return ICP_ERR_QUEUE_FULL;
+    const uint64_t first = ctx->next_ticket;
+    ctx->next_ticket += (uint64_t)n;
+    for (int i = 0; i < n; ++i) {
+      tickets_out[i] = first + (uint64_t)i;
+      ctx->state[tickets_out[i]] = 0;
+      tune_request(ctx, *rs[i], 1);
+      rs[i]->ticket = tickets_out[i];
+      ctx->queue.push_back(std::move(rs[i]));
+    }
+    if (!ctx->started) {
+      ctx->started = true;
+      ctx->worker = std::thread(scheduler, ctx);
+    }
+  }
+  ctx->cv.notify_all();
   return ICP_OK;
 }
 

@@ -59,6 +59,41 @@ def test_batch_equals_alone_bitwise(ctx):
         assert g["latency_ms"] > 0
 
 
+def test_device_inputs_equal_host_inputs(ctx):
+    """icp_batch_submit_dev reads the arrays in HBM in place: the results are
+    those of the same requests submitted as host arrays, bit for bit, also
+    when the arrays are written by work still queued on the caller's stream
+    at submission (the setups wait for it)."""
+    import torch
+    reqs = _requests(10, seed_config=44)
+    announce("batch of 10 pairs: device inputs vs host inputs")
+    host = _wait(ctx, B.icp_batch_submit(ctx, [r for _, r in reqs]))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        # zeros first, then the real coordinates, both queued on s
+        dreqs = []
+        for _, (P, Q, Qn, prm) in reqs:
+            t = [None if a is None else torch.zeros(a.shape, dtype=torch.float32, device="cuda")
+                 for a in (P, Q, Qn)]
+            for dst, a in zip(t, (P, Q, Qn)):
+                if a is not None:
+                    dst.copy_(torch.from_numpy(a).pin_memory().to("cuda", non_blocking=True))
+            dreqs.append((t[0], t[1], t[2], prm))
+        tickets = B.icp_batch_submit_dev(ctx, dreqs, stream=s)
+    dev = _wait(ctx, tickets)
+    for h, g in zip(host, dev):
+        assert np.array_equal(h["T"], g["T"]) and h["nn_passes"] == g["nn_passes"]
+        assert h["energy"] == g["energy"]
+    # sizes and parameters are checked; nothing is queued on an error
+    P, Q = dreqs[0][0], dreqs[0][1]
+    bad = B.icp_params_default(B.ICP_P2PL_WELSCH, nu_min=1e-3)
+    rc, _ = B.icp_batch_submit_dev(ctx, [(P, Q, None, bad)], raw=True)
+    assert rc == B.ICP_ERR_NO_NORMALS
+    rc, _ = B.icp_batch_submit_dev(ctx, [(P[:0], Q, None, B.icp_params_default(B.ICP_P2P_L2))], raw=True)
+    assert rc == B.ICP_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+
+
 def test_batch_exhaustive_edge_shapes(ctx):
     # exhaustive-method pairs in the multi-slot engine: odd tile counts (a tile
     # pair whose second tile is missing or partial), single and ragged clusters;
