@@ -31,12 +31,7 @@ __global__ __launch_bounds__(256) void epi_kernel(const SlotDesc* __restrict__ d
     const int g = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (g >= wl->epi_total) break;
-    int lo = 0, hi = wl->n_active - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (wl->epi_base[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    lo = __builtin_amdgcn_readfirstlane(lo);
+    const int lo = wave_find_slot(wl->epi_base, wl->n_active, g);
     const int slot = __builtin_amdgcn_readfirstlane(wl->slot[lo]);
     const SlotDesc& D = descs[slot];
     const SlotState& S = states[slot];

@@ -265,6 +265,28 @@ __device__ __forceinline__ int slice_queue_item(int* q, int total, int round) {
 }
 
 constexpr int kMaxSlots = 1024;
+
+// Compacted-list index of work item g: the largest a < n with base[a] <= g
+// (base is a nondecreasing prefix with base[0] = 0 <= g). The wavefront
+// probes 64 evenly spaced entries, then the entries between the last probe
+// that qualifies and the next: two memory round trips for n <= 4096, where a
+// bisection takes one per step. Called by all 64 lanes of a wavefront with
+// uniform arguments; returns a uniform value.
+__device__ __forceinline__ int wave_find_slot(const int* __restrict__ base, int n, int g) {
+  static_assert(kMaxSlots <= 64 * 64, "two probe levels cover the compacted list");
+  if (n <= 1) return 0;
+  const int lane = (int)(threadIdx.x & 63);
+  const int step = (n + 63) >> 6;
+  int i = lane * step;
+  unsigned long long m = __builtin_amdgcn_ballot_w64(i < n && ldg(base, i) <= g);
+  int lo = (63 - __builtin_clzll(m)) * step;  // lane 0 probes base[0] <= g
+  if (step > 1) {
+    i = lo + lane;
+    m = __builtin_amdgcn_ballot_w64(lane < step && i < n && ldg(base, i) <= g);
+    lo += 63 - __builtin_clzll(m);
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
 // trace row: [E, nu, solver position, reuse, T_eval (16), proposal (16)]
 constexpr int kTraceRow = 36;
 

@@ -225,14 +225,6 @@ __device__ __forceinline__ int filter_cluster(const float4* __restrict__ tg,
 }
 
 
-__device__ __forceinline__ int find_slot(const int* __restrict__ base, int n_active, int g) {
-  int lo = 0, hi = n_active - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (base[mid] <= g) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
 
 // Transformed source point of this lane and its warm-start bound W (the exact
 // FP32 squared distance to the previous pass's closest target, inflated so
@@ -296,7 +288,7 @@ __global__ __launch_bounds__(64 * kCullWaves) void nn_cull_kernel(
     const int g = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (g >= wl->nn_total) break;
-    const int a = __builtin_amdgcn_readfirstlane(find_slot(wl->nn_base, wl->n_active, g));
+    const int a = wave_find_slot(wl->nn_base, wl->n_active, g);
     // a wave-uniform slot keeps the descriptor's fields in scalar registers
     const int slot = __builtin_amdgcn_readfirstlane(wl->slot[a]);
     const SlotDesc& D = descs[slot];
@@ -548,7 +540,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     if (lane == 0) g = slice_queue_item(wl->q_s, s_total, round);
     g = __builtin_amdgcn_readfirstlane(__shfl(g, 0, 64));
     if (g >= s_total) break;
-    const int a = __builtin_amdgcn_readfirstlane(find_slot(wl->s_base, wl->n_active, g));
+    const int a = wave_find_slot(wl->s_base, wl->n_active, g);
     const int slot = __builtin_amdgcn_readfirstlane(wl->slot[a]);
     const SlotDesc& D = descs[slot];
     const SlotState& S = states[slot];
@@ -955,7 +947,7 @@ __global__ __launch_bounds__(64) void nn_brute_multi_kernel(const SlotDesc* __re
   const int total = wl->b_total;
   const int na = wl->n_active;
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
-    const int a = find_slot(wl->b_base, na, g);
+    const int a = wave_find_slot(wl->b_base, na, g);
     const int slot = __builtin_amdgcn_readfirstlane(wl->slot[a]);
     const SlotDesc& D = descs[slot];
     const SlotState& S = states[slot];
