@@ -106,10 +106,16 @@ __device__ __forceinline__ unsigned long long exact_scan(const float4* qorg, int
 // The same lower bound with fused multiply-adds (fewer roundings). Callers
 // compare it against a threshold raised by 2^-19 for its rounding: lb2 <=
 // thr (1 + 2^-19) holds whenever lb2 (1 - 2^-20) <= thr does.
+// The offset from the box is p - clamp(p, lo, hi), the clamp a single median
+// of three: p - lo below the box, p - hi above it (the negated values of
+// lo - p and p - hi, so the squares are those of the two-sided form), 0
+// inside. An empty box (lo = +inf, hi = -inf: the padding chunks of a
+// pair's last cluster) gives 0, so such a chunk is filtered, which its
+// infinite filter values leave without effect.
 __device__ __forceinline__ float box_lb2_fma(float px, float py, float pz, float4 lo, float4 hi) {
-  const float dx = fmaxf(fmaxf(lo.x - px, px - hi.x), 0.0f);
-  const float dy = fmaxf(fmaxf(lo.y - py, py - hi.y), 0.0f);
-  const float dz = fmaxf(fmaxf(lo.z - pz, pz - hi.z), 0.0f);
+  const float dx = px - __builtin_amdgcn_fmed3f(px, lo.x, hi.x);
+  const float dy = py - __builtin_amdgcn_fmed3f(py, lo.y, hi.y);
+  const float dz = pz - __builtin_amdgcn_fmed3f(pz, lo.z, hi.z);
   return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
 }
 
@@ -208,8 +214,9 @@ __device__ __forceinline__ int filter_cluster(const float4* __restrict__ tg,
 #pragma unroll
     for (int ch = 0; ch < kChunksPerCluster; ++ch) {
       const float lb2 = box_lb2_fma(px, py, pz, bx[2 * ch], bx[2 * ch + 1]);
-      if (wave_any_of(lb2 <= thr, vmask)) mask |= 1u << ch;
+      mask |= wave_any_of(lb2 <= thr, vmask) ? (1u << ch) : 0u;
     }
+    mask = __builtin_amdgcn_readfirstlane(mask);  // uniform: the chunk loop runs on scalar bits
     const int n = __builtin_popcount(mask);
     for (; mask; mask &= mask - 1u) {
       const int ch = __builtin_ctz(mask);
