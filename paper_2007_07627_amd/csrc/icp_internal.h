@@ -162,6 +162,9 @@ struct SlotState {
 };
 
 constexpr int kQueues = 8;
+// sub-queues of the slice queue: a multiple of kQueues, so that sub-queue x
+// is served by the workgroups of die x mod kQueues only
+constexpr int kSliceQueues = 8;
 constexpr int kQueueStride = 64;  // ints between sub-queue counters
 constexpr int kStatStride = 32;  // u64 between per-die statistics lines
 
@@ -198,7 +201,7 @@ struct WorkList {
   // dynamic work counters (reset by the planners): kQueues sub-queues each
   int q_nn[kQueues * kQueueStride];
   int q_epi[kQueues * kQueueStride];
-  int q_s[kQueues * kQueueStride];
+  int q_s[kSliceQueues * kQueueStride];
 };
 
 // Exhaustive method in the multi-slot engine: one item = a pair of 64-source
@@ -257,10 +260,11 @@ __device__ __forceinline__ int queue_item(int* q, int round) {
 constexpr int kSliceRun = 16;
 
 __device__ __forceinline__ int slice_queue_item(int* q, int total, int round) {
-  const int x = (int)(blockIdx.x % kQueues);
-  const int nb = ((int)gridDim.x - x + kQueues - 1) / kQueues;  // workgroups of die x
-  const int k = round == 0 ? (int)(blockIdx.x / kQueues) : nb + atomicAdd(&q[x * kQueueStride], 1);
-  const long long item = ((long long)(k / kSliceRun) * kQueues + x) * kSliceRun + (k % kSliceRun);
+  static_assert(kSliceQueues % kQueues == 0, "every slice sub-queue belongs to one die");
+  const int x = (int)(blockIdx.x % kSliceQueues);
+  const int nb = ((int)gridDim.x - x + kSliceQueues - 1) / kSliceQueues;  // workgroups of sub-queue x
+  const int k = round == 0 ? (int)(blockIdx.x / kSliceQueues) : nb + atomicAdd(&q[x * kQueueStride], 1);
+  const long long item = ((long long)(k / kSliceRun) * kSliceQueues + x) * kSliceRun + (k % kSliceRun);
   return item < total ? (int)item : total;
 }
 

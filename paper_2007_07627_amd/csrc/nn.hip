@@ -522,7 +522,7 @@ __global__ __launch_bounds__(1024) void slice_plan_kernel(const SlotDesc* __rest
     s[t] += x;
     __syncthreads();
   }
-  if (t < kQueues) wl->q_s[t * kQueueStride] = 0;
+  if (t < kSliceQueues) wl->q_s[t * kQueueStride] = 0;
   if (t < na) wl->s_base[t] = s[t] - v;
   if (t == 1023) {
     wl->s_base[na] = s[1023];
@@ -974,8 +974,9 @@ void launch_brute(const SlotDesc* descs, const SlotState* states, int grid, hipS
 
 void launch_nn(const SlotDesc* descs, const SlotState* states, WorkList* wl, int grid,
                bool single, hipStream_t st) {
-  // every sub-queue needs workgroups of its own (blockIdx mod kQueues)
-  grid = std::max(grid, kQueues * kCullWaves);
+  // every sub-queue needs workgroups of its own (blockIdx mod kQueues, and
+  // mod kSliceQueues for the slice kernel)
+  grid = std::max(grid, std::max(kQueues * kCullWaves, kSliceQueues));
   hipLaunchKernelGGL(nn_cull_kernel, dim3(grid / kCullWaves), dim3(64 * kCullWaves), 0, st, descs,
                      states, wl);
   if (!single) hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl);

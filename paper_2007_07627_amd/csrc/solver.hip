@@ -1101,8 +1101,8 @@ __device__ void plan_single(const SlotDesc& D, const SlotState& S, WorkList* wl,
   for (int q = 0; q < kQueues; ++q) {
     wl->q_nn[q * kQueueStride] = 0;
     wl->q_epi[q * kQueueStride] = 0;
-    wl->q_s[q * kQueueStride] = 0;
   }
+  for (int q = 0; q < kSliceQueues; ++q) wl->q_s[q * kQueueStride] = 0;
 }
 
 // Sum of the per-tile partial moments in a fixed order: lane l adds tiles
