@@ -249,6 +249,11 @@ static void stats_from(const unsigned long long* v, icp_result* r) {
   r->nn_exact_pairs = b;
 }
 
+// Setup streams of the batch engine (HIP maps streams onto a few hardware
+// queues; a handful suffices to overlap the short setup kernels of many
+// requests).
+constexpr int kSetupStreams = 4;
+
 static void fill_stats(const HostSlot& h, hipStream_t st, icp_result* r) {
   unsigned long long v[kQueues * kStatStride] = {};
   if (h.mem && hipMemcpyAsync(v, h.mem + h.L.o_stats, sizeof v, hipMemcpyDeviceToHost, st) == hipSuccess &&
@@ -278,7 +283,12 @@ struct Engine {
   bool single = false;       // one slot at a time, planned by its own solver
   bool brute = false;        // one-slot engine: the resident pair uses the exhaustive method
   hipStream_t st = nullptr;  // passes
-  hipStream_t side = nullptr;  // admission / setup
+  hipStream_t side = nullptr;  // admission / setup (the first of `sides`)
+  // Setup streams: slot s is set up on sides[s % sides.size()], so that the
+  // setups of a large admission (a few hundred short kernels per request)
+  // run side by side instead of one request after another.
+  std::vector<hipStream_t> sides;
+  hipStream_t setup_stream(int s) const { return sides[(size_t)s % sides.size()]; }
   // Uploads of the admission. Host arrays are pageable, and a pageable copy
   // returns only once it has run, so on their own stream the host waits for
   // the copy itself, not for the setup kernels queued before it on `side`.
@@ -323,7 +333,9 @@ struct Engine {
     arena = a;
     HIP_OK(hipSetDevice(dev));
     HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    HIP_OK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    sides.assign(single ? 1 : kSetupStreams, nullptr);
+    for (auto& x : sides) HIP_OK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    side = sides[0];
     HIP_OK(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&up_done, hipEventDisableTiming));
     HIP_OK(hipMalloc(&d_desc, sizeof(SlotDesc) * kMaxSlots));
@@ -370,7 +382,9 @@ struct Engine {
     if (h_reset) (void)hipHostFree(h_reset);
     h_fin_state = nullptr; h_fin_stats = nullptr; h_reset = nullptr;
     if (st) (void)hipStreamDestroy(st);
-    if (side) (void)hipStreamDestroy(side);
+    for (auto& x : sides)
+      if (x) (void)hipStreamDestroy(x);
+    sides.clear();
     if (up) (void)hipStreamDestroy(up);
     if (up_done) (void)hipEventDestroy(up_done);
     d_desc = nullptr; d_state = nullptr; d_wl = nullptr; d_done = nullptr; h_done = nullptr;
@@ -481,7 +495,7 @@ struct Engine {
     auto F = [&](size_t o) { return reinterpret_cast<float*>(b + o); };
     auto F4 = [&](size_t o) { return reinterpret_cast<float4*>(b + o); };
     unsigned* scratch = reinterpret_cast<unsigned*>(b + L.o_scratch);
-    hipStream_t ss = side;
+    hipStream_t ss = setup_stream(s);
     char* st_base = reinterpret_cast<char*>(d_state + s);
     float* bbQ = reinterpret_cast<float*>(st_base + offsetof(SlotState, bbQ));
     float* bbP = reinterpret_cast<float*>(st_base + offsetof(SlotState, bbP));
@@ -603,8 +617,7 @@ struct Engine {
     h.zero = 0;
     HIP_OK(hipMemcpyAsync(d_done + s, &h.zero, sizeof(int), hipMemcpyHostToDevice, up));
     HIP_OK(hipEventRecord(up_done, up));
-    HIP_OK(hipStreamWaitEvent(ss, up_done, 0));
-    if (r.ready) HIP_OK(hipStreamWaitEvent(ss, r.ready->ev, 0));  // the activation on `side` covers the uploads
+    HIP_OK(hipStreamWaitEvent(ss, up_done, 0));  // the activation on the setup stream covers the uploads
     h_done[s] = 0;
     if (sync) HIP_OK(hipStreamSynchronize(ss));
     return hipGetLastError() == hipSuccess;
@@ -614,14 +627,14 @@ struct Engine {
   // host sources of its uploads may be freed.
   void drain() {
     (void)hipStreamSynchronize(up);
-    (void)hipStreamSynchronize(side);
+    for (auto x : sides) (void)hipStreamSynchronize(x);
   }
 
   // Make the slot RUNNING on the pass stream once its setup has completed.
   bool activate(int s) {
     hipEvent_t ev;
     HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    HIP_OK(hipEventRecord(ev, side));
+    HIP_OK(hipEventRecord(ev, setup_stream(s)));
     HIP_OK(hipStreamWaitEvent(st, ev, 0));
     launch_boot(d_desc, d_state, s, d_wl, single, st);
     (void)hipEventDestroy(ev);
