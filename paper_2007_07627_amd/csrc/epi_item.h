@@ -14,24 +14,22 @@
 //    classical point-to-plane ICP takes g = 1 and the energy term B^2.
 #pragma once
 #include "icp_internal.h"
+#include "wave_sum.h"
 
 namespace icp {
 
+// The block's sum of v (NV <= 32 values per thread, four wavefronts): each
+// wavefront's sum by recursive halving, then the four in wavefront order.
 template <int NV>
-__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* out) {
+__device__ __forceinline__ void block_reduce_store(const double (&v)[NV], double* out) {
+  static_assert(NV <= 32, "at most 32 values");
   __shared__ double s_red[4][32];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double w[32];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double x = v[i];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-    v[i] = x;
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) s_red[wave][i] = v[i];
-  }
+  for (int i = 0; i < 32; ++i) w[i] = i < NV ? v[i] : 0.0;
+  const double t = wave_sum32(w);
+  if ((lane & 1) == 0) s_red[wave][lane >> 1] = t;
   __syncthreads();
   if (threadIdx.x < NV) {
     const int i = threadIdx.x;

@@ -13,7 +13,7 @@ constexpr int kCluster = 128;    // targets per cluster of the Hilbert-ordered i
 constexpr int kChunk = 16;       // targets per deferred-argmin chunk
 constexpr int kChunksPerCluster = kCluster / kChunk;
 constexpr int kSuper = 16;       // clusters per super-cluster (coarse culling level)
-constexpr int kEpiRows = 4;      // sources per thread of a reduction work item
+constexpr int kEpiRows = 2;      // sources per thread of a reduction work item
 constexpr int kEpiTile = 256 * kEpiRows;  // sources per reduction work item
 constexpr int kPartStride = 32;  // doubles per reduction partial
 constexpr int kHist = 8;         // Anderson ring capacity (m <= 6 needs m + 1)

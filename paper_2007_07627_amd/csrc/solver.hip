@@ -19,6 +19,7 @@
 //  - Zero total weight or a singular 6x6 system ends the registration with a
 //    flag and the current transform.
 #include "icp_internal.h"
+#include "wave_sum.h"
 
 namespace icp {
 
@@ -1105,29 +1106,26 @@ __device__ void plan_single(const SlotDesc& D, const SlotState& S, WorkList* wl,
   for (int q = 0; q < kSliceQueues; ++q) wl->q_s[q * kQueueStride] = 0;
 }
 
-// Sum of the per-tile partial moments in a fixed order: lane l adds tiles
-// l, l + 64, ... in turn, then a fixed butterfly combines the lanes (lane 0
-// holds the result). The value count is a template parameter so that the
-// accumulators stay in registers.
+// Sum of the per-item partial moments in a fixed order: lane l adds items
+// l, l + 64, ... in turn, then the wavefront sums the lanes by recursive
+// halving (wave_sum32); every lane receives the totals. The value count is a
+// template parameter so that the accumulators stay in registers.
 template <int NV>
 __device__ __forceinline__ void merge_partials(const SlotDesc& D, double* acc) {
   const int lane = threadIdx.x;
-  double a[NV];
+  double a[32];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) a[v] = 0.0;
-  // four tiles' loads in flight per lane; the sums stay in tile order
+  for (int v = 0; v < 32; ++v) a[v] = 0.0;
+  // four items' loads in flight per lane; the sums stay in item order
 #pragma unroll 4
   for (int e = lane; e < D.nepi; e += 64) {
     const double* p = D.part + (size_t)e * kPartStride;
 #pragma unroll
     for (int v = 0; v < NV; ++v) a[v] += ldg(p, v);
   }
+  const double t = wave_sum32(a);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double x = a[v];
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-    acc[v] = x;
-  }
+  for (int v = 0; v < NV; ++v) acc[v] = readlane_f64(t, 2 * v);
 #pragma unroll
   for (int v = NV; v < kP2PLVals; ++v) acc[v] = 0.0;
 }
