@@ -570,7 +570,7 @@ def brute_batch_roofline(B, ds):
     pairs = float(sum(r["nn_pairs"] for r in res))
     passes = max(1, st["passes"])
     tf = pairs * FLOPS_PER_PAIR / (max(st["nn_ms"], 1e-9) * 1e-3) / 1e12
-    return {"kernel": "nn_brute_multi_kernel (exhaustive, batch engine)", "pairs": len(ds), "M": 4096,
+    return {"kernel": "nn_slice_kernel, exhaustive items of the batch engine", "pairs": len(ds), "M": 4096,
             "N": 4096, "batch_passes": passes, "pairs_examined_per_pass": pairs / passes,
             "nn_ms_per_pass": st["nn_ms"] / passes, "achieved_tflops": tf, "peak_tflops": FP32_PEAK_TFLOPS,
             "frac": tf / FP32_PEAK_TFLOPS, "registrations_per_s_profiled": len(ds) / wall}

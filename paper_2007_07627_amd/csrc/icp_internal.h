@@ -202,6 +202,7 @@ struct WorkList {
   int q_nn[kQueues * kQueueStride];
   int q_epi[kQueues * kQueueStride];
   int q_s[kSliceQueues * kQueueStride];
+  int q_b[kQueues * kQueueStride];  // exhaustive-method items (multi-slot engine)
 };
 
 // Exhaustive method in the multi-slot engine: one item = a pair of 64-source

@@ -162,25 +162,38 @@ __device__ __forceinline__ float lane_f(float v, int j) {
 // of the three FMAs and of the last FMA); 4u is used, so for the chunk
 // minimum v: lo = v - 2^-22 |v| - delta, hi = v + 2^-22 |v| + delta,
 // delta = 2^-22 7 (|pl| + rho)^2.
+// Minimum of n values by a balanced tree of three-way minima (v_min3: one
+// instruction per two values).
+template <int N>
+__device__ __forceinline__ float min_tree(const float* v) {
+  if constexpr (N == 1) {
+    return v[0];
+  } else if constexpr (N == 2) {
+    return fminf(v[0], v[1]);
+  } else {
+    constexpr int M = (N + 2) / 3;
+    float w[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const int a = 3 * i;
+      if (a + 2 < N) w[i] = fminf(fminf(v[a], v[a + 1]), v[a + 2]);
+      else if (a + 1 < N) w[i] = fminf(v[a], v[a + 1]);
+      else w[i] = v[a];
+    }
+    return min_tree<M>(w);
+  }
+}
+
 __device__ __forceinline__ void filter_chunk(const float4* __restrict__ qc, int id, float npx,
                                              float npy, float npz, float pp, float delta,
                                              LaneBest& L) {
-  static_assert(kChunk == 16, "the min tree below covers 16 targets");
   float sv[kChunk];
 #pragma unroll
   for (int j = 0; j < kChunk; ++j) {
     const float4 a = qc[j];
     sv[j] = __builtin_fmaf(npx, a.x, __builtin_fmaf(npy, a.y, __builtin_fmaf(npz, a.z, a.w)));
   }
-  // balanced tree of three-way minima (8 instructions for 16 values)
-  const float t0 = fminf(fminf(sv[0], sv[1]), sv[2]);
-  const float t1 = fminf(fminf(sv[3], sv[4]), sv[5]);
-  const float t2 = fminf(fminf(sv[6], sv[7]), sv[8]);
-  const float t3 = fminf(fminf(sv[9], sv[10]), sv[11]);
-  const float t4 = fminf(fminf(sv[12], sv[13]), sv[14]);
-  const float m0 = fminf(fminf(t0, t1), t2);
-  const float m1 = fminf(fminf(t3, t4), sv[15]);
-  const float v = __builtin_fmaf(2.0f, fminf(m0, m1), pp);
+  const float v = __builtin_fmaf(2.0f, min_tree<kChunk>(sv), pp);
   // an all-padding chunk has v = +inf: keep lo = hi = +inf (no inf - inf)
   const float e = fminf(0x1.0p-22f * fabsf(v) + delta, 1e38f);
   const float lo = v - e, hi = v + e;
@@ -523,6 +536,7 @@ __global__ __launch_bounds__(1024) void slice_plan_kernel(const SlotDesc* __rest
     __syncthreads();
   }
   if (t < kSliceQueues) wl->q_s[t * kQueueStride] = 0;
+  if (t < kQueues) wl->q_b[t * kQueueStride] = 0;
   if (t < na) wl->s_base[t] = s[t] - v;
   if (t == 1023) {
     wl->s_base[na] = s[1023];
@@ -531,6 +545,10 @@ __global__ __launch_bounds__(1024) void slice_plan_kernel(const SlotDesc* __rest
 }
 
 // ------------------------------------------------------------------ slice kernel
+__device__ void multi_brute_items(const SlotDesc* __restrict__ descs,
+                                  const SlotState* __restrict__ states, WorkList* __restrict__ wl,
+                                  float4* s_tgt);
+
 __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict__ descs,
                                                       const SlotState* __restrict__ states,
                                                       WorkList* __restrict__ wl) {
@@ -750,6 +768,7 @@ __global__ __launch_bounds__(64) void nn_slice_kernel(const SlotDesc* __restrict
     }
     __syncthreads();
   }
+  if (!wl->single) multi_brute_items(descs, states, wl, s_tgt);
 }
 
 // ------------------------------------------------------------------ exhaustive kernel
@@ -946,25 +965,37 @@ __global__ __launch_bounds__(64) void nn_brute_kernel(const SlotDesc* __restrict
 }
 
 // Multi-slot engine, exhaustive method: the items of every searching pair
-// (brute_items per pair, prefixed by the planner), shared out statically.
-__global__ __launch_bounds__(64) void nn_brute_multi_kernel(const SlotDesc* __restrict__ descs,
-                                                            const SlotState* __restrict__ states,
-                                                            const WorkList* __restrict__ wl) {
-  __shared__ float4 s_tgt[kCluster];
-  const int total = wl->b_total;
-  const int na = wl->n_active;
-  for (int g = blockIdx.x; g < total; g += gridDim.x) {
+// (brute_items per pair, prefixed by the planner), run by the slice kernel's
+// wavefronts once the slices are used up: the uniform items fill the uneven
+// tail of the slices. Sub-queue x (the workgroups on die x) serves the items
+// x, x + kQueues, ...
+__device__ void multi_brute_items(const SlotDesc* __restrict__ descs,
+                                                  const SlotState* __restrict__ states,
+                                                  WorkList* __restrict__ wl, float4* s_tgt) {
+  // loop bounds in scalar registers: the exit test is uniform
+  const int total = __builtin_amdgcn_readfirstlane(wl->b_total);
+  const int na = __builtin_amdgcn_readfirstlane(wl->n_active);
+  const int x = (int)(blockIdx.x % kQueues);
+  for (;;) {
+    int k = 0;
+    if (threadIdx.x == 0) k = atomicAdd(&wl->q_b[x * kQueueStride], 1);
+    const int g = __builtin_amdgcn_readfirstlane(__shfl(k, 0, 64)) * kQueues + x;
+    if (g >= total) break;
     const int a = wave_find_slot(wl->b_base, na, g);
     const int slot = __builtin_amdgcn_readfirstlane(wl->slot[a]);
     const SlotDesc& D = descs[slot];
     const SlotState& S = states[slot];
-    const int item = g - wl->b_base[a];
+    const int item = g - __builtin_amdgcn_readfirstlane(wl->b_base[a]);
     const int split = brute_split(D.ncl, D.brute_clusters);
     const int len = (D.ncl + split - 1) / split;
-    const int pi = item / split, k = item - pi * split;
-    const int c0 = k * len, c1 = min(D.ncl, c0 + len);
-    if (c0 >= c1) continue;
-    brute_item(D, S, pi, c0, c1, s_tgt);
+    const int pi = item / split, kk = item - pi * split;
+    const int c0 = kk * len, c1 = min(D.ncl, c0 + len);
+    if (c0 < c1) brute_item(D, S, pi, c0, c1, s_tgt);
+    // The wavefront reconverges here before lane 0 fetches the next item
+    // (as in the slice loop). Without this point the compiled loop let lane 0
+    // leave after an item while the other lanes went round again on the
+    // stale item number, without end.
+    __syncthreads();
   }
 }
 
@@ -981,7 +1012,6 @@ void launch_nn(const SlotDesc* descs, const SlotState* states, WorkList* wl, int
                      states, wl);
   if (!single) hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl);
   hipLaunchKernelGGL(nn_slice_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
-  if (!single) hipLaunchKernelGGL(nn_brute_multi_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
 }
 
 }  // namespace icp
