@@ -343,7 +343,7 @@ def batch_bench(args, B, pairs):
                                    "point-to-plane trajectories can wander into other minima; the oracle "
                                    "lands in such minima too (tests replay these trajectories step by step)"},
         "roofline": nn_roofline(prof, float(sum(r["nn_pairs"] for r in res_prof)), "batch-256",
-                                "one profiled batch of the same 256 pairs; kernels timed per batch pass"),
+                                "one profiled batch of the same 256 pairs; kernels timed per batch pass (the two slot branches of a pass one after the other, their intervals summed)"),
         "tuning": tuning,
     }
     return out, {"pairs": pairs, "passes": passes}

@@ -33,15 +33,15 @@ namespace icp {
 void launch_nn(const SlotDesc*, const SlotState*, WorkList*, int, bool, hipStream_t);
 void launch_brute(const SlotDesc*, const SlotState*, int, hipStream_t);
 void launch_epi(const SlotDesc*, const SlotState*, WorkList*, int, bool, hipStream_t);
-void launch_solver(const SlotDesc*, SlotState*, int, int*, WorkList*, bool, hipStream_t);
+void launch_solver(const SlotDesc*, SlotState*, int, int*, WorkList*, bool, hipStream_t, int, int);
 void launch_boot(const SlotDesc*, SlotState*, int, WorkList*, bool, hipStream_t);
-void launch_median(const SlotDesc*, SlotState*, int, hipStream_t);
+void launch_median(const SlotDesc*, SlotState*, int, hipStream_t, int, int);
 void launch_estimate_normals(const float4*, const float4*, const float4*, const float4*, const float4*,
                              int, int, const float*, const float*, const float*, float*, hipStream_t);
 void launch_nu_min_auto(const float4*, const float4*, const float4*, const float4*, const float4*, int,
                         int, const float*, const float*, const float*, const float*, const float*,
                         const float*, int, bool, double*, double*, hipStream_t);
-void launch_plan(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t);
+void launch_plan(const SlotDesc*, const SlotState*, WorkList*, int, hipStream_t, int, int);
 void launch_aos_to_soa(const float*, int, float*, float*, float*, hipStream_t);
 void launch_bbox(const float*, const float*, const float*, int, float*, double*, hipStream_t);
 size_t sort_scratch_words(int);
@@ -277,10 +277,19 @@ static void fill_result(const SlotState& S, icp_result* r) {
 
 // ------------------------------------------------------------------ engine
 
+// Branches of the multi-slot engine: slot s belongs to branch s mod
+// kBranches, each branch with its own work list, and a replay runs the
+// branches' passes as parallel chains (the second on its own stream), so that
+// one branch's reduction, solver and planning overlap the other's search.
+constexpr int kBranches = 2;
+
 struct Engine {
   int dev = 0;
   int capacity = 1;
   bool single = false;       // one slot at a time, planned by its own solver
+  int nbr = 1;               // branches (kBranches for the multi-slot engine)
+  hipStream_t st2 = nullptr;  // the second branch's passes inside a replay
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool brute = false;        // one-slot engine: the resident pair uses the exhaustive method
   hipStream_t st = nullptr;  // passes
   hipStream_t side = nullptr;  // admission / setup (the first of `sides`)
@@ -333,6 +342,12 @@ struct Engine {
     arena = a;
     HIP_OK(hipSetDevice(dev));
     HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    nbr = single ? 1 : kBranches;
+    if (nbr > 1) {
+      HIP_OK(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
+      HIP_OK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+      HIP_OK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    }
     sides.assign(single ? 1 : kSetupStreams, nullptr);
     for (auto& x : sides) HIP_OK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
     side = sides[0];
@@ -340,7 +355,7 @@ struct Engine {
     HIP_OK(hipEventCreateWithFlags(&up_done, hipEventDisableTiming));
     HIP_OK(hipMalloc(&d_desc, sizeof(SlotDesc) * kMaxSlots));
     HIP_OK(hipMalloc(&d_state, sizeof(SlotState) * kMaxSlots));
-    HIP_OK(hipMalloc(&d_wl, sizeof(WorkList)));
+    HIP_OK(hipMalloc(&d_wl, sizeof(WorkList) * nbr));
     HIP_OK(hipMalloc(&d_done, sizeof(int) * kMaxSlots));
     HIP_OK(hipHostMalloc((void**)&h_done, sizeof(int) * kMaxSlots, hipHostMallocDefault));
     HIP_OK(hipHostMalloc((void**)&h_fin_state, sizeof(SlotState) * kMaxSlots, hipHostMallocDefault));
@@ -351,7 +366,7 @@ struct Engine {
     HIP_OK(hipMemset(d_desc, 0, sizeof(SlotDesc) * kMaxSlots));
     HIP_OK(hipMemset(d_state, 0, sizeof(SlotState) * kMaxSlots));
     HIP_OK(hipMemset(d_done, 0, sizeof(int) * kMaxSlots));
-    HIP_OK(hipMemset(d_wl, 0, sizeof(WorkList)));
+    HIP_OK(hipMemset(d_wl, 0, sizeof(WorkList) * nbr));
     std::memset(h_done, 0, sizeof(int) * kMaxSlots);
     hs.assign(kMaxSlots, HostSlot());
     int cus = 256;
@@ -382,6 +397,10 @@ struct Engine {
     if (h_reset) (void)hipHostFree(h_reset);
     h_fin_state = nullptr; h_fin_stats = nullptr; h_reset = nullptr;
     if (st) (void)hipStreamDestroy(st);
+    if (st2) (void)hipStreamDestroy(st2);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    st2 = nullptr; ev_fork = nullptr; ev_join = nullptr;
     for (auto& x : sides)
       if (x) (void)hipStreamDestroy(x);
     sides.clear();
@@ -392,7 +411,7 @@ struct Engine {
   }
 
   bool ensure_events(int passes) {
-    while ((int)pev.size() < 4 * passes) {
+    while ((int)pev.size() < 4 * passes * nbr) {
       hipEvent_t e;
       HIP_OK(hipEventCreate(&e));
       pev.push_back(e);
@@ -407,36 +426,51 @@ struct Engine {
     else (void)hipEventRecord(pev[k], s);
   }
 
-  // One pass. The one-slot engine is planned by its solver (and boot) kernel,
-  // so a pass is cull, slices, reduction, solver, with the median only on
-  // the pass that needs it (the first); the multi-slot engine plans its work
-  // lists on the device and runs the median kernel every pass (it returns at
-  // once for slots that do not need it).
-  void enqueue_pass(hipStream_t s, int i = 0, bool capturing = false, bool median = false) {
-    if (!single) launch_plan(d_desc, d_state, d_wl, capacity, s);
-    mark(4 * i, s, capturing);
+  // One pass of branch b (the one-slot engine: its single slot). The one-slot
+  // engine is planned by its solver (and boot) kernel, so a pass is cull,
+  // slices, reduction, solver, with the median only on the pass that needs it
+  // (the first); the multi-slot engine plans the branch's work lists on the
+  // device and runs the median kernel every pass (it returns at once for
+  // slots that do not need it). Timing events 4 k .. 4 k + 3.
+  void enqueue_branch(hipStream_t s, int b, int k, bool capturing, bool median) {
+    if (!single) launch_plan(d_desc, d_state, d_wl + b, capacity, s, b, nbr);
+    mark(4 * k, s, capturing);
     // the one-slot engine's exhaustive method needs no cull pass
     if (single && brute) launch_brute(d_desc, d_state, nn_grid, s);
-    else launch_nn(d_desc, d_state, d_wl, nn_grid, single, s);
-    mark(4 * i + 1, s, capturing);
-    launch_epi(d_desc, d_state, d_wl, epi_grid, single, s);
-    mark(4 * i + 2, s, capturing);
-    if (!single || median) launch_median(d_desc, d_state, capacity, s);
-    launch_solver(d_desc, d_state, capacity, d_done, d_wl, single, s);
-    mark(4 * i + 3, s, capturing);
+    else launch_nn(d_desc, d_state, d_wl + b, nn_grid, single, s);
+    mark(4 * k + 1, s, capturing);
+    launch_epi(d_desc, d_state, d_wl + b, epi_grid, single, s);
+    mark(4 * k + 2, s, capturing);
+    if (!single || median) launch_median(d_desc, d_state, capacity, s, b, nbr);
+    launch_solver(d_desc, d_state, capacity, d_done, d_wl + b, single, s, b, nbr);
+    mark(4 * k + 3, s, capturing);
+  }
+
+  // One pass of every branch, the branches one after another on stream s
+  // (the form with timing events).
+  void enqueue_pass(hipStream_t s, int i = 0, bool capturing = false, bool median = false) {
+    for (int b = 0; b < nbr; ++b) enqueue_branch(s, b, i * nbr + b, capturing, median);
   }
 
   // after the stream has been synchronised
+  // Per pass, the sums over its branches.
   void collect_profile(int passes) {
     if (!prof) return;
     for (int i = 0; i < passes; ++i) {
-      float a = 0.f, b = 0.f, c = 0.f;
-      if (hipEventElapsedTime(&a, pev[4 * i], pev[4 * i + 1]) == hipSuccess &&
-          hipEventElapsedTime(&b, pev[4 * i + 1], pev[4 * i + 2]) == hipSuccess &&
-          hipEventElapsedTime(&c, pev[4 * i + 2], pev[4 * i + 3]) == hipSuccess) {
-        prof_ms[0] += a;
-        prof_ms[1] += b;
-        prof_ms[2] += c;
+      double sum[3] = {0.0, 0.0, 0.0};
+      bool ok = true;
+      for (int br = 0; br < nbr && ok; ++br) {
+        const int k = i * nbr + br;
+        float a = 0.f, b = 0.f, c = 0.f;
+        ok = hipEventElapsedTime(&a, pev[4 * k], pev[4 * k + 1]) == hipSuccess &&
+             hipEventElapsedTime(&b, pev[4 * k + 1], pev[4 * k + 2]) == hipSuccess &&
+             hipEventElapsedTime(&c, pev[4 * k + 2], pev[4 * k + 3]) == hipSuccess;
+        sum[0] += a;
+        sum[1] += b;
+        sum[2] += c;
+      }
+      if (ok) {
+        for (int j = 0; j < 3; ++j) prof_ms[j] += sum[j];
         prof_passes++;
       } else {
         (void)hipGetLastError();  // do not leave a timing failure as the sticky error
@@ -452,7 +486,18 @@ struct Engine {
     if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
     if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
     HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < phases; ++i) enqueue_pass(st, i, true);
+    if (nbr == 1) {
+      for (int i = 0; i < phases; ++i) enqueue_pass(st, i, true);
+    } else {
+      // the two branches' passes as parallel chains of the graph
+      static_assert(kBranches == 2, "one extra stream per branch beyond the first");
+      HIP_OK(hipEventRecord(ev_fork, st));
+      HIP_OK(hipStreamWaitEvent(st2, ev_fork, 0));
+      for (int i = 0; i < phases; ++i) enqueue_branch(st, 0, 2 * i, true, false);
+      for (int i = 0; i < phases; ++i) enqueue_branch(st2, 1, 2 * i + 1, true, false);
+      HIP_OK(hipEventRecord(ev_join, st2));
+      HIP_OK(hipStreamWaitEvent(st, ev_join, 0));
+    }
     HIP_OK(hipStreamEndCapture(st, &graph));
     HIP_OK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
     gphases = phases;
@@ -463,9 +508,21 @@ struct Engine {
     return true;
   }
 
+  // A free slot of the branch with the fewest resident slots (then the next
+  // fewest), lowest index first.
   int free_slot() const {
+    int cnt[kBranches] = {};
     for (int i = 0; i < capacity; ++i)
-      if (!hs[i].used) return i;
+      if (hs[i].used) cnt[i % nbr]++;
+    bool tried[kBranches] = {};
+    for (int t = 0; t < nbr; ++t) {
+      int b = -1;
+      for (int c = 0; c < nbr; ++c)
+        if (!tried[c] && (b < 0 || cnt[c] < cnt[b])) b = c;
+      tried[b] = true;
+      for (int i = b; i < capacity; i += nbr)
+        if (!hs[i].used) return i;
+    }
     return -1;
   }
 
@@ -1575,7 +1632,7 @@ icp_status icp_nn_query_dev_noalloc(const float* P_dev, int64_t M, const float* 
   if (D.method == NN_BRUTE) launch_brute(desc, state, nd->nn_grid, st);
   else launch_nn(desc, state, wl, nd->nn_grid, true, st);
   launch_epi(desc, state, wl, nd->epi_grid, true, st);
-  launch_solver(desc, state, 1, done, wl, true, st);
+  launch_solver(desc, state, 1, done, wl, true, st, 0, 1);
   return hipGetLastError() == hipSuccess ? ICP_OK : ICP_ERR_DEVICE;
 }
 

@@ -407,15 +407,17 @@ __global__ void fill_u64_kernel(unsigned long long* __restrict__ p, int n, unsig
 
 // ------------------------------------------------------------------ planner
 
-// Rebuild the compacted list of RUNNING slots and the prefix sums of their
-// closest-point and reduction work items; reset the dynamic work counters.
+// Rebuild the compacted list of RUNNING slots of one branch (slots branch,
+// branch + nbranch, ...) and the prefix sums of their closest-point and
+// reduction work items; reset the dynamic work counters.
 __global__ __launch_bounds__(1024) void plan_kernel(const SlotDesc* __restrict__ descs,
                                                     const SlotState* __restrict__ states,
-                                                    WorkList* __restrict__ wl, int capacity) {
+                                                    WorkList* __restrict__ wl, int capacity,
+                                                    int branch, int nbranch) {
   __shared__ int s_act[1024], s_nn[1024], s_epi[1024], s_b[1024];
   const int t = threadIdx.x;
   int act = 0, nn = 0, ep = 0, bi = 0;
-  if (t < capacity && states[t].status == ST_RUNNING) {
+  if (t < capacity && t % nbranch == branch && states[t].status == ST_RUNNING) {
     const SlotDesc& D = descs[t];
     act = 1;
     // cluster method: cull items (tiles) when the candidate lists are rebuilt;
@@ -532,8 +534,9 @@ void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStre
 }
 
 void launch_plan(const SlotDesc* descs, const SlotState* states, WorkList* wl, int capacity,
-                 hipStream_t st) {
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl, capacity);
+                 hipStream_t st, int branch, int nbranch) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl, capacity, branch,
+                     nbranch);
 }
 
 }  // namespace icp

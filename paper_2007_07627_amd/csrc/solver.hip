@@ -1019,8 +1019,9 @@ stage_end:
 // Median of the slot's median keys (the element of rank M/2 of non-negative
 // FP64 values, ordered by their bit patterns) by an 8-bit radix select.
 __global__ __launch_bounds__(1024) void median_kernel(const SlotDesc* __restrict__ descs,
-                                                      SlotState* __restrict__ states, int capacity) {
-  const int slot = blockIdx.x;
+                                                      SlotState* __restrict__ states, int capacity,
+                                                      int branch, int nbranch) {
+  const int slot = (int)blockIdx.x * nbranch + branch;
   if (slot >= capacity) return;
   SlotState& S = states[slot];
   if (S.status != ST_RUNNING || !S.want_median) return;
@@ -1187,8 +1188,8 @@ __device__ __forceinline__ void solver_run(const SlotDesc* __restrict__ descs,
 __global__ __launch_bounds__(64) void solver_kernel(const SlotDesc* __restrict__ descs,
                                                     SlotState* __restrict__ states, int capacity,
                                                     int* __restrict__ done, WorkList* __restrict__ wl,
-                                                    int single) {
-  const int slot = blockIdx.x;
+                                                    int single, int branch, int nbranch) {
+  const int slot = (int)blockIdx.x * nbranch + branch;
   if (slot >= capacity) return;
   solver_run(descs, states, done, wl, slot, single);
 }
@@ -1263,14 +1264,21 @@ __global__ void boot_kernel(const SlotDesc* __restrict__ descs, SlotState* __res
 // Exact median (element of rank floor(M/2)) of the non-negative FP64 keys of
 // one slot by 8-bit radix selection on the bit patterns.
 
+// The slots of branch b of nbranch are b, b + nbranch, ... (one branch: all).
 void launch_solver(const SlotDesc* descs, SlotState* states, int capacity, int* done,
-                   WorkList* wl, bool single, hipStream_t st) {
-  hipLaunchKernelGGL(solver_kernel, dim3(capacity), dim3(64), 0, st, descs, states, capacity, done,
-                     wl, single ? 1 : 0);
+                   WorkList* wl, bool single, hipStream_t st, int branch, int nbranch) {
+  const int grid = (capacity - branch + nbranch - 1) / nbranch;
+  if (grid <= 0) return;
+  hipLaunchKernelGGL(solver_kernel, dim3(grid), dim3(64), 0, st, descs, states, capacity, done,
+                     wl, single ? 1 : 0, branch, nbranch);
 }
 
-void launch_median(const SlotDesc* descs, SlotState* states, int capacity, hipStream_t st) {
-  hipLaunchKernelGGL(median_kernel, dim3(capacity), dim3(1024), 0, st, descs, states, capacity);
+void launch_median(const SlotDesc* descs, SlotState* states, int capacity, hipStream_t st,
+                   int branch, int nbranch) {
+  const int grid = (capacity - branch + nbranch - 1) / nbranch;
+  if (grid <= 0) return;
+  hipLaunchKernelGGL(median_kernel, dim3(grid), dim3(1024), 0, st, descs, states, capacity, branch,
+                     nbranch);
 }
 
 void launch_boot(const SlotDesc* descs, SlotState* states, int slot, WorkList* wl, bool single,
