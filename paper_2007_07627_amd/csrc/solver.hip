@@ -66,7 +66,9 @@ __device__ inline Coef coeffs(double t) {
     k.Cd = -1.0 / 60.0 + t2 / 1260.0 - t4 / 60480.0 + t6 / 4989600.0 - t8 / 622702080.0 +
            t10 / 108972864000.0;
   } else {
-    const double s = sin(t), c = cos(t), h = sin(0.5 * t);
+    double s, c;
+    sincos(t, &s, &c);
+    const double h = sin(0.5 * t);
     const double omc = 2.0 * h * h;  // 1 - cos t
     k.A = s / t;
     k.B = omc / t2;
@@ -111,11 +113,12 @@ __device__ __forceinline__ void twist_log(const double T[16], double xi[6]) {
     // theta / (2 sin theta): the quotient itself is accurate down to tiny
     // angles (no cancellation); below 1e-4 its series, whose first omitted
     // term 7 theta^4 / 720 is below 1e-18
+    // sn is sin(theta) (the norm of the skew part's axial vector)
     double f;
     if (th < 1e-4) {
       f = 0.5 + th * th / 12.0;
     } else {
-      f = th / (2.0 * sin(th));
+      f = th / (2.0 * sn);
     }
     d[0] = f * v[0]; d[1] = f * v[1]; d[2] = f * v[2];
   } else {
@@ -147,7 +150,7 @@ __device__ __forceinline__ void twist_log(const double T[16], double xi[6]) {
         t2 * t2 * t2 * t2 / 47900160.0;
   } else {
     const double h = sin(0.5 * th);
-    g = (1.0 - th * sin(th) / (4.0 * h * h)) / (th * th);
+    g = (1.0 - th * sn / (4.0 * h * h)) / (th * th);
   }
   double W[9], W2[9];
   skew(d, W);
@@ -312,18 +315,12 @@ __device__ bool top_eig_rqi(const double A[16], const double x0[4], double q[4],
     for (int i = 0; i < 4; ++i) x[i] = y[i] * iny;
   }
   if (!settled || !(rn <= 1e-12 * nA)) return false;
-  // Householder reflection H = I - 2 v v^T / (v^T v), v = x + sign(x_m) e_m
-  int m = 0;
-#pragma unroll
-  for (int i = 1; i < 4; ++i)
-    if (fabs(x[i]) > fabs(x[m])) m = i;
+  // Householder reflection H = I - 2 v v^T / (v^T v), v = x + sign(x_0) e_0
+  // (v^T v = 2 (1 + |x_0|) >= 2 for any unit x, so the reflection is well
+  // conditioned whichever component carries it)
   double v[4] = {x[0], x[1], x[2], x[3]};
-  double xm = x[0];
-#pragma unroll
-  for (int i = 1; i < 4; ++i) xm = (i == m) ? x[i] : xm;
-  const double sg = xm >= 0.0 ? 1.0 : -1.0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) v[i] += (i == m) ? sg : 0.0;
+  const double sg = x[0] >= 0.0 ? 1.0 : -1.0;
+  v[0] += sg;
   const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
   const double s2 = 2.0 / vv;
   double H[16];
@@ -331,34 +328,21 @@ __device__ bool top_eig_rqi(const double A[16], const double x0[4], double q[4],
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) H[4 * i + j] = ((i == j) ? 1.0 : 0.0) - s2 * v[i] * v[j];
-  // H A H; column m of H is -sg x, the other columns span its complement
-  double AH[16], C[16];
+  // H A H; column 0 of H is -sg x, columns 1..3 span its complement
+  double AH[16];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 1; j < 4; ++j)
       AH[4 * i + j] = A[4 * i] * H[j] + A[4 * i + 1] * H[4 + j] + A[4 * i + 2] * H[8 + j] + A[4 * i + 3] * H[12 + j];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      C[4 * i + j] = H[i] * AH[j] + H[4 + i] * AH[4 + j] + H[8 + i] * AH[8 + j] + H[12 + i] * AH[12 + j];
-  // complement block rows/cols {0..3} \ {m}, gathered by selects
+  // complement block: rows and columns 1..3 of H A H
   double B[9];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double val = 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int ia = i < m ? i : i - 1, jc = j < m ? j : j - 1;
-          if (i != m && j != m && ia == a && jc == c) val = C[4 * i + j];
-        }
-      B[3 * a + c] = val;
-    }
+    for (int c = 0; c < 3; ++c)
+      B[3 * a + c] = H[a + 1] * AH[c + 1] + H[4 + a + 1] * AH[4 + c + 1] + H[8 + a + 1] * AH[8 + c + 1] +
+                     H[12 + a + 1] * AH[12 + c + 1];
   l0 = mu;
   const double b = mu - 2e-12 * fabs(mu) - rn;
   const double c11 = b - B[0], c21 = -0.5 * (B[3] + B[1]), c31 = -0.5 * (B[6] + B[2]);
