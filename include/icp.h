@@ -113,7 +113,9 @@ typedef struct {
  * weight-and-reduce pass, and the median + solver kernels; passes counted.
  * While profiling, the graph engine launches the same passes directly on its
  * stream (same kernels and host synchronisation cadence) instead of replaying
- * the captured graph. */
+ * the captured graph; the batch engine's two slot branches, whose passes run
+ * side by side in a replay, then run one after the other and a pass's times
+ * are the sums over both. */
 typedef struct {
   double nn_ms, reduce_ms, solve_ms;
   long long passes;
