@@ -59,6 +59,26 @@ def test_batch_equals_alone_bitwise(ctx):
         assert g["latency_ms"] > 0
 
 
+@pytest.mark.parametrize("slots", [1, 3])
+def test_uneven_slot_branches_equal_alone(slots):
+    """The batch engine's slots form two branches (even and odd slot numbers)
+    whose passes run side by side: with one slot the second branch is empty,
+    with three the branches hold two and one pairs, and admissions refill
+    whichever branch frees a slot. Every result equals the pair alone."""
+    h = B.icp_create(0, 4 << 30)
+    try:
+        B.icp_batch_config(h, 3, slots)
+        reqs = _requests(7, seed_config=47)
+        announce(f"7 pairs through {slots} slot(s)")
+        res = _wait(h, B.icp_batch_submit(h, [r for _, r in reqs]), timeout=300.0)
+        for (d, (P, Q, Qn, prm)), g in zip(reqs, res):
+            a = B.icp_register(h, P, Q, Qn, prm)
+            assert np.array_equal(g["T"], a["T"]), "batched result differs from the pair alone"
+            assert g["nn_passes"] == a["nn_passes"] and g["energy"] == a["energy"]
+    finally:
+        B.icp_destroy(h)
+
+
 def test_device_inputs_equal_host_inputs(ctx):
     """icp_batch_submit_dev reads the arrays in HBM in place: the results are
     those of the same requests submitted as host arrays, bit for bit, also
