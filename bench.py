@@ -220,6 +220,25 @@ def tuning_used(B, ctx, shapes, batch):
             "settings": [dict(json.loads(k), pairs=v) for k, v in sorted(seen.items(), key=lambda x: -x[1])]}
 
 
+def counter_run(B, torch, pairs, passes_per_replay):
+    """One batch-256 step from device inputs, without timing events or
+    comparators: the run that rocprofv3 --pmc counts. Prints the batch's
+    passes (the highest per-pair count) as a JSON line."""
+    dev = torch.device("cuda:0")
+    dreqs = [(torch.from_numpy(P).to(dev), torch.from_numpy(Q).to(dev),
+              None if Qn is None else torch.from_numpy(Qn).to(dev), prm)
+             for P, Q, Qn, prm in (_request(B, d) for d in pairs)]
+    torch.cuda.synchronize()
+    ctx = B.icp_create(0, 32 << 30)
+    B.icp_batch_config(ctx, passes_per_replay, min(1024, len(pairs)))
+    t0 = time.perf_counter()
+    res = _wait_tickets(B, ctx, B.icp_batch_submit_dev(ctx, dreqs, torch.cuda.current_stream()))
+    log(f"counter run: {len(res)} registrations in {time.perf_counter() - t0:.2f} s")
+    B.icp_destroy(ctx)
+    print(json.dumps({"counter_run": "batch-256", "pairs": len(res),
+                      "max_pair_passes": int(max(r["nn_passes"] for r in res))}), flush=True)
+
+
 def batch_bench(args, B, pairs):
     """Batch-256: the pairs' arrays are uploaded to HBM first; a step submits
     all of them (device pointers, icp_batch_submit_dev) and waits for the last
@@ -627,6 +646,9 @@ def main():
                     help="skip the batch's plain-loop comparator (counter runs: every dispatch is slow)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="headline only: no 100k x 100k pair, no exhaustive-kernel runs")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="batch-256 only: one batch step from device inputs and nothing else (no timing "
+                         "events, no comparators), for rocprofv3 --pmc runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of known size (for HBM counter runs)")
     args = ap.parse_args()
@@ -637,6 +659,8 @@ def main():
         sys.exit(2)
 
     # every input first, in forked workers, before this process touches the GPU
+    if args.counter_run:
+        args.workload, args.no_serve, args.no_secondary = "batch-256", True, True
     t0 = time.perf_counter()
     if args.workload == "batch-256":
         pairs = generate(_gen_batch_pair, args.batch_pairs, args.workers)
@@ -688,6 +712,9 @@ def main():
         return
 
     log(f"workload batch-256: {len(pairs)} pairs")
+    if args.counter_run:
+        counter_run(B, torch, pairs, args.passes_per_replay)
+        return
     out, info = batch_bench(args, B, pairs)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample of the batch)")
