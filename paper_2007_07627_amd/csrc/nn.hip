@@ -1008,7 +1008,9 @@ void launch_nn(const SlotDesc* descs, const SlotState* states, WorkList* wl, int
   // every sub-queue needs workgroups of its own (blockIdx mod kQueues, and
   // mod kSliceQueues for the slice kernel)
   grid = std::max(grid, std::max(kQueues * kCullWaves, kSliceQueues));
-  hipLaunchKernelGGL(nn_cull_kernel, dim3(grid / kCullWaves), dim3(64 * kCullWaves), 0, st, descs,
+  // the cull waits on memory most of the time: 7/4 of the search's wavefronts
+  // (seven per SIMD at the default grid, which its registers allow)
+  hipLaunchKernelGGL(nn_cull_kernel, dim3(grid * 7 / (4 * kCullWaves)), dim3(64 * kCullWaves), 0, st, descs,
                      states, wl);
   if (!single) hipLaunchKernelGGL(slice_plan_kernel, dim3(1), dim3(1024), 0, st, descs, states, wl);
   hipLaunchKernelGGL(nn_slice_kernel, dim3(grid), dim3(64), 0, st, descs, states, wl);
